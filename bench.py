@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Throughput of the MSP connectivity update (arXiv 2509.26193) on one MI355X.
+
+One step = one whole connectivity update over the resident synthetic brain:
+build the octree, refresh the vacancy aggregates, run the Barnes-Hut target search for
+every vacant axonal element, commit the accepted synapses. The counts are restored
+from a resident copy at the start of each step so that every step does the same work.
+
+Prints one JSON line (rank 0). Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
+REC_BYTES = 16             # one per-type node record {x, y, z, count} at 4 bytes each
+OPEN_BYTES = 8             # child link + mask + depth of an opened node
+SRC_BYTES = 16             # source record
+OUT_BYTES = 4              # one int32 target
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_workload(name, theta):
+    from synth_inputs import config_clusters, config_large, config_small
+    if name == "large":
+        w = config_large()
+    elif name == "clusters":
+        w = config_clusters(theta=0.3 if theta is None else theta)
+    elif name == "small":
+        w = config_small()
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    if theta is not None:
+        w.theta = float(theta)
+    return w
+
+
+def algorithmic_bytes(cnt, off):
+    """Bytes the method must read for one launch: each source's level-0 list once
+    (records visited, nodes opened, the source), each search's restart lists, and
+    one output per search."""
+    v = cnt["visits"].astype(np.int64)
+    o = cnt["opens"].astype(np.int64)
+    v0 = cnt["visits0"].astype(np.int64)
+    o0 = cnt["opens0"].astype(np.int64)
+    first = off[:-1][np.diff(off) > 0]          # first element of every source
+    lvl0 = (REC_BYTES * v0[first] + OPEN_BYTES * o0[first] + SRC_BYTES).sum()
+    rest = (REC_BYTES * (v - v0) + OPEN_BYTES * (o - o0) + OUT_BYTES).sum()
+    return int(lvl0 + rest), int(v0[first].sum() + (v - v0).sum())
+
+
+def cpu_baseline(w, gpu_target, sample, threads):
+    from oracle import oracle as orc
+    t0 = time.time()
+    t = orc.OracleTree(w.pos, w.box_min, w.box_edge)
+    tb = time.time() - t0
+    t0 = time.time()
+    t.update_counts(w.vac_exc, w.vac_inh)
+    tr = time.time() - t0
+    off, src, elem = orc.search_list(w.vac_axon)
+    rng = np.random.default_rng(1234)
+    m = min(sample, src.size)
+    q = np.sort(rng.choice(src.size, size=m, replace=False))
+    log(f"oracle tree built in {tb:.1f} s, refreshed in {tr:.1f} s; timing {m} searches")
+    t0 = time.time()
+    r = t.find_targets(w.neuron_type, w.sigma, w.theta, w.seed, w.step, src[q], elem[q],
+                       nthreads=threads)
+    ts = time.time() - t0
+    differ = int((r["target"] != gpu_target[q]).sum())
+    outside = int(((r["target"] != gpu_target[q]) & ~(r["window"] < 1e-6)).sum())
+    return dict(value=m / ts, unit="searches/s", cores=threads, kind="oracle",
+                sample=(f"{m} random searches of the {src.size} in one update of {w.name} "
+                        f"(fp64 oracle, OpenMP {threads} threads); tree build {tb:.1f} s and "
+                        f"refresh {tr:.1f} s not included"),
+                parity=dict(sampled=m, differing=differ, outside_window=outside))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="large", choices=["large", "clusters", "small"])
+    ap.add_argument("--theta", type=float, default=None)
+    ap.add_argument("--cpu-sample", type=int, default=40000)
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding of the search is a design note, not implemented)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2509_26193_amd as msp
+
+    dev = torch.device("cuda:0")
+    w = make_workload(args.workload, args.theta)
+    S = w.searches
+    log(f"workload {w.name}: n={w.n} searches={S} sigma={w.sigma} theta={w.theta}")
+    T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    pos = T(w.pos, torch.float64)
+    ty = T(w.neuron_type, torch.uint8)
+    va0, ve0, vi0 = T(w.vac_axon, torch.int32), T(w.vac_exc, torch.int32), T(w.vac_inh, torch.int32)
+    va, ve, vi = va0.clone(), ve0.clone(), vi0.clone()
+    tgt_buf = torch.empty(S, dtype=torch.int32, device=dev)
+    off_buf = torch.empty(w.n + 1, dtype=torch.int64, device=dev)
+    times = {"build": [], "refresh": [], "search": [], "commit": [], "kernel": []}
+
+    def step(record):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record()
+        tree = msp.build_octree(pos, w.box_min, w.box_edge)
+        ev[1].record()
+        va.copy_(va0)
+        ve.copy_(ve0)
+        vi.copy_(vi0)
+        msp.update_vacant_counts(tree, ve, vi)
+        ev[2].record()
+        tm = {}
+        tgt, off = msp.find_targets(tree, ty, va, w.sigma, w.theta, w.seed, w.step,
+                                    target_out=tgt_buf, elem_offset_out=off_buf, timing=tm)
+        ev[3].record()
+        res = msp.commit_synapses(tgt, off, ty, va, ve, vi, w.seed, w.step, syn_capacity=S)
+        ev[4].record()
+        tree.free()
+        if record:
+            torch.cuda.synchronize()
+            for k, (a, b) in zip(("build", "refresh", "search", "commit"), zip(ev[:-1], ev[1:])):
+                times[k].append(a.elapsed_time(b))
+            times["kernel"].append(tm["kernel_ms"])
+        return res["n_formed"]
+
+    for k in range(args.warmup):
+        step(False)
+        log(f"warmup step {k + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    formed = 0
+    for k in range(args.steps):
+        formed = step(True)
+        log(f"timed step {k + 1}/{args.steps}: search kernel {times['kernel'][-1]:.2f} ms")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec = (t1 - t0) / args.steps
+    value = S / sec
+
+    # exact algorithmic work of the launch (the kernel's own counters, untimed pass)
+    tree = msp.build_octree(pos, w.box_min, w.box_edge)
+    va.copy_(va0); ve.copy_(ve0); vi.copy_(vi0)
+    msp.update_vacant_counts(tree, ve, vi)
+    tgt, off, cnt = msp.find_targets(tree, ty, va, w.sigma, w.theta, w.seed, w.step, counters=True)
+    torch.cuda.synchronize()
+    off_h = off.cpu().numpy()
+    cnt_h = {k: v.cpu().numpy() for k, v in cnt.items()}
+    gpu_target = tgt.cpu().numpy().astype(np.int64)
+    tree.free()
+    B, visits = algorithmic_bytes(cnt_h, off_h)
+    kmean = float(np.mean(times["kernel"])) / 1e3
+    achieved = B / kmean
+    roof = dict(bound="hbm", achieved=achieved / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
+                frac=achieved / HBM_PEAK, traffic=None,
+                kernel="search_simple_k", kernel_ms=kmean * 1e3,
+                algorithmic_bytes_per_launch=B, node_visits_per_launch=visits)
+    log(f"step {sec * 1e3:.1f} ms; search kernel {kmean * 1e3:.2f} ms; "
+        f"{achieved / 1e9:.1f} GB/s algorithmic ({roof['frac']:.3f} of HBM peak)")
+
+    out = {
+        "metric": "axon target searches/sec",
+        "value": value,
+        "unit": "searches/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64/f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "neurons": w.n, "searches_per_step": S,
+                   "sigma_um": w.sigma, "theta": w.theta,
+                   "step": "build_octree + update_vacant_counts + find_targets + commit_synapses",
+                   "synapses_formed": formed},
+        "breakdown_ms": {k: float(np.mean(v)) for k, v in times.items()},
+        "search_kernel_searches_per_s": S / kmean,
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        threads = args.cpu_threads or min(os.cpu_count() or 1, 64)
+        out["cpu_baseline"] = cpu_baseline(w, gpu_target, args.cpu_sample, threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * msp.h -- C ABI of libmsp, the MI355X (gfx950) implementation of the connectivity
+ * update of the Model of Structural Plasticity with a Barnes-Hut target search,
+ * as described in Czappa, Kaster, Wolf, "I Like To Move It -- Computation Instead
+ * of Data in the Brain" (arXiv 2509.26193).
+ *
+ * The update (Sec. III-A, "Update of synapses"; Sec. III-B):
+ *   1. msp_build_octree        -- spatial octree over the neurons (Sec. III-B,
+ *                                 "Spatial octree"); positions never change, so once.
+ *   2. msp_update_vacant_counts-- bottom-up vacancy aggregates (Sec. III-B,
+ *                                 "Division of work"; Alg. 1, first three lines).
+ *   3. msp_find_targets        -- every vacant axonal element draws a partner with
+ *                                 the Barnes-Hut acceptance test and restarts
+ *                                 (Sec. III-B, "Division of work").
+ *   4. msp_commit_synapses     -- each neuron accepts as many requests as it has
+ *                                 vacant dendritic elements, at random; the rest are
+ *                                 declined (Sec. III-A, "Update of synapses").
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers owned by the caller unless marked (host).
+ *     The caller keeps them alive until the work queued on the stream has finished.
+ *   - Work is queued on the given stream `s` (0 = the default stream). Calls that
+ *     must size an output (find_targets, commit) read one scalar back to the host
+ *     and therefore synchronise on `s`; every other call is asynchronous.
+ *   - Every call returns an msp_status and never throws. Arguments are validated
+ *     before anything is queued; on an error nothing is written.
+ *   - Data-dependent errors found on the device (a non-finite position, a negative
+ *     count) raise a sticky per-octree flag read by msp_last_device_error.
+ *   - Neuron ids are 0..n-1, the row order of the position array. Neuron type 0 =
+ *     excitatory, 1 = inhibitory. A source of type t searches the type-t vacant
+ *     dendritic elements (the request carries the cell type, Sec. III-B).
+ *   - Limits: 1 <= n <= MSP_MAX_NEURONS; the octree has fewer than 2^26 nodes.
+ */
+#ifndef MSP_H
+#define MSP_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t msp_status;
+#define MSP_OK                 0
+#define MSP_ERR_INVALID       (-1)  /* bad argument, freed or foreign handle          */
+#define MSP_ERR_OOM           (-2)  /* device allocation failed                       */
+#define MSP_ERR_HIP           (-3)  /* a HIP runtime call failed                      */
+#define MSP_ERR_CAPACITY      (-4)  /* an output buffer is too small; nothing written */
+#define MSP_ERR_DEVICE        (-5)  /* data error detected on the device              */
+#define MSP_ERR_UNIMPLEMENTED (-6)
+
+#define MSP_MAX_NEURONS (1LL << 25)
+
+typedef struct msp_octree_s* msp_octree;
+
+/*
+ * Build the octree over n neurons (Sec. III-B, "Spatial octree"; "Division of the
+ * simulation domain" for the Morton-indexed cells).
+ *   pos       [n][3] float64, row-major (x, y, z) per neuron, micrometres.
+ *   box_min   (host) [3] minimum corner of the cubic domain; box_edge (host) > 0 its
+ *             edge. Each axis is quantised to 21 bits, q = floor((x - min) / edge * 2^21),
+ *             clamped into [0, 2^21 - 1] (positions outside the cube fall in edge cells).
+ *   leaf_size must be 1: a leaf holds one neuron, except that neurons whose quantised
+ *             positions coincide share one depth-21 leaf.
+ *   out       (host) receives the handle. The library owns every node array.
+ * Errors: MSP_ERR_INVALID for n < 1 or n > MSP_MAX_NEURONS, non-finite or non-positive
+ * box, leaf_size != 1, null pointers; MSP_ERR_OOM. A non-finite position sets the
+ * device error flag. The build synchronises on `s` once to size the node arrays.
+ */
+msp_status msp_build_octree(const double* pos, int64_t n, const double box_min[3],
+                            double box_edge, int32_t leaf_size, hipStream_t s,
+                            msp_octree* out);
+
+/*
+ * Refresh the per-type vacancy aggregates bottom-up (Sec. III-B, "Division of work":
+ * a leaf carries its neuron's position and count, an inner node the sum of its
+ * children's counts and the count-weighted average of their positions).
+ *   vac_dend_exc, vac_dend_inh [n] int32 >= 0, vacant dendritic elements per neuron.
+ * Centroids are accumulated in float64 over the children in octant order, one
+ * rounding per operation. Idempotent; topology is unchanged. A negative count sets
+ * the device error flag.
+ */
+msp_status msp_update_vacant_counts(msp_octree t, const int32_t* vac_dend_exc,
+                                    const int32_t* vac_dend_inh, hipStream_t s);
+
+/*
+ * Barnes-Hut target search for every vacant axonal element (Sec. III-B, "Division
+ * of work"; Sec. III-A, "Update of synapses").
+ *   neuron_type [n] uint8 (0/1); vac_axon [n] int32, a_i >= 0 searches of neuron i.
+ *   sigma_um > 0: kernel width, weight of a node = v * exp(-d^2 / sigma^2).
+ *   theta >= 0: a cell of edge l at distance d from the source is accepted iff
+ *             l < theta * d (evaluated as l*l < theta*theta*d*d in float64); leaves are
+ *             always accepted, a cell containing the source is always opened.
+ *   seed, step: the draw of element j of neuron i at restart level k uses Philox4x64-10
+ *             with key (seed, 0) and counter (i, j, step, k).
+ *   target_out [capacity_S] int32: target_out[elem_offset[i] + j] = chosen neuron id,
+ *             or -1 if no neuron with a vacancy of the right type has nonzero weight.
+ *   elem_offset_out [n+1] int64: exclusive prefix sum of vac_axon (CSR by source).
+ * Every search reads the octree as refreshed last (all requests are formed before
+ * any is answered). Errors: MSP_ERR_CAPACITY if S = sum(vac_axon) > capacity_S:
+ * then only elem_offset_out is written (elem_offset_out[n] = S sizes the buffer);
+ * MSP_ERR_INVALID for sigma <= 0, theta < 0, a negative vac_axon or a type > 1
+ * (the last two found on the device before the search: target_out is not written).
+ */
+msp_status msp_find_targets(msp_octree t, const uint8_t* neuron_type, const int32_t* vac_axon,
+                            double sigma_um, double theta, uint64_t seed, uint64_t step,
+                            int32_t* target_out, int64_t* elem_offset_out, int64_t capacity_S,
+                            hipStream_t s);
+
+/*
+ * Diagnostics of one msp_find_targets call. Every pointer is nullable.
+ *   z0      [S] float64: normaliser of the level-0 list of each search;
+ *   levels  [S] int32: number of lists drawn from (1 + restarts);
+ *   visits  [S] int32: node records examined over all levels (a start node counts
+ *           once, a bucket leaf once); opens [S] int32: nodes replaced by their
+ *           children over all levels (the start node included);
+ *   visits0, opens0 [S] int32: the level-0 part of visits / opens (the level-0 list
+ *           of a source is shared by all of its elements);
+ *   kernel_ms (host): duration of the search kernel, from HIP events recorded on `s`
+ *           around it; when set, the call waits for the kernel to finish.
+ */
+typedef struct msp_search_diag {
+  double* z0;
+  int32_t* levels;
+  int32_t* visits;
+  int32_t* opens;
+  int32_t* visits0;
+  int32_t* opens0;
+  float* kernel_ms;
+} msp_search_diag;
+
+/* msp_find_targets with diagnostics (diag may be null). */
+msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
+                                 const int32_t* vac_axon, double sigma_um, double theta,
+                                 uint64_t seed, uint64_t step, int32_t* target_out,
+                                 int64_t* elem_offset_out, int64_t capacity_S,
+                                 const msp_search_diag* diag, hipStream_t s);
+
+/*
+ * Accept or decline every request (Sec. III-A, "Update of synapses"; Sec. III-B:
+ * requests are exchanged, accepted locally and answered yes/no).
+ *   target [S], elem_offset [n+1]: as produced by msp_find_targets.
+ *   Requests on target g of source type t form one group; the group accepts
+ *   min(#requests, vacant type-t dendritic elements of g) requests, those with the
+ *   smallest Philox4x64-10 word 0 under key (seed, 1) and counter (i, j, step, 0),
+ *   ties broken by (i, j); the rest are declined.
+ *   vac_axon, vac_exc, vac_inh [n] int32, in/out: decremented by the synapses formed.
+ *   syn_src, syn_tgt [syn_capacity] int32, syn_type [syn_capacity] uint8: the formed
+ *   synapses, ordered by (source, element). n_formed: device int64 scalar.
+ *   accepted_out [S] uint8 (nullable in msp_commit_synapses_ex): 1 if the request in
+ *   that slot was accepted.
+ * Errors: MSP_ERR_CAPACITY if more than syn_capacity synapses would form (then no
+ * count is modified and nothing is written). After a commit the octree is stale
+ * until the next msp_update_vacant_counts.
+ */
+msp_status msp_commit_synapses(const int32_t* target, const int64_t* elem_offset,
+                               const uint8_t* neuron_type, int64_t n, int32_t* vac_axon,
+                               int32_t* vac_exc, int32_t* vac_inh, uint64_t seed, uint64_t step,
+                               int32_t* syn_src, int32_t* syn_tgt, uint8_t* syn_type,
+                               int64_t syn_capacity, int64_t* n_formed, hipStream_t s);
+
+msp_status msp_commit_synapses_ex(const int32_t* target, const int64_t* elem_offset,
+                                  const uint8_t* neuron_type, int64_t n, int32_t* vac_axon,
+                                  int32_t* vac_exc, int32_t* vac_inh, uint64_t seed,
+                                  uint64_t step, int32_t* syn_src, int32_t* syn_tgt,
+                                  uint8_t* syn_type, int64_t syn_capacity, int64_t* n_formed,
+                                  uint8_t* accepted_out, hipStream_t s);
+
+/* Release the octree (waits for the device to finish using it). A freed or foreign
+ * handle is rejected with MSP_ERR_INVALID by every call (magic-number check). */
+void msp_free_octree(msp_octree t);
+
+/* Wait for stream s; MSP_ERR_HIP if the stream reported an error. */
+msp_status msp_sync(hipStream_t s);
+
+/* Static description of a status code. */
+const char* msp_status_string(msp_status st);
+
+/* Synchronise on the device and return MSP_ERR_DEVICE if a data error (non-finite
+ * position at build, negative count at refresh) was detected, else MSP_OK. Clears
+ * nothing: the flag is sticky for the life of the octree. */
+msp_status msp_last_device_error(msp_octree t);
+
+/* Sizes: number of neurons and nodes (host outputs, nullable). */
+msp_status msp_octree_info(msp_octree t, int64_t* n_neurons, int64_t* n_nodes);
+
+/*
+ * Copy the topology out (all outputs device pointers, nullable):
+ *   order [n] int32 neuron ids in (Morton key, id) order; keys [n] uint64 sorted keys;
+ *   depth [N] int32; node_begin, node_end [N] int64 ranges into `order`;
+ *   subtree_end [N] int64: nodes are numbered in depth-first pre-order, children in
+ *   octant order (digit 4x + 2y + z), so the subtree of node k is [k, subtree_end[k]).
+ */
+msp_status msp_octree_export_topology(msp_octree t, int32_t* order, uint64_t* keys,
+                                      int32_t* depth, int64_t* node_begin, int64_t* node_end,
+                                      int64_t* subtree_end, hipStream_t s);
+
+/* Copy the type-`type` aggregates out: count [N] int64, centroid [N][3] float64 (device,
+ * nullable). The centroid of a node with count 0 is unspecified. */
+msp_status msp_octree_export_aggregates(msp_octree t, int32_t type, int64_t* count,
+                                        double* centroid, hipStream_t s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSP_H */

@@ -1,0 +1,12 @@
+"""MI355X (gfx950) implementation of the MSP connectivity update (arXiv 2509.26193).
+
+The computation lives in libmsp.so (hand-written HIP kernels behind the C ABI of
+include/msp.h); this package is its thin Python binding. Entry points follow the
+four steps of one update: build_octree, update_vacant_counts, find_targets,
+commit_synapses.
+"""
+from ._lib import (MspError, Octree, build_octree, commit_synapses, find_targets,
+                   header_functions, lib, status_string, sync, update_vacant_counts)
+
+__all__ = ["MspError", "Octree", "build_octree", "update_vacant_counts", "find_targets",
+           "commit_synapses", "sync", "status_string", "header_functions", "lib"]

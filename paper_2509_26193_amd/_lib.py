@@ -1,0 +1,284 @@
+"""ctypes binding of libmsp (include/msp.h): argument marshalling only.
+
+Tensors must be CUDA (HIP) tensors on the current device with the dtypes below;
+every computation runs in libmsp's HIP kernels. If libmsp.so has not been built,
+importing the functions raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmsp.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "msp.h")
+
+MSP_OK = 0
+MSP_ERR_INVALID = -1
+MSP_ERR_OOM = -2
+MSP_ERR_HIP = -3
+MSP_ERR_CAPACITY = -4
+MSP_ERR_DEVICE = -5
+MSP_ERR_UNIMPLEMENTED = -6
+
+
+class MspError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+_dbl = ctypes.c_double
+
+class SearchDiag(ctypes.Structure):
+    _fields_ = [("z0", _vp), ("levels", _vp), ("visits", _vp), ("opens", _vp),
+                ("visits0", _vp), ("opens0", _vp), ("kernel_ms", ctypes.POINTER(ctypes.c_float))]
+
+
+_SIGS = {
+    "msp_status_string": (ctypes.c_char_p, [_i32]),
+    "msp_sync": (_i32, [_vp]),
+    "msp_build_octree": (_i32, [_vp, _i64, _vp, _dbl, _i32, _vp, ctypes.POINTER(_vp)]),
+    "msp_update_vacant_counts": (_i32, [_vp, _vp, _vp, _vp]),
+    "msp_find_targets": (_i32, [_vp, _vp, _vp, _dbl, _dbl, _u64, _u64, _vp, _vp, _i64, _vp]),
+    "msp_find_targets_diag": (_i32, [_vp, _vp, _vp, _dbl, _dbl, _u64, _u64, _vp, _vp, _i64,
+                                     ctypes.POINTER(SearchDiag), _vp]),
+    "msp_commit_synapses": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _u64, _u64, _vp, _vp, _vp,
+                                   _i64, _vp, _vp]),
+    "msp_commit_synapses_ex": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _u64, _u64, _vp, _vp,
+                                      _vp, _i64, _vp, _vp, _vp]),
+    "msp_free_octree": (None, [_vp]),
+    "msp_last_device_error": (_i32, [_vp]),
+    "msp_octree_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "msp_octree_export_topology": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "msp_octree_export_aggregates": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+}
+
+_lib = None
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/msp.h."""
+    with open(HEADER) as f:
+        txt = f.read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(msp_[a-z0-9_]+)\s*\(", txt)))
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(st: int) -> str:
+    return lib().msp_status_string(int(st)).decode()
+
+
+def _check(st: int, what: str) -> None:
+    if st != MSP_OK:
+        raise MspError(st, what)
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, name: str, numel: int | None = None) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return t.data_ptr()
+
+
+def _opt(t, dtype, name, numel=None):
+    return None if t is None else _dev(t, dtype, name, numel)
+
+
+class Octree:
+    """Handle of an octree built by msp_build_octree (owned by libmsp)."""
+
+    def __init__(self, handle: int, n: int, device: torch.device):
+        self._h = handle
+        self.n = n
+        self.device = device
+
+    @property
+    def handle(self) -> int:
+        if not self._h:
+            raise ValueError("octree was freed")
+        return self._h
+
+    @property
+    def num_nodes(self) -> int:
+        nn = _i64()
+        nN = _i64()
+        _check(lib().msp_octree_info(self.handle, ctypes.byref(nn), ctypes.byref(nN)), "octree_info")
+        return int(nN.value)
+
+    def free(self) -> None:
+        if self._h:
+            lib().msp_free_octree(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def last_device_error(self) -> int:
+        return int(lib().msp_last_device_error(self.handle))
+
+    def export_topology(self, stream=None) -> dict:
+        N = self.num_nodes
+        dev = self.device
+        out = dict(order=torch.empty(self.n, dtype=torch.int32, device=dev),
+                   keys=torch.empty(self.n, dtype=torch.int64, device=dev),
+                   depth=torch.empty(N, dtype=torch.int32, device=dev),
+                   begin=torch.empty(N, dtype=torch.int64, device=dev),
+                   end=torch.empty(N, dtype=torch.int64, device=dev),
+                   subtree_end=torch.empty(N, dtype=torch.int64, device=dev))
+        _check(lib().msp_octree_export_topology(
+            self.handle, out["order"].data_ptr(), out["keys"].data_ptr(), out["depth"].data_ptr(),
+            out["begin"].data_ptr(), out["end"].data_ptr(), out["subtree_end"].data_ptr(),
+            _stream(stream)), "export_topology")
+        return out
+
+    def export_aggregates(self, type_: int, stream=None):
+        N = self.num_nodes
+        v = torch.empty(N, dtype=torch.int64, device=self.device)
+        c = torch.empty((N, 3), dtype=torch.float64, device=self.device)
+        _check(lib().msp_octree_export_aggregates(self.handle, int(type_), v.data_ptr(),
+                                                  c.data_ptr(), _stream(stream)),
+               "export_aggregates")
+        return v, c
+
+
+def build_octree(pos: torch.Tensor, box_min, box_edge: float, leaf_size: int = 1,
+                 stream=None) -> Octree:
+    n = pos.shape[0]
+    p = _dev(pos, torch.float64, "pos", 3 * n)
+    bm = (ctypes.c_double * 3)(*[float(x) for x in box_min])
+    h = _vp()
+    _check(lib().msp_build_octree(p, n, bm, float(box_edge), int(leaf_size), _stream(stream),
+                                  ctypes.byref(h)), "build_octree")
+    return Octree(h.value, n, pos.device)
+
+
+def update_vacant_counts(tree: Octree, vac_exc: torch.Tensor, vac_inh: torch.Tensor,
+                         stream=None) -> None:
+    _check(lib().msp_update_vacant_counts(tree.handle, _dev(vac_exc, torch.int32, "vac_exc", tree.n),
+                                          _dev(vac_inh, torch.int32, "vac_inh", tree.n),
+                                          _stream(stream)), "update_vacant_counts")
+
+
+def find_targets(tree: Octree, neuron_type: torch.Tensor, vac_axon: torch.Tensor, sigma: float,
+                 theta: float, seed: int, step: int, target_out: torch.Tensor | None = None,
+                 elem_offset_out: torch.Tensor | None = None, diag: bool = False,
+                 counters: bool = False, timing: dict | None = None, stream=None):
+    """Returns (target[S], elem_offset[n+1]); with diag also (z0[S], levels[S]); with
+    counters also a dict of visits/opens/visits0/opens0 [S]. target_out may be a
+    preallocated int32 buffer of any capacity >= S. If `timing` is a dict, the search
+    kernel's duration (HIP events on the launch stream) is stored under "kernel_ms"."""
+    n = tree.n
+    dev = tree.device
+    ty = _dev(neuron_type, torch.uint8, "neuron_type", n)
+    a = _dev(vac_axon, torch.int32, "vac_axon", n)
+    if elem_offset_out is None:
+        elem_offset_out = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    off = _dev(elem_offset_out, torch.int64, "elem_offset_out", n + 1)
+    st = _stream(stream)
+    ms = ctypes.c_float(0.0)
+    extra = {}
+    for attempt in range(2):
+        cap = 0 if target_out is None else target_out.numel()
+        d = SearchDiag()
+        if diag:
+            extra["z0"] = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
+            extra["levels"] = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        if counters:
+            for k in ("visits", "opens", "visits0", "opens0"):
+                extra[k] = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        for k, v in extra.items():
+            setattr(d, k, v.data_ptr())
+        if timing is not None:
+            d.kernel_ms = ctypes.pointer(ms)
+        tp = None if target_out is None else _dev(target_out, torch.int32, "target_out")
+        rc = lib().msp_find_targets_diag(tree.handle, ty, a, float(sigma), float(theta), int(seed),
+                                         int(step), tp, off, cap, ctypes.byref(d), st)
+        if rc == MSP_ERR_CAPACITY and attempt == 0:
+            S = int(elem_offset_out[n].item())
+            target_out = torch.empty(max(S, 1), dtype=torch.int32, device=dev)
+            continue
+        _check(rc, "find_targets")
+        break
+    S = int(elem_offset_out[n].item())
+    if target_out is None:
+        target_out = torch.empty(0, dtype=torch.int32, device=dev)
+    if timing is not None:
+        timing["kernel_ms"] = float(ms.value)
+    out = [target_out[:S], elem_offset_out]
+    if diag:
+        out += [extra["z0"][:S], extra["levels"][:S]]
+    if counters:
+        out.append({k: extra[k][:S] for k in ("visits", "opens", "visits0", "opens0")})
+    return tuple(out)
+
+
+def commit_synapses(target: torch.Tensor, elem_offset: torch.Tensor, neuron_type: torch.Tensor,
+                    vac_axon: torch.Tensor, vac_exc: torch.Tensor, vac_inh: torch.Tensor,
+                    seed: int, step: int, syn_capacity: int | None = None,
+                    return_accepted: bool = False, stream=None) -> dict:
+    """Accept/decline all requests; vac_* are updated in place. Returns the synapses."""
+    n = vac_axon.numel()
+    dev = vac_axon.device
+    S = int(elem_offset[n].item()) if syn_capacity is None else None
+    cap = S if syn_capacity is None else int(syn_capacity)
+    src = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    tgt = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    sty = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
+    nf = torch.zeros(1, dtype=torch.int64, device=dev)
+    Sx = target.numel()
+    acc = torch.empty(max(Sx, 1), dtype=torch.uint8, device=dev) if return_accepted else None
+    tp = _dev(target, torch.int32, "target") if target.numel() > 0 else None
+    rc = lib().msp_commit_synapses_ex(tp, _dev(elem_offset, torch.int64, "elem_offset", n + 1),
+                                      _dev(neuron_type, torch.uint8, "neuron_type", n), n,
+                                      _dev(vac_axon, torch.int32, "vac_axon", n),
+                                      _dev(vac_exc, torch.int32, "vac_exc", n),
+                                      _dev(vac_inh, torch.int32, "vac_inh", n), int(seed), int(step),
+                                      src.data_ptr(), tgt.data_ptr(), sty.data_ptr(), cap,
+                                      nf.data_ptr(), None if acc is None else acc.data_ptr(),
+                                      _stream(stream))
+    _check(rc, "commit_synapses")
+    m = int(nf.item())
+    out = dict(syn_src=src[:m], syn_tgt=tgt[:m], syn_type=sty[:m], n_formed=m)
+    if return_accepted:
+        out["accepted"] = acc[:Sx]
+    return out
+
+
+def sync(stream=None) -> None:
+    _check(lib().msp_sync(_stream(stream)), "sync")

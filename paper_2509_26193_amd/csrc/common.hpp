@@ -1,0 +1,138 @@
+// Shared device/host definitions of libmsp (one translation unit: msp.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstddef>
+#include <cstdio>
+#include <mutex>
+
+#include "msp.h"
+
+namespace msp {
+
+constexpr uint32_t kMagic = 0x3150534Du;   // "MSP1"
+constexpr uint32_t kDead = 0xDEADBEEFu;
+constexpr int kMaxDepth = 21;              // 21 bits per axis, 63-bit Morton keys
+constexpr int kWave = 64;
+
+// Per-node, per-type search record (32 bytes, one scalar load of 8 dwords).
+//   x, y, z : float64 centroid of the type's vacant dendritic elements (leaf: the
+//             neuron's position);
+//   v       : vacant elements of the type below the node;
+//   meta    : inner node -> bits 0..25 pre-order subtree end ("skip"), 26..30 depth;
+//             leaf        -> bit 31 set; single neuron: bits 0..29 neuron id;
+//                            bucket (coincident neurons) : bit 30 set, bits 0..29 node index.
+struct alignas(32) NodeRec {
+  double x, y, z;
+  int32_t v;
+  uint32_t meta;
+};
+static_assert(sizeof(NodeRec) == 32, "NodeRec must be 32 bytes");
+
+constexpr uint32_t kLeafBit = 0x80000000u;
+constexpr uint32_t kBucketBit = 0x40000000u;
+constexpr uint32_t kIdMask = 0x3FFFFFFFu;
+constexpr uint32_t kSkipBits = 26;
+constexpr uint32_t kSkipMask = (1u << kSkipBits) - 1u;
+constexpr int64_t kMaxNodes = (int64_t)1 << kSkipBits;
+
+// device error flags (sticky, per octree)
+constexpr int32_t kErrNonFinite = 1;
+constexpr int32_t kErrNegative = 2;
+constexpr int32_t kErrOverflow = 4;
+constexpr int32_t kErrArgs = 8;
+
+}  // namespace msp
+
+struct msp_octree_s {
+  uint32_t magic;
+  int device;
+  int64_t n;             // neurons
+  int64_t N;             // nodes
+  double box_min[3];
+  double box_edge;
+  // neuron arrays (device)
+  double* pos;           // [n][3] by id
+  uint64_t* keys;        // [n] sorted Morton keys
+  int32_t* order;        // [n] ids in (key, id) order
+  int32_t* leaf_of;      // [n] by id: leaf node holding the neuron
+  // topology (device), nodes in depth-first pre-order
+  int32_t* skip;         // [N] subtree end
+  uint8_t* depth;        // [N]
+  int32_t* nbeg;         // [N] range in `order`
+  int32_t* nend;         // [N]
+  int32_t* level_nodes;  // [N] node ids grouped by depth
+  int64_t level_off[msp::kMaxDepth + 2];
+  msp::NodeRec* rec[2];  // [N] per type
+  int32_t* vs[2];        // [n] per type: counts in sorted order (bucket members)
+  int32_t* err;          // [1] sticky device error flags
+  bool refreshed;
+};
+
+#define MSP_HIP_TRY(expr)                                   \
+  do {                                                      \
+    hipError_t e_ = (expr);                                 \
+    if (e_ != hipSuccess) {                                 \
+      (void)hipGetLastError();                              \
+      return e_ == hipErrorOutOfMemory ? MSP_ERR_OOM : MSP_ERR_HIP; \
+    }                                                       \
+  } while (0)
+
+namespace msp {
+
+inline bool handle_ok(const msp_octree_s* t) { return t != nullptr && t->magic == kMagic; }
+
+// Stream-ordered temporary device memory; released on the same stream.
+struct Temp {
+  hipStream_t s;
+  void* p = nullptr;
+  explicit Temp(hipStream_t st) : s(st) {}
+  hipError_t alloc(size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    return hipMallocAsync(&p, bytes, s);
+  }
+  ~Temp() {
+    if (p) (void)hipFreeAsync(p, s);
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+inline unsigned grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two
+// 64x64->128-bit products and a xor with the round key; the key advances by the
+// Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x64_10(uint64_t& c0, uint64_t& c1, uint64_t& c2,
+                                              uint64_t& c3, uint64_t k0, uint64_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t a0 = 0xD2E7470EE14C6C93ULL * c0;
+    const uint64_t h0 = __umul64hi(0xD2E7470EE14C6C93ULL, c0);
+    const uint64_t a1 = 0xCA5A826395121157ULL * c2;
+    const uint64_t h1 = __umul64hi(0xCA5A826395121157ULL, c2);
+    const uint64_t n0 = h1 ^ c1 ^ k0;
+    const uint64_t n2 = h0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = a1;
+    c2 = n2;
+    c3 = a0;
+    k0 += 0x9E3779B97F4A7C15ULL;
+    k1 += 0xBB67AE8584CAA73BULL;
+  }
+}
+
+__device__ __forceinline__ uint64_t philox_word0(uint64_t seed, uint64_t stream, uint64_t a,
+                                                 uint64_t b, uint64_t c, uint64_t d) {
+  philox4x64_10(a, b, c, d, seed, stream);
+  return a;
+}
+
+}  // namespace msp

@@ -1,0 +1,208 @@
+// Device-wide exclusive prefix sums and an LSD radix sort of (64-bit key, int32 value).
+#pragma once
+
+#include "common.hpp"
+
+namespace msp {
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+// Exclusive scan of one value per thread across a 256-thread block (4 waves).
+template <class T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* lds4, T* total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  T x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    T y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) lds4[w] = x;
+  __syncthreads();
+  T off = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kScanBlock / kWave; ++k) {
+    T s = lds4[k];
+    off += (k < w) ? s : T(0);
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + x - v;
+}
+
+template <class T, class Tin, class F>
+__global__ void __launch_bounds__(kScanBlock) scan_reduce_k(const Tin* in, int64_t n, T* sums, F f) {
+  __shared__ T lds4[kScanBlock / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  T s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t idx = base + (int64_t)k * kScanBlock + threadIdx.x;
+    if (idx < n) s += f(in[idx], idx);
+  }
+  T tot;
+  (void)block_exclusive_scan<T>(s, lds4, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// out[i] = sum_{k<i} f(in[k]) + offsets[block]; if total_out, out[n] = grand total.
+template <class T, class Tin, class F>
+__global__ void __launch_bounds__(kScanBlock) scan_apply_k(const Tin* in, int64_t n, T* out,
+                                                          const T* offsets, F f, int write_total) {
+  __shared__ T lds4[kScanBlock / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  T v[kScanItems];
+  T s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t idx = base + k;
+    v[k] = idx < n ? f(in[idx], idx) : T(0);
+    s += v[k];
+  }
+  T tot;
+  T pre = block_exclusive_scan<T>(s, lds4, &tot);
+  pre += offsets ? offsets[blockIdx.x] : T(0);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t idx = base + k;
+    if (idx < n) out[idx] = pre;
+    pre += v[k];
+  }
+  if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanBlock - 1) out[n] = pre;
+}
+
+template <class T>
+struct Ident {
+  __device__ T operator()(T x, int64_t) const { return x; }
+};
+
+// Exclusive scan of f(in[i]) into out[0..n) (and out[n] = total if write_total).
+// `in` and `out` may alias element-for-element.
+template <class T, class Tin, class F>
+hipError_t exclusive_scan(const Tin* in, T* out, int64_t n, F f, bool write_total, hipStream_t s) {
+  if (n <= 0) {
+    if (write_total) return hipMemsetAsync(out, 0, sizeof(T), s);
+    return hipSuccess;
+  }
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb == 1) {
+    scan_apply_k<T, Tin, F><<<1, kScanBlock, 0, s>>>(in, n, out, nullptr, f, write_total ? 1 : 0);
+    return hipGetLastError();
+  }
+  Temp sums(s);
+  hipError_t e = sums.alloc(sizeof(T) * (size_t)nb);
+  if (e != hipSuccess) return e;
+  scan_reduce_k<T, Tin, F><<<(unsigned)nb, kScanBlock, 0, s>>>(in, n, sums.as<T>(), f);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = exclusive_scan<T, T, Ident<T>>(sums.as<T>(), sums.as<T>(), nb, Ident<T>(), false, s);
+  if (e != hipSuccess) return e;
+  scan_apply_k<T, Tin, F><<<(unsigned)nb, kScanBlock, 0, s>>>(in, n, out, sums.as<T>(), f,
+                                                             write_total ? 1 : 0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// LSD radix sort, 8-bit digits. Stable: equal keys keep their input order, so
+// sorting (key, id) pairs that start in id order yields (key, id) order.
+// ---------------------------------------------------------------------------
+constexpr int kSortBlock = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortBlock * kSortItems;
+
+__global__ void __launch_bounds__(kSortBlock) rs_hist_k(const uint64_t* keys, int64_t n, int shift,
+                                                       uint32_t* hist, int nb) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int k = 0; k < kSortItems; ++k) {
+    int64_t idx = base + (int64_t)k * kSortBlock + threadIdx.x;
+    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kSortBlock) rs_scatter_k(const uint64_t* kin, const int32_t* vin,
+                                                          uint64_t* kout, int32_t* vout, int64_t n,
+                                                          int shift, const uint32_t* off, int nb) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[kSortBlock / kWave][256];
+  const int t = threadIdx.x;
+  const int w = t / kWave;
+  const int lane = t & (kWave - 1);
+  const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (kWave - lane));
+  run[t] = off[(int64_t)t * nb + blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int c = 0; c < kSortItems; ++c) {
+#pragma unroll
+    for (int k = 0; k < kSortBlock / kWave; ++k) wcnt[k][t] = 0;
+    __syncthreads();
+    const int64_t idx = base + (int64_t)c * kSortBlock + t;
+    const bool valid = idx < n;
+    const uint64_t key = valid ? kin[idx] : 0ull;
+    const uint32_t d = (uint32_t)(key >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt);
+    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t p = run[d] + rank;
+      for (int k = 0; k < w; ++k) p += wcnt[k][d];
+      kout[p] = key;
+      vout[p] = vin[idx];
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int k = 0; k < kSortBlock / kWave; ++k) add += wcnt[k][t];
+    run[t] += add;
+  }
+}
+
+// Sort (keys, vals) of length n ascending by key; `bits` = number of key bits to sort.
+// Buffers k0/v0 hold the input and receive the output; k1/v1 are scratch of size n.
+inline hipError_t radix_sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int64_t n,
+                                   int bits, hipStream_t s) {
+  if (n <= 1) return hipSuccess;
+  const int64_t nb = (n + kSortTile - 1) / kSortTile;
+  Temp hist(s);
+  hipError_t e = hist.alloc(sizeof(uint32_t) * 256 * (size_t)nb);
+  if (e != hipSuccess) return e;
+  uint64_t* ka = k0;
+  int32_t* va = v0;
+  uint64_t* kb = k1;
+  int32_t* vb = v1;
+  int passes = 0;
+  for (int shift = 0; shift < bits; shift += 8, ++passes) {
+    rs_hist_k<<<(unsigned)nb, kSortBlock, 0, s>>>(ka, n, shift, hist.as<uint32_t>(), (int)nb);
+    e = exclusive_scan<uint32_t, uint32_t, Ident<uint32_t>>(hist.as<uint32_t>(), hist.as<uint32_t>(),
+                                                            256 * nb, Ident<uint32_t>(), false, s);
+    if (e != hipSuccess) return e;
+    rs_scatter_k<<<(unsigned)nb, kSortBlock, 0, s>>>(ka, va, kb, vb, n, shift, hist.as<uint32_t>(),
+                                                     (int)nb);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    uint64_t* tk = ka; ka = kb; kb = tk;
+    int32_t* tv = va; va = vb; vb = tv;
+  }
+  if (ka != k0) {
+    e = hipMemcpyAsync(k0, ka, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(v0, va, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s);
+  }
+  return e;
+}
+
+}  // namespace msp

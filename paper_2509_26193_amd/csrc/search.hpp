@@ -1,0 +1,250 @@
+// Barnes-Hut target search (Sec. III-B, "Division of work"; Sec. III-A, "Update of
+// synapses"). For every vacant axonal element of source i (type t):
+//   * expand a start cell S (first the root): walk its subtree in depth-first
+//     pre-order; a node with no type-t vacancy is skipped, a leaf (a neuron other
+//     than i) is always accepted, a cell containing i is opened, any other cell is
+//     accepted iff l^2 < theta^2 d^2 (l = edge, d = distance from i to the cell's
+//     type-t centroid) and opened otherwise;
+//   * weight each accepted entry by v * exp(-d^2 / sigma^2), draw u from Philox and
+//     take the first entry whose running sum exceeds u * Z;
+//   * a neuron ends the search; a cell becomes the next start cell (restart).
+// Acceptance decisions are evaluated in float64 exactly as written (no contraction),
+// weights in float32 with a running shift (largest weight = 1) so that no list
+// underflows, and running sums in float64.
+#pragma once
+
+#include <math.h>
+
+#include "common.hpp"
+
+namespace msp {
+
+constexpr double kLog2e = 1.4426950408889634074;
+// exp(-x) is 0 in float64 beyond this x; such entries carry no weight.
+constexpr double kUnderflowX = 745.13321910194110842;
+constexpr int kMaxLevels = 64;
+
+struct SearchArgs {
+  const NodeRec* rec[2];
+  const int32_t* vs[2];          // per-type counts in sorted order (bucket members)
+  const double* pos;
+  const int32_t* order;
+  const int32_t* nbeg;
+  const int32_t* nend;
+  const int32_t* leaf_of;
+  const uint8_t* type;
+  const int32_t* vac_axon;
+  const int64_t* elem_off;
+  const int32_t* work;           // sources with a_i > 0, in search order
+  const int32_t* work_count;     // device scalar: number of sources in `work`
+  int32_t* target;
+  int32_t* err;
+  double L2;                     // box_edge * box_edge
+  double theta2;                 // theta * theta
+  double inv_s2;                 // 1 / (sigma * sigma)
+  uint64_t seed, step;
+};
+
+// Running normaliser with a shift: Z = sum_e v_e * 2^((m - x_e) log2 e), m = min x_e.
+struct SumPass {
+  double inv_s2;
+  double Z = 0.0;
+  double m = HUGE_VAL;
+  __device__ __forceinline__ bool operator()(int32_t, bool, int32_t v, double d2) {
+    const double xe = d2 * inv_s2;
+    if (!(xe <= kUnderflowX)) return false;
+    if (xe < m) {
+      Z = Z * (double)exp2f((float)((xe - m) * kLog2e));
+      m = xe;
+    }
+    Z = Z + (double)v * (double)exp2f((float)((m - xe) * kLog2e));
+    return false;
+  }
+};
+
+// First entry whose running sum exceeds T (same weights as SumPass with its final m).
+struct SelectPass {
+  double inv_s2;
+  double m;
+  double T;
+  double P = 0.0;
+  int32_t chosen = -1;
+  bool chosen_neuron = false;
+  int32_t last = -1;
+  bool last_neuron = false;
+  __device__ __forceinline__ bool operator()(int32_t id, bool neuron, int32_t v, double d2) {
+    const double xe = d2 * inv_s2;
+    if (!(xe <= kUnderflowX)) return false;
+    const double w = (double)v * (double)exp2f((float)((m - xe) * kLog2e));
+    if (w > 0.0) {
+      last = id;
+      last_neuron = neuron;
+    }
+    P = P + w;
+    if (P > T) {
+      chosen = id;
+      chosen_neuron = neuron;
+      return true;
+    }
+    return false;
+  }
+};
+
+__device__ __forceinline__ double dist2(double ax, double ay, double az, double bx, double by,
+                                        double bz) {
+  const double dx = ax - bx;
+  const double dy = ay - by;
+  const double dz = az - bz;
+  return dx * dx + dy * dy + dz * dz;
+}
+
+// Members of a leaf node x (record r) other than the source, with their counts.
+template <class F>
+__device__ __forceinline__ bool leaf_entries(const SearchArgs& A, const int32_t* vs, int32_t x,
+                                             const NodeRec& r, int32_t i, double xi, double yi,
+                                             double zi, F& f) {
+  if (!(r.meta & kBucketBit)) {
+    const int32_t id = (int32_t)(r.meta & kIdMask);
+    if (id == i) return false;
+    return f(id, true, r.v, dist2(xi, yi, zi, r.x, r.y, r.z));
+  }
+  for (int32_t p = A.nbeg[x]; p < A.nend[x]; ++p) {
+    const int32_t id = A.order[p];
+    const int32_t v = vs[p];
+    if (id == i || v == 0) continue;
+    const double* q = A.pos + 3 * (int64_t)id;
+    if (f(id, true, v, dist2(xi, yi, zi, q[0], q[1], q[2]))) return true;
+  }
+  return false;
+}
+
+// Node records examined and nodes opened (the algorithmic work of one expansion).
+struct Count {
+  int32_t visits = 0, opens = 0;
+};
+
+// Accepted list of the expansion of start node S for source i, in list order.
+template <bool COUNT, class F>
+__device__ void expand(const SearchArgs& A, const NodeRec* __restrict__ R, const int32_t* vs,
+                       int32_t S, int32_t i, int32_t li, double xi, double yi, double zi, F& f,
+                       Count& cnt) {
+  const NodeRec s = R[S];
+  if (COUNT) cnt.visits += 1;
+  if (s.meta & kLeafBit) {
+    if (s.v != 0) (void)leaf_entries(A, vs, S, s, i, xi, yi, zi, f);
+    return;
+  }
+  if (COUNT) cnt.opens += 1;
+  const int32_t end = (int32_t)(s.meta & kSkipMask);
+  int32_t x = S + 1;
+  while (x < end) {
+    const NodeRec r = R[x];
+    if (COUNT) cnt.visits += 1;
+    if (r.meta & kLeafBit) {
+      if (r.v != 0 && leaf_entries(A, vs, x, r, i, xi, yi, zi, f)) return;
+      ++x;
+      continue;
+    }
+    int32_t sk = (int32_t)(r.meta & kSkipMask);
+    sk = sk > x ? sk : x + 1;
+    if (r.v == 0) {
+      x = sk;
+      continue;
+    }
+    if (li >= x && li < sk) {        // the source's own cell is always opened
+      if (COUNT) cnt.opens += 1;
+      ++x;
+      continue;
+    }
+    const double d2 = dist2(xi, yi, zi, r.x, r.y, r.z);
+    const int dep = (int)((r.meta >> kSkipBits) & 31u);
+    const double l2 = ldexp(A.L2, -2 * dep);       // (L 2^-k)^2, exact scaling
+    if (l2 < A.theta2 * d2) {
+      if (f(x, false, r.v, d2)) return;
+      x = sk;
+    } else {
+      if (COUNT) cnt.opens += 1;
+      ++x;
+    }
+  }
+}
+
+__device__ __forceinline__ double draw_u(uint64_t seed, int32_t i, int32_t j, uint64_t step,
+                                         int level) {
+  const uint64_t r = philox_word0(seed, 0, (uint64_t)i, (uint64_t)j, step, (uint64_t)level);
+  return (double)(r >> 40) * 0x1p-24;
+}
+
+// Complete one search from its level-0 normaliser. The selection passes re-walk a
+// prefix of a list already walked by its sum pass and are not counted.
+template <bool COUNT>
+__device__ int32_t finish_search(const SearchArgs& A, const NodeRec* R, const int32_t* vs,
+                                 int32_t i, int32_t j, int32_t li, double xi, double yi, double zi,
+                                 const SumPass& s0, int* levels_out, Count& cnt) {
+  int32_t S = 0;
+  SumPass s = s0;
+  Count none;
+  for (int level = 0; level < kMaxLevels; ++level) {
+    if (level > 0) {
+      s = SumPass{A.inv_s2};
+      expand<COUNT>(A, R, vs, S, i, li, xi, yi, zi, s, cnt);
+    }
+    *levels_out = level + 1;
+    if (!(s.Z > 0.0)) return -1;
+    const double T = draw_u(A.seed, i, j, A.step, level) * s.Z;
+    SelectPass p{A.inv_s2, s.m, T};
+    expand<false>(A, R, vs, S, i, li, xi, yi, zi, p, none);
+    const int32_t id = p.chosen >= 0 ? p.chosen : p.last;
+    const bool neuron = p.chosen >= 0 ? p.chosen_neuron : p.last_neuron;
+    if (id < 0) return -1;
+    if (neuron) return id;
+    S = id;
+  }
+  atomicOr(A.err, kErrArgs);
+  return -1;
+}
+
+struct DiagOut {
+  double* z0;
+  int32_t* levels;
+  int32_t* visits;
+  int32_t* opens;
+  int32_t* visits0;
+  int32_t* opens0;
+};
+
+// One thread per source: the level-0 normaliser is shared by the source's elements.
+template <bool DIAG>
+__global__ void __launch_bounds__(256) search_simple_k(SearchArgs A, DiagOut D) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= *A.work_count) return;
+  const int32_t i = A.work[w];
+  const int t = A.type[i] ? 1 : 0;
+  const NodeRec* R = A.rec[t];
+  const int32_t* vs = A.vs[t];
+  const int32_t a = A.vac_axon[i];
+  const int32_t li = A.leaf_of[i];
+  const double xi = A.pos[3 * (int64_t)i], yi = A.pos[3 * (int64_t)i + 1],
+               zi = A.pos[3 * (int64_t)i + 2];
+  const int64_t off = A.elem_off[i];
+  SumPass s0{A.inv_s2};
+  Count c0;
+  expand<DIAG>(A, R, vs, 0, i, li, xi, yi, zi, s0, c0);
+  const double z0 = s0.Z > 0.0 ? s0.Z * exp(-s0.m) : 0.0;
+  for (int32_t j = 0; j < a; ++j) {
+    int lev = 0;
+    Count c = c0;
+    const int32_t tgt = finish_search<DIAG>(A, R, vs, i, j, li, xi, yi, zi, s0, &lev, c);
+    A.target[off + j] = tgt;
+    if (DIAG) {
+      if (D.z0) D.z0[off + j] = z0;
+      if (D.levels) D.levels[off + j] = lev;
+      if (D.visits) D.visits[off + j] = c.visits;
+      if (D.opens) D.opens[off + j] = c.opens;
+      if (D.visits0) D.visits0[off + j] = c0.visits;
+      if (D.opens0) D.opens0[off + j] = c0.opens;
+    }
+  }
+}
+
+}  // namespace msp

@@ -1,0 +1,298 @@
+"""Parity of the HIP path (through the C ABI) with the fp64 CPU oracle.
+
+Bars: octree topology and counts bit-exact, float64 centroids bit-exact, level-0
+normalisers within 1e-5 relative, target choices identical except draws within 1e-6
+of a cumulative boundary (share < 1e-4), synapse lists bit-exact given identical
+proposals.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2509_26193_amd as msp
+from oracle import oracle as orc
+from synth_inputs import (config_clusters, config_large, config_small, uniform_cube, Workload)
+from gpu_util import DEV, T, compare_search, gpu_search, oracle_tree, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _degenerate_positions():
+    rng = np.random.default_rng(11)
+    cases = {}
+    for n in (1, 2, 3, 9, 150):
+        cases[f"uniform{n}"] = rng.uniform(0, 1000, size=(n, 3))
+    p = rng.uniform(0, 1000, size=(300, 3))
+    p[5] = p[6] = p[7] = p[2]
+    p[10] = p[9] + 1e-6
+    cases["buckets"] = p
+    cases["all_coincident"] = np.full((12, 3), 500.0)
+    c = rng.uniform(0, 1000, size=(3, 3))
+    cases["chains"] = np.repeat(c, 40, axis=0) + rng.normal(0, 0.01, size=(120, 3))
+    return cases
+
+
+def _workload(pos, seed=1, sigma=300.0, theta=0.3):
+    n = pos.shape[0]
+    rng = np.random.default_rng(seed)
+    return Workload("case", pos, np.zeros(3), 1000.0, (rng.random(n) < 0.3).astype(np.uint8),
+                    rng.integers(0, 3, n).astype(np.int32), rng.integers(0, 4, n).astype(np.int32),
+                    rng.integers(0, 4, n).astype(np.int32), sigma, theta, seed=seed)
+
+
+def _check_tree(w, label):
+    g = gpu_search(w)
+    t = oracle_tree(w)
+    topo = g["tree"].export_topology()
+    nd = t.nodes()
+    order, keys = t.order()
+    assert g["tree"].num_nodes == t.num_nodes, (g["tree"].num_nodes, t.num_nodes)
+    assert np.array_equal(topo["order"].cpu().numpy(), order)
+    assert np.array_equal(topo["keys"].cpu().numpy().view(np.uint64), np.sort(keys))
+    assert np.array_equal(topo["depth"].cpu().numpy(), nd["depth"])
+    assert np.array_equal(topo["begin"].cpu().numpy(), nd["begin"])
+    assert np.array_equal(topo["end"].cpu().numpy(), nd["end"])
+    assert np.array_equal(topo["subtree_end"].cpu().numpy(), nd["subtree_end"])
+    for ty in (0, 1):
+        v, c = g["tree"].export_aggregates(ty)
+        ov, oc = t.aggregates(ty)
+        v, c = v.cpu().numpy(), c.cpu().numpy()
+        assert np.array_equal(v, ov)
+        pos = ov > 0
+        assert np.array_equal(c[pos].view(np.uint64), oc[pos].view(np.uint64)), label
+    say(f"[{label}] tree ok: n={w.n} nodes={t.num_nodes}")
+    return g, t
+
+
+@pytest.mark.parametrize("case", list(_degenerate_positions()))
+def test_tree_and_search_degenerate(case):
+    pos = _degenerate_positions()[case]
+    say(f"case {case} n={pos.shape[0]}")
+    w = _workload(pos)
+    g, t = _check_tree(w, case)
+    off, src, elem = orc.search_list(w.vac_axon)
+    assert np.array_equal(g["off"], off)
+    o = t.find_targets(w.neuron_type, w.sigma, w.theta, w.seed, w.step, src, elem)
+    compare_search(g["target"], g["z0"], o, case)
+    g["tree"].free()
+
+
+def test_tree_small_bitwise():
+    w = config_small()
+    g, t = _check_tree(w, "small4096")
+    g["tree"].free()
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.2, 0.3, 0.5, 0.9])
+def test_search_small(theta):
+    w = config_small()
+    say(f"small4096 theta={theta}")
+    g = gpu_search(w, theta=theta)
+    t = oracle_tree(w)
+    off, src, elem = orc.search_list(w.vac_axon)
+    o = t.find_targets(w.neuron_type, w.sigma, theta, w.seed, w.step, src, elem)
+    compare_search(g["target"], g["z0"], o, f"small theta={theta}")
+    same = g["target"] == o["target"]
+    assert np.array_equal(g["levels"][same], o["levels"][same])
+    # the kernel examines exactly the oracle's node records (same acceptance decisions)
+    assert np.array_equal(g["visits"][same], o["visits"][same])
+    assert np.array_equal(g["opens"][same], o["opens"][same])
+    g["tree"].free()
+
+
+def test_search_theta0_is_direct():
+    w = uniform_cube(600, 1000.0, seed=9)
+    g = gpu_search(w, theta=0.0)
+    t = oracle_tree(w)
+    off, src, elem = orc.search_list(w.vac_axon)
+    o = t.find_targets(w.neuron_type, w.sigma, 0.0, w.seed, w.step, src, elem)
+    compare_search(g["target"], g["z0"], o, "theta0")
+    assert np.all(g["levels"] == 1)
+    g["tree"].free()
+
+
+def test_special_cases():
+    # all vacancy on one neuron: every other source picks it, it finds nobody
+    w = uniform_cube(3000, 1000.0, seed=12)
+    w.vac_exc[:] = 0
+    w.vac_inh[:] = 0
+    w.vac_exc[77] = 5
+    w.vac_inh[77] = 5
+    g = gpu_search(w)
+    off = g["off"]
+    src = np.repeat(np.arange(w.n), w.vac_axon)
+    assert np.all(g["target"][src != 77] == 77)
+    assert np.all(g["target"][src == 77] == -1)
+    g["tree"].free()
+    # no vacancy anywhere: every search returns -1
+    w = uniform_cube(500, 1000.0, seed=13)
+    w.vac_exc[:] = 0
+    w.vac_inh[:] = 0
+    g = gpu_search(w)
+    assert np.all(g["target"] == -1)
+    g["tree"].free()
+    # no searches at all
+    w = uniform_cube(500, 1000.0, seed=14)
+    w.vac_axon[:] = 0
+    g = gpu_search(w)
+    assert g["target"].size == 0 and g["off"][-1] == 0
+    g["tree"].free()
+
+
+def test_far_apart_pair_underflow():
+    # two neurons 40 sigma apart: the fp64 weight exp(-1600) is 0, so no target
+    pos = np.array([[0.0, 0.0, 0.0], [999.0, 999.0, 999.0]])
+    w = Workload("pair", pos, np.zeros(3), 1000.0, np.zeros(2, np.uint8), np.ones(2, np.int32),
+                 np.ones(2, np.int32), np.ones(2, np.int32), 43.0, 0.3)
+    g = gpu_search(w)
+    t = oracle_tree(w)
+    o = t.find_targets(w.neuron_type, w.sigma, w.theta, 42, 0, [0, 1], [0, 0])
+    assert np.array_equal(g["target"], o["target"])
+    # 20 sigma apart (weight e^-400): representable in fp64, chosen by both
+    w.sigma = 86.6
+    g = gpu_search(w)
+    o = t.find_targets(w.neuron_type, w.sigma, w.theta, 42, 0, [0, 1], [0, 0])
+    assert np.array_equal(g["target"], o["target"])
+    assert list(o["target"]) == [1, 0]
+    g["tree"].free()
+
+
+def test_deterministic_and_order_independent():
+    w = config_small()
+    a = gpu_search(w)
+    b = gpu_search(w)
+    assert np.array_equal(a["target"], b["target"])
+    assert np.array_equal(a["z0"].view(np.uint64), b["z0"].view(np.uint64))
+    a["tree"].free()
+    b["tree"].free()
+
+
+def test_commit_parity_with_gpu_proposals():
+    w = config_small()
+    g = gpu_search(w)
+    res = msp.commit_synapses(T(g["target"].astype(np.int32), torch.int32), T(g["off"], torch.int64),
+                              g["ty"], g["va"], g["ve"], g["vi"], w.seed, w.step,
+                              return_accepted=True)
+    oc = orc.commit(g["off"], g["target"], w.neuron_type, w.vac_axon, w.vac_exc, w.vac_inh,
+                    w.seed, w.step)
+    say(f"commit: formed {res['n_formed']} of {g['target'].size} requests")
+    assert res["n_formed"] == oc["n_formed"]
+    assert np.array_equal(res["syn_src"].cpu().numpy(), oc["syn_src"])
+    assert np.array_equal(res["syn_tgt"].cpu().numpy(), oc["syn_tgt"])
+    assert np.array_equal(res["syn_type"].cpu().numpy(), oc["syn_type"])
+    assert np.array_equal(res["accepted"].cpu().numpy(), oc["accepted"])
+    for k, name in ((g["va"], "vac_axon"), (g["ve"], "vac_exc"), (g["vi"], "vac_inh")):
+        assert np.array_equal(k.cpu().numpy(), oc[name]), name
+    g["tree"].free()
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_commit_heavy_collisions(seed):
+    rng = np.random.default_rng(seed)
+    n = 20000
+    ty = (rng.random(n) < 0.2).astype(np.uint8)
+    a = rng.integers(0, 5, n).astype(np.int32)
+    ve = rng.integers(0, 3, n).astype(np.int32)
+    vi = rng.integers(0, 3, n).astype(np.int32)
+    off, src, elem = orc.search_list(a)
+    tgt = rng.integers(0, 300, src.size)          # ~100 requests per target
+    tgt[rng.random(src.size) < 0.05] = -1
+    tgt[::97] = 4                                 # one hub with thousands of requests
+    res = msp.commit_synapses(T(tgt.astype(np.int32), torch.int32), T(off, torch.int64),
+                              T(ty, torch.uint8), T(a, torch.int32), T(ve, torch.int32),
+                              T(vi, torch.int32), 99, 7, return_accepted=True)
+    oc = orc.commit(off, tgt, ty, a, ve, vi, 99, 7)
+    assert res["n_formed"] == oc["n_formed"]
+    assert np.array_equal(res["accepted"].cpu().numpy(), oc["accepted"])
+    assert np.array_equal(res["syn_src"].cpu().numpy(), oc["syn_src"])
+    assert np.array_equal(res["syn_tgt"].cpu().numpy(), oc["syn_tgt"])
+
+
+def test_capacity_and_invalid_inputs():
+    w = uniform_cube(1000, 1000.0, seed=4)
+    tree = msp.build_octree(T(w.pos, torch.float64), w.box_min, w.box_edge)
+    ve, vi = T(w.vac_exc, torch.int32), T(w.vac_inh, torch.int32)
+    msp.update_vacant_counts(tree, ve, vi)
+    ty, va = T(w.neuron_type, torch.uint8), T(w.vac_axon, torch.int32)
+    L = msp.lib()
+    st = torch.cuda.current_stream().cuda_stream
+    small = torch.full((5,), -7, dtype=torch.int32, device=DEV)
+    off = torch.empty(w.n + 1, dtype=torch.int64, device=DEV)
+    rc = L.msp_find_targets(tree.handle, ty.data_ptr(), va.data_ptr(), w.sigma, w.theta, 1, 0,
+                            small.data_ptr(), off.data_ptr(), 5, st)
+    assert rc == msp._lib.MSP_ERR_CAPACITY
+    assert torch.all(small == -7)
+    assert int(off[-1]) == w.searches
+    for sig, th in ((0.0, 0.3), (-1.0, 0.3), (750.0, -0.1), (float("nan"), 0.3)):
+        rc = L.msp_find_targets(tree.handle, ty.data_ptr(), va.data_ptr(), sig, th, 1, 0,
+                                small.data_ptr(), off.data_ptr(), 5, st)
+        assert rc == msp._lib.MSP_ERR_INVALID
+    bad = va.clone()
+    bad[3] = -1
+    with pytest.raises(msp.MspError):
+        msp.find_targets(tree, ty, bad, w.sigma, w.theta, 1, 0)
+    # commit over capacity leaves every count untouched
+    tgt, off = msp.find_targets(tree, ty, va, w.sigma, w.theta, 1, 0)
+    before = (va.clone(), ve.clone(), vi.clone())
+    with pytest.raises(msp.MspError) as ei:
+        msp.commit_synapses(tgt, off, ty, va, ve, vi, 1, 0, syn_capacity=1)
+    assert ei.value.status == msp._lib.MSP_ERR_CAPACITY
+    for x, y in zip(before, (va, ve, vi)):
+        assert torch.equal(x, y)
+    # negative dendritic count: sticky device flag
+    assert tree.last_device_error() == 0
+    neg = ve.clone()
+    neg[0] = -2
+    msp.update_vacant_counts(tree, neg, vi)
+    assert tree.last_device_error() == msp._lib.MSP_ERR_DEVICE
+    tree.free()
+    # non-finite position: sticky device flag
+    p = w.pos.copy()
+    p[10, 1] = np.nan
+    t2 = msp.build_octree(T(p, torch.float64), w.box_min, w.box_edge)
+    assert t2.last_device_error() == msp._lib.MSP_ERR_DEVICE
+    t2.free()
+
+
+def test_clusters_sampled():
+    """2^20 neurons in 64 Gaussian clusters, full GPU update, oracle on a sample."""
+    for theta in (0.2, 0.5):
+        w = config_clusters(theta=theta)
+        say(f"clusters n={w.n} theta={theta} searches={w.searches}")
+        g = gpu_search(w)
+        t = oracle_tree(w)
+        off, src, elem = orc.search_list(w.vac_axon)
+        rng = np.random.default_rng(5)
+        q = np.sort(rng.choice(src.size, size=6000, replace=False))
+        o = t.find_targets(w.neuron_type, w.sigma, theta, w.seed, w.step, src[q], elem[q])
+        compare_search(g["target"][q], g["z0"][q], o, f"clusters theta={theta}")
+        g["tree"].free()
+        del t
+
+
+def test_full_update_sequence_small():
+    """Four updates on the GPU against the oracle, both sides from the same state."""
+    w = uniform_cube(3000, 1000.0, seed=21, a_hi=3, v_hi=2)
+    tree = msp.build_octree(T(w.pos, torch.float64), w.box_min, w.box_edge)
+    ot = orc.OracleTree(w.pos, w.box_min, w.box_edge)
+    a, e, i = w.vac_axon.copy(), w.vac_exc.copy(), w.vac_inh.copy()
+    ty = T(w.neuron_type, torch.uint8)
+    for step in range(4):
+        ga, ge, gi = T(a, torch.int32), T(e, torch.int32), T(i, torch.int32)
+        msp.update_vacant_counts(tree, ge, gi)
+        tgt, off, z0, _ = msp.find_targets(tree, ty, ga, w.sigma, w.theta, w.seed, step, diag=True)
+        ot.update_counts(e, i)
+        ooff, src, elem = orc.search_list(a)
+        o = ot.find_targets(w.neuron_type, w.sigma, w.theta, w.seed, step, src, elem)
+        gt = tgt.cpu().numpy().astype(np.int64)
+        compare_search(gt, z0.cpu().numpy(), o, f"update {step}")
+        res = msp.commit_synapses(tgt, off, ty, ga, ge, gi, w.seed, step)
+        oc = orc.commit(ooff, gt, w.neuron_type, a, e, i, w.seed, step)
+        assert np.array_equal(res["syn_src"].cpu().numpy(), oc["syn_src"])
+        assert np.array_equal(res["syn_tgt"].cpu().numpy(), oc["syn_tgt"])
+        a, e, i = oc["vac_axon"], oc["vac_exc"], oc["vac_inh"]
+        assert np.array_equal(ga.cpu().numpy(), a)
+        # next update: regrow a few elements so searches continue
+        a = a + (np.arange(w.n) % 7 == step).astype(np.int32)
+        e = e + (np.arange(w.n) % 5 == step).astype(np.int32)
+    tree.free()
