@@ -9,7 +9,7 @@
 //     take the first entry whose running sum exceeds u * Z;
 //   * a neuron ends the search; a cell becomes the next start cell (restart).
 // Acceptance decisions are evaluated in float64 exactly as written (no contraction),
-// weights in float32 with a running shift (largest weight = 1) so that no list
+// weight mantissas in float32 with an exact power-of-two shift so that no list
 // underflows, and running sums in float64.
 #pragma once
 
@@ -45,27 +45,42 @@ struct SearchArgs {
   uint64_t seed, step;
 };
 
-// Running normaliser with a shift: Z = sum_e v_e * 2^((m - x_e) log2 e), m = min x_e.
+// Kernel weights v * exp(-x), x = d^2 / sigma^2, with y = x log2(e) split as
+// y = fl + fr (fl integer, 0 <= fr < 1): mantissa 2^-fr in float32, then an exact
+// power-of-two scale 2^(s - fl) relative to a running shift s = min fl (so the
+// largest weight of a list is in (v/2, v]). Rescaling a partial sum when s drops
+// is exact, so the sum pass and the selection pass see identical weights and sums.
+__device__ __forceinline__ bool weight_parts(double d2, double inv_s2, double& mant, int& fl) {
+  const double x = d2 * inv_s2;
+  if (!(x <= kUnderflowX)) return false;        // exp(-x) is 0 in float64
+  const double y = x * kLog2e;
+  const double f = floor(y);
+  mant = (double)exp2f(-(float)(y - f));
+  fl = (int)f;
+  return true;
+}
+
 struct SumPass {
   double inv_s2;
   double Z = 0.0;
-  double m = HUGE_VAL;
+  int s = 0x7FFFFFFF;                           // running shift (min fl)
   __device__ __forceinline__ bool operator()(int32_t, bool, int32_t v, double d2) {
-    const double xe = d2 * inv_s2;
-    if (!(xe <= kUnderflowX)) return false;
-    if (xe < m) {
-      Z = Z * (double)exp2f((float)((xe - m) * kLog2e));
-      m = xe;
+    double mant;
+    int fl;
+    if (!weight_parts(d2, inv_s2, mant, fl)) return false;
+    if (fl < s) {
+      Z = (s == 0x7FFFFFFF) ? 0.0 : ldexp(Z, fl - s);
+      s = fl;
     }
-    Z = Z + (double)v * (double)exp2f((float)((m - xe) * kLog2e));
+    Z = Z + ldexp((double)v * mant, s - fl);
     return false;
   }
 };
 
-// First entry whose running sum exceeds T (same weights as SumPass with its final m).
+// First entry whose running sum exceeds T (same weights as SumPass with its final s).
 struct SelectPass {
   double inv_s2;
-  double m;
+  int s;
   double T;
   double P = 0.0;
   int32_t chosen = -1;
@@ -73,9 +88,10 @@ struct SelectPass {
   int32_t last = -1;
   bool last_neuron = false;
   __device__ __forceinline__ bool operator()(int32_t id, bool neuron, int32_t v, double d2) {
-    const double xe = d2 * inv_s2;
-    if (!(xe <= kUnderflowX)) return false;
-    const double w = (double)v * (double)exp2f((float)((m - xe) * kLog2e));
+    double mant;
+    int fl;
+    if (!weight_parts(d2, inv_s2, mant, fl)) return false;
+    const double w = ldexp((double)v * mant, s - fl);
     if (w > 0.0) {
       last = id;
       last_neuron = neuron;
@@ -192,7 +208,7 @@ __device__ int32_t finish_search(const SearchArgs& A, const NodeRec* R, const in
     *levels_out = level + 1;
     if (!(s.Z > 0.0)) return -1;
     const double T = draw_u(A.seed, i, j, A.step, level) * s.Z;
-    SelectPass p{A.inv_s2, s.m, T};
+    SelectPass p{A.inv_s2, s.s, T};
     expand<false>(A, R, vs, S, i, li, xi, yi, zi, p, none);
     const int32_t id = p.chosen >= 0 ? p.chosen : p.last;
     const bool neuron = p.chosen >= 0 ? p.chosen_neuron : p.last_neuron;
@@ -230,7 +246,7 @@ __global__ void __launch_bounds__(256) search_simple_k(SearchArgs A, DiagOut D) 
   SumPass s0{A.inv_s2};
   Count c0;
   expand<DIAG>(A, R, vs, 0, i, li, xi, yi, zi, s0, c0);
-  const double z0 = s0.Z > 0.0 ? s0.Z * exp(-s0.m) : 0.0;
+  const double z0 = s0.Z > 0.0 ? ldexp(s0.Z, -s0.s) : 0.0;
   for (int32_t j = 0; j < a; ++j) {
     int lev = 0;
     Count c = c0;
