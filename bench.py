@@ -173,7 +173,7 @@ def main():
     achieved = B / kmean
     roof = dict(bound="hbm", achieved=achieved / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
                 frac=achieved / HBM_PEAK, traffic=None,
-                kernel="search_simple_k", kernel_ms=kmean * 1e3,
+                kernel="search_sweep_k+search_draw_k", kernel_ms=kmean * 1e3,
                 algorithmic_bytes_per_launch=B, node_visits_per_launch=visits)
     log(f"step {sec * 1e3:.1f} ms; search kernel {kmean * 1e3:.2f} ms; "
         f"{achieved / 1e9:.1f} GB/s algorithmic ({roof['frac']:.3f} of HBM peak)")

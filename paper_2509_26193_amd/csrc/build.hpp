@@ -74,8 +74,7 @@ __global__ void __launch_bounds__(kBuildBlock) nodes_k(const uint64_t* __restric
                                                       const int32_t* __restrict__ order, int64_t n,
                                                       const int32_t* __restrict__ base,
                                                       int32_t* skip, uint8_t* depth, int32_t* nbeg,
-                                                      int32_t* nend, int32_t* leaf_of,
-                                                      int32_t* level_cnt) {
+                                                      int32_t* nend, int32_t* leaf_of) {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n) return;
   const int cl = m == 0 ? -1 : common_digits(keys[m - 1], keys[m]);
@@ -113,20 +112,44 @@ __global__ void __launch_bounds__(kBuildBlock) nodes_k(const uint64_t* __restric
     depth[idx] = (uint8_t)k;
     nbeg[idx] = (int32_t)m;
     nend[idx] = (int32_t)e;
-    atomicAdd(&level_cnt[k], 1);
     const bool leaf = (e - m == 1) || k == kMaxDepth;
     if (leaf)
       for (int64_t p = m; p < e; ++p) leaf_of[order[p]] = (int32_t)idx;
   }
 }
 
+// Nodes per depth: block-local counts in LDS, one global atomic per depth and block.
+__global__ void __launch_bounds__(kBuildBlock) level_count_k(const uint8_t* __restrict__ depth,
+                                                            int64_t N, int32_t* level_cnt) {
+  __shared__ int32_t c[kMaxDepth + 1];
+  if (threadIdx.x <= kMaxDepth) c[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < N) atomicAdd(&c[depth[x]], 1);
+  __syncthreads();
+  if (threadIdx.x <= kMaxDepth && c[threadIdx.x]) atomicAdd(&level_cnt[threadIdx.x], c[threadIdx.x]);
+}
+
+// Group node ids by depth (order within a depth is arbitrary: the refresh of one
+// depth treats its nodes independently).
 __global__ void __launch_bounds__(kBuildBlock) level_scatter_k(const uint8_t* __restrict__ depth,
                                                               int64_t N, int32_t* cursor,
                                                               int32_t* level_nodes) {
+  __shared__ int32_t c[kMaxDepth + 1];
+  __shared__ int32_t base[kMaxDepth + 1];
+  if (threadIdx.x <= kMaxDepth) c[threadIdx.x] = 0;
+  __syncthreads();
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= N) return;
-  const int p = atomicAdd(&cursor[depth[x]], 1);
-  level_nodes[p] = (int32_t)x;
+  int d = -1, r = 0;
+  if (x < N) {
+    d = depth[x];
+    r = atomicAdd(&c[d], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x <= kMaxDepth && c[threadIdx.x])
+    base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], c[threadIdx.x]);
+  __syncthreads();
+  if (d >= 0) level_nodes[base[d] + r] = (int32_t)x;
 }
 
 // Per-type records start with count 0 and the node's meta word: an inner node keeps

@@ -1,6 +1,7 @@
 // libmsp: C ABI entry points (declared in include/msp.h). One translation unit.
 #include <cmath>
 #include <cstring>
+#include <cstdlib>
 #include <new>
 
 #include "common.hpp"
@@ -8,6 +9,7 @@
 #include "build.hpp"
 #include "refresh.hpp"
 #include "search.hpp"
+#include "search_wave.hpp"
 #include "commit.hpp"
 
 using namespace msp;
@@ -57,18 +59,31 @@ __global__ void check_axon_k(const int32_t* __restrict__ a, const uint8_t* __res
   if (a[i] < 0 || ty[i] > 1) atomicOr(flag, 1);
 }
 
-// Sources with a_i > 0 in Morton order, excitatory first, then inhibitory.
+// Sources with a_i > 0 in Morton order: excitatory ones first, then inhibitory ones
+// from the next multiple of 64, so that no 64-source tile mixes the two types.
+// Unused slots hold -1. count[0] = number of tiles.
 __global__ void worklist_k(const int32_t* __restrict__ order, const int32_t* __restrict__ a,
                            const uint8_t* __restrict__ ty, int64_t n,
                            const int32_t* __restrict__ p0, const int32_t* __restrict__ p1,
                            int32_t* __restrict__ work, int32_t* __restrict__ count) {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m == 0) *count = p0[n] + p1[n];
+  const int32_t base1 = (p0[n] + kWave - 1) / kWave * kWave;
+  if (m == 0) *count = (base1 + (p1[n] + kWave - 1) / kWave * kWave) / kWave;
   if (m >= n) return;
   const int32_t id = order[m];
   if (a[id] <= 0) return;
-  if (ty[id]) work[p0[n] + p1[m]] = id;
+  if (ty[id]) work[base1 + p1[m]] = id;
   else work[p0[m]] = id;
+}
+
+// One thread per worklist slot (the first, per-source kernel).
+__global__ void tiles_to_slots_k(const int32_t* __restrict__ tiles, int32_t* __restrict__ slots) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *slots = *tiles * kWave;
+}
+
+bool use_simple_kernel() {
+  const char* e = getenv("MSP_SEARCH_KERNEL");
+  return e && std::strcmp(e, "simple") == 0;
 }
 
 }  // namespace
@@ -166,7 +181,9 @@ msp_status msp_build_octree(const double* pos, int64_t n, const double box_min[3
     TRY(hipMemsetAsync(lcnt, 0, sizeof(int32_t) * 2 * (kMaxDepth + 1), s));
     nodes_k<<<grid_for(n, kBuildBlock), kBuildBlock, 0, s>>>(t->keys, t->order, n,
                                                              base.as<int32_t>(), t->skip, t->depth,
-                                                             t->nbeg, t->nend, t->leaf_of, lcnt);
+                                                             t->nbeg, t->nend, t->leaf_of);
+    TRY(hipGetLastError());
+    level_count_k<<<grid_for(N, kBuildBlock), kBuildBlock, 0, s>>>(t->depth, N, lcnt);
     TRY(hipGetLastError());
     int32_t hc[kMaxDepth + 1];
     TRY(hipMemcpyAsync(hc, lcnt, sizeof(hc), hipMemcpyDeviceToHost, s));
@@ -248,9 +265,9 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
     return MSP_ERR_INVALID;
   if (capacity_S < 0) return MSP_ERR_INVALID;
   const int64_t n = t->n;
-  Temp flag(s), p0(s), p1(s), work(s);
-  MSP_HIP_TRY(flag.alloc(sizeof(int32_t) * 2));
-  MSP_HIP_TRY(hipMemsetAsync(flag.p, 0, sizeof(int32_t) * 2, s));
+  Temp flag(s), p0(s), p1(s), work(s), ck(s);
+  MSP_HIP_TRY(flag.alloc(sizeof(int32_t) * (4 + kXcd)));
+  MSP_HIP_TRY(hipMemsetAsync(flag.p, 0, sizeof(int32_t) * (4 + kXcd), s));
   check_axon_k<<<grid_for(n, 256), 256, 0, s>>>(vac_axon, neuron_type, n, flag.as<int32_t>());
   MSP_HIP_TRY(hipGetLastError());
   MSP_HIP_TRY((exclusive_scan<int64_t, int32_t, CountPos>(vac_axon, elem_offset_out, n, CountPos(),
@@ -267,16 +284,21 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
 
   MSP_HIP_TRY(p0.alloc(sizeof(int32_t) * (n + 1)));
   MSP_HIP_TRY(p1.alloc(sizeof(int32_t) * (n + 1)));
-  MSP_HIP_TRY(work.alloc(sizeof(int32_t) * n));
+  const int64_t slots = n + 2 * kWave;
+  MSP_HIP_TRY(work.alloc(sizeof(int32_t) * slots));
+  MSP_HIP_TRY(hipMemsetAsync(work.p, 0xFF, sizeof(int32_t) * slots, s));
   MSP_HIP_TRY((exclusive_scan<int32_t, int32_t, SrcFlag>(t->order, p0.as<int32_t>(), n,
                                                          SrcFlag{vac_axon, neuron_type, 0}, true, s)));
   MSP_HIP_TRY((exclusive_scan<int32_t, int32_t, SrcFlag>(t->order, p1.as<int32_t>(), n,
                                                          SrcFlag{vac_axon, neuron_type, 1}, true, s)));
-  int32_t* wcount = flag.as<int32_t>() + 1;
+  int32_t* tiles = flag.as<int32_t>() + 1;
+  int32_t* nslots = flag.as<int32_t>() + 2;
+  int32_t* queue = flag.as<int32_t>() + 4;
   worklist_k<<<grid_for(n, 256), 256, 0, s>>>(t->order, vac_axon, neuron_type, n,
                                               p0.as<int32_t>(), p1.as<int32_t>(),
-                                              work.as<int32_t>(), wcount);
+                                              work.as<int32_t>(), tiles);
   MSP_HIP_TRY(hipGetLastError());
+  const bool simple = use_simple_kernel();
 
   SearchArgs A;
   A.rec[0] = t->rec[0];
@@ -292,7 +314,7 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
   A.vac_axon = vac_axon;
   A.elem_off = elem_offset_out;
   A.work = work.as<int32_t>();
-  A.work_count = wcount;
+  A.work_count = nslots;
   A.target = target_out;
   A.err = t->err;
   A.L2 = t->box_edge * t->box_edge;
@@ -311,12 +333,63 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
   if (timed) {
     MSP_HIP_TRY(hipEventCreate(&ev[0]));
     MSP_HIP_TRY(hipEventCreate(&ev[1]));
-    MSP_HIP_TRY(hipEventRecord(ev[0], s));
   }
-  if (any)
-    search_simple_k<true><<<grid_for(n, 256), 256, 0, s>>>(A, D);
-  else
-    search_simple_k<false><<<grid_for(n, 256), 256, 0, s>>>(A, D);
+  // the coherent sweep needs the exact tile count to size its checkpoint buffers
+  int32_t ntiles = 0;
+  if (!simple) {
+    MSP_HIP_TRY(hipMemcpyAsync(&ntiles, tiles, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MSP_HIP_TRY(hipStreamSynchronize(s));
+  }
+  SweepOut W{};
+  unsigned sweep_blocks = 0;
+  if (simple) {
+    tiles_to_slots_k<<<1, 64, 0, s>>>(tiles, nslots);
+  } else {
+    int ncu = 0, per_cu = 0;
+    MSP_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, t->device));
+    MSP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, any ? (const void*)search_sweep_k<true> : (const void*)search_sweep_k<false>,
+        kWaveBlock, 0));
+    if (per_cu < 1) per_cu = 1;
+    int64_t blocks = (int64_t)ncu * per_cu;
+    const int64_t need = ((int64_t)ntiles + (kWaveBlock / kWave) - 1) / (kWaveBlock / kWave);
+    if (blocks > need) blocks = need;
+    if (blocks < 1) blocks = 1;
+    sweep_blocks = (unsigned)blocks;
+    const int64_t nt = ntiles > 0 ? ntiles : 1;
+    const int64_t ns = nt * kWave;
+    const int64_t nc = nt * kCkpt * kWave;
+    const size_t bytes = sizeof(double) * (size_t)(ns + nc) +
+                         sizeof(int32_t) * (size_t)(3 * ns + nt + nt * kCkpt + 2 * nc);
+    MSP_HIP_TRY(ck.alloc(bytes));
+    W.Z = ck.as<double>();
+    W.ck_P = W.Z + ns;
+    W.s = reinterpret_cast<int32_t*>(W.ck_P + nc);
+    W.v0 = W.s + ns;
+    W.o0 = W.v0 + ns;
+    W.nck = W.o0 + ns;
+    W.ck_x = W.nck + nt;
+    W.ck_s = W.ck_x + nt * kCkpt;
+    W.ck_me = W.ck_s + nc;
+    W.tile_count = tiles;
+    W.queue = queue;
+  }
+  if (timed) MSP_HIP_TRY(hipEventRecord(ev[0], s));
+  if (simple) {
+    if (any)
+      search_simple_k<true><<<grid_for(slots, 256), 256, 0, s>>>(A, D);
+    else
+      search_simple_k<false><<<grid_for(slots, 256), 256, 0, s>>>(A, D);
+  } else if (ntiles > 0) {
+    const unsigned draw_grid = grid_for((int64_t)ntiles * kWave, 256);
+    if (any) {
+      search_sweep_k<true><<<sweep_blocks, kWaveBlock, 0, s>>>(A, W);
+      search_draw_k<true><<<draw_grid, 256, 0, s>>>(A, D, W);
+    } else {
+      search_sweep_k<false><<<sweep_blocks, kWaveBlock, 0, s>>>(A, W);
+      search_draw_k<false><<<draw_grid, 256, 0, s>>>(A, D, W);
+    }
+  }
   hipError_t le = hipGetLastError();
   if (timed) {
     float ms = 0.0f;

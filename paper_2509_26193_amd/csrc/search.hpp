@@ -55,7 +55,9 @@ __device__ __forceinline__ bool weight_parts(double d2, double inv_s2, double& m
   if (!(x <= kUnderflowX)) return false;        // exp(-x) is 0 in float64
   const double y = x * kLog2e;
   const double f = floor(y);
-  mant = (double)exp2f(-(float)(y - f));
+  // y - f is in [0, 1): 2^-(y-f) is in (1/2, 1], a normal float32, so the bare
+  // hardware exp2 needs no range reduction
+  mant = (double)__builtin_amdgcn_exp2f(-(float)(y - f));
   fl = (int)f;
   return true;
 }
@@ -139,20 +141,12 @@ struct Count {
   int32_t visits = 0, opens = 0;
 };
 
-// Accepted list of the expansion of start node S for source i, in list order.
+// The source's own walk over pre-order positions [x, end) of a start cell's
+// subtree (visiting, skipping, opening and accepting as the search rules say).
 template <bool COUNT, class F>
-__device__ void expand(const SearchArgs& A, const NodeRec* __restrict__ R, const int32_t* vs,
-                       int32_t S, int32_t i, int32_t li, double xi, double yi, double zi, F& f,
-                       Count& cnt) {
-  const NodeRec s = R[S];
-  if (COUNT) cnt.visits += 1;
-  if (s.meta & kLeafBit) {
-    if (s.v != 0) (void)leaf_entries(A, vs, S, s, i, xi, yi, zi, f);
-    return;
-  }
-  if (COUNT) cnt.opens += 1;
-  const int32_t end = (int32_t)(s.meta & kSkipMask);
-  int32_t x = S + 1;
+__device__ void expand_range(const SearchArgs& A, const NodeRec* __restrict__ R, const int32_t* vs,
+                             int32_t x, int32_t end, int32_t i, int32_t li, double xi, double yi,
+                             double zi, F& f, Count& cnt) {
   while (x < end) {
     const NodeRec r = R[x];
     if (COUNT) cnt.visits += 1;
@@ -185,26 +179,36 @@ __device__ void expand(const SearchArgs& A, const NodeRec* __restrict__ R, const
   }
 }
 
+// Accepted list of the expansion of start node S for source i, in list order.
+template <bool COUNT, class F>
+__device__ void expand(const SearchArgs& A, const NodeRec* __restrict__ R, const int32_t* vs,
+                       int32_t S, int32_t i, int32_t li, double xi, double yi, double zi, F& f,
+                       Count& cnt) {
+  const NodeRec s = R[S];
+  if (COUNT) cnt.visits += 1;
+  if (s.meta & kLeafBit) {
+    if (s.v != 0) (void)leaf_entries(A, vs, S, s, i, xi, yi, zi, f);
+    return;
+  }
+  if (COUNT) cnt.opens += 1;
+  expand_range<COUNT>(A, R, vs, S + 1, (int32_t)(s.meta & kSkipMask), i, li, xi, yi, zi, f, cnt);
+}
+
 __device__ __forceinline__ double draw_u(uint64_t seed, int32_t i, int32_t j, uint64_t step,
                                          int level) {
   const uint64_t r = philox_word0(seed, 0, (uint64_t)i, (uint64_t)j, step, (uint64_t)level);
   return (double)(r >> 40) * 0x1p-24;
 }
 
-// Complete one search from its level-0 normaliser. The selection passes re-walk a
-// prefix of a list already walked by its sum pass and are not counted.
+// Levels >= 1 of a search: restart at the chosen cell S until a neuron is drawn.
 template <bool COUNT>
-__device__ int32_t finish_search(const SearchArgs& A, const NodeRec* R, const int32_t* vs,
-                                 int32_t i, int32_t j, int32_t li, double xi, double yi, double zi,
-                                 const SumPass& s0, int* levels_out, Count& cnt) {
-  int32_t S = 0;
-  SumPass s = s0;
+__device__ int32_t restart_search(const SearchArgs& A, const NodeRec* R, const int32_t* vs,
+                                  int32_t S, int32_t i, int32_t j, int32_t li, double xi,
+                                  double yi, double zi, int* levels_out, Count& cnt) {
   Count none;
-  for (int level = 0; level < kMaxLevels; ++level) {
-    if (level > 0) {
-      s = SumPass{A.inv_s2};
-      expand<COUNT>(A, R, vs, S, i, li, xi, yi, zi, s, cnt);
-    }
+  for (int level = 1; level < kMaxLevels; ++level) {
+    SumPass s{A.inv_s2};
+    expand<COUNT>(A, R, vs, S, i, li, xi, yi, zi, s, cnt);
     *levels_out = level + 1;
     if (!(s.Z > 0.0)) return -1;
     const double T = draw_u(A.seed, i, j, A.step, level) * s.Z;
@@ -218,6 +222,25 @@ __device__ int32_t finish_search(const SearchArgs& A, const NodeRec* R, const in
   }
   atomicOr(A.err, kErrArgs);
   return -1;
+}
+
+// Complete one search from its level-0 normaliser. The selection passes re-walk a
+// prefix of a list already walked by its sum pass and are not counted.
+template <bool COUNT>
+__device__ int32_t finish_search(const SearchArgs& A, const NodeRec* R, const int32_t* vs,
+                                 int32_t i, int32_t j, int32_t li, double xi, double yi, double zi,
+                                 const SumPass& s0, int* levels_out, Count& cnt) {
+  Count none;
+  *levels_out = 1;
+  if (!(s0.Z > 0.0)) return -1;
+  const double T = draw_u(A.seed, i, j, A.step, 0) * s0.Z;
+  SelectPass p{A.inv_s2, s0.s, T};
+  expand<false>(A, R, vs, 0, i, li, xi, yi, zi, p, none);
+  const int32_t id = p.chosen >= 0 ? p.chosen : p.last;
+  const bool neuron = p.chosen >= 0 ? p.chosen_neuron : p.last_neuron;
+  if (id < 0) return -1;
+  if (neuron) return id;
+  return restart_search<COUNT>(A, R, vs, id, i, j, li, xi, yi, zi, levels_out, cnt);
 }
 
 struct DiagOut {
@@ -235,6 +258,7 @@ __global__ void __launch_bounds__(256) search_simple_k(SearchArgs A, DiagOut D) 
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= *A.work_count) return;
   const int32_t i = A.work[w];
+  if (i < 0) return;                           // padding slot
   const int t = A.type[i] ? 1 : 0;
   const NodeRec* R = A.rec[t];
   const int32_t* vs = A.vs[t];
