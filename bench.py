@@ -61,6 +61,53 @@ def algorithmic_bytes(cnt, off):
     return int(lvl0 + rest), int(v0[first].sum() + (v - v0).sum())
 
 
+def sweep_bytes(cnt, off):
+    """Algorithmic bytes of the level-0 sweep kernel: every source's level-0 records
+    visited, nodes opened and the source record, once per source."""
+    v0 = cnt["visits0"].astype(np.int64)
+    o0 = cnt["opens0"].astype(np.int64)
+    first = off[:-1][np.diff(off) > 0]
+    return int((REC_BYTES * v0[first] + OPEN_BYTES * o0[first] + SRC_BYTES).sum())
+
+
+def kernel_sources_hash():
+    """Hash of the search kernel sources: measured HBM traffic is reported only for
+    the kernel version it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("search.hpp", "search_wave.hpp", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2509_26193_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per sweep launch from the committed rocprofv3 PMC summary, if it was
+    taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "search_sweep_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = d.get(workload)
+    if not e or e.get("kernel_sources") != kernel_sources_hash():
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def copy_calibration():
+    """A plain device copy of known size (1 GiB read + 1 GiB written per launch), run
+    under the same rocprofv3 counters to scale FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("copy calibration: 3 launches of a 1 GiB device-to-device copy")
+
+
 def cpu_baseline(w, gpu_target, sample, threads):
     from oracle import oracle as orc
     t0 = time.time()
@@ -97,12 +144,18 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=40000)
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the plain-copy kernel used to scale HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding of the search is a design note, not implemented)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import torch
     import paper_2509_26193_amd as msp
@@ -118,7 +171,7 @@ def main():
     va, ve, vi = va0.clone(), ve0.clone(), vi0.clone()
     tgt_buf = torch.empty(S, dtype=torch.int32, device=dev)
     off_buf = torch.empty(w.n + 1, dtype=torch.int64, device=dev)
-    times = {"build": [], "refresh": [], "search": [], "commit": [], "kernel": []}
+    times = {"build": [], "refresh": [], "search": [], "commit": [], "sweep": [], "draw": []}
 
     def step(record):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
@@ -141,7 +194,8 @@ def main():
             torch.cuda.synchronize()
             for k, (a, b) in zip(("build", "refresh", "search", "commit"), zip(ev[:-1], ev[1:])):
                 times[k].append(a.elapsed_time(b))
-            times["kernel"].append(tm["kernel_ms"])
+            times["sweep"].append(tm["sweep_ms"])
+            times["draw"].append(tm["draw_ms"])
         return res["n_formed"]
 
     for k in range(args.warmup):
@@ -152,7 +206,8 @@ def main():
     formed = 0
     for k in range(args.steps):
         formed = step(True)
-        log(f"timed step {k + 1}/{args.steps}: search kernel {times['kernel'][-1]:.2f} ms")
+        log(f"timed step {k + 1}/{args.steps}: sweep {times['sweep'][-1]:.2f} ms, "
+            f"draw {times['draw'][-1]:.2f} ms")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sec = (t1 - t0) / args.steps
@@ -169,14 +224,29 @@ def main():
     gpu_target = tgt.cpu().numpy().astype(np.int64)
     tree.free()
     B, visits = algorithmic_bytes(cnt_h, off_h)
-    kmean = float(np.mean(times["kernel"])) / 1e3
-    achieved = B / kmean
+    first = off_h[:-1][np.diff(off_h) > 0]
+    lane_steps = int((cnt_h["visits0"][first].astype(np.int64) - 1).sum())
+    wave_steps = int(cnt_h["wave_steps"][0])
+    union_eff = lane_steps / max(1, 64 * wave_steps)
+    Bs = sweep_bytes(cnt_h, off_h)
+    sweep_s = float(np.mean(times["sweep"])) / 1e3
+    draw_s = float(np.mean(times["draw"])) / 1e3
+    achieved = Bs / sweep_s
+    traffic = measured_traffic(w.name)
     roof = dict(bound="hbm", achieved=achieved / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
-                frac=achieved / HBM_PEAK, traffic=None,
-                kernel="search_sweep_k+search_draw_k", kernel_ms=kmean * 1e3,
-                algorithmic_bytes_per_launch=B, node_visits_per_launch=visits)
-    log(f"step {sec * 1e3:.1f} ms; search kernel {kmean * 1e3:.2f} ms; "
-        f"{achieved / 1e9:.1f} GB/s algorithmic ({roof['frac']:.3f} of HBM peak)")
+                frac=achieved / HBM_PEAK, traffic=traffic,
+                kernel="search_sweep_k", kernel_ms=sweep_s * 1e3,
+                algorithmic_bytes_per_launch=Bs,
+                search_total=dict(kernels="search_sweep_k+search_draw_k",
+                                  ms=(sweep_s + draw_s) * 1e3, algorithmic_bytes=B,
+                                  node_visits=visits,
+                                  achieved=B / (sweep_s + draw_s) / 1e9,
+                                  frac=B / (sweep_s + draw_s) / HBM_PEAK),
+                sweep_wave_steps=wave_steps, sweep_lane_visits=lane_steps,
+                sweep_lane_utilisation=union_eff)
+    log(f"step {sec * 1e3:.1f} ms; sweep {sweep_s * 1e3:.2f} ms ({achieved / 1e9:.0f} GB/s "
+        f"algorithmic, {roof['frac']:.3f} of HBM peak); draw {draw_s * 1e3:.2f} ms; "
+        f"{wave_steps} wave steps, lane utilisation {union_eff:.3f}")
 
     out = {
         "metric": "axon target searches/sec",
@@ -196,7 +266,7 @@ def main():
                    "step": "build_octree + update_vacant_counts + find_targets + commit_synapses",
                    "synapses_formed": formed},
         "breakdown_ms": {k: float(np.mean(v)) for k, v in times.items()},
-        "search_kernel_searches_per_s": S / kmean,
+        "search_kernels_searches_per_s": S / (sweep_s + draw_s),
         "roofline": roof,
     }
     if not args.no_cpu:

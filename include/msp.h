@@ -117,8 +117,13 @@ msp_status msp_find_targets(msp_octree t, const uint8_t* neuron_type, const int3
  *           children over all levels (the start node included);
  *   visits0, opens0 [S] int32: the level-0 part of visits / opens (the level-0 list
  *           of a source is shared by all of its elements);
- *   kernel_ms (host): duration of the search kernel, from HIP events recorded on `s`
- *           around it; when set, the call waits for the kernel to finish.
+ *   kernel_ms (host) [2]: durations in ms, from HIP events recorded on `s` around each
+ *           kernel: [0] the level-0 sweep, [1] the draws and restarts; when set, the
+ *           call waits for the kernels to finish.
+ *   wave_steps (device int64 scalar): incremented by the number of node steps of the
+ *           shared level-0 walks (one per 64-source wavefront tile); with visits0 it
+ *           gives the fraction of lanes doing useful work. Counted only when one of
+ *           the per-search arrays above is also requested.
  */
 typedef struct msp_search_diag {
   double* z0;
@@ -128,6 +133,7 @@ typedef struct msp_search_diag {
   int32_t* visits0;
   int32_t* opens0;
   float* kernel_ms;
+  int64_t* wave_steps;
 } msp_search_diag;
 
 /* msp_find_targets with diagnostics (diag may be null). */

@@ -39,7 +39,8 @@ _dbl = ctypes.c_double
 
 class SearchDiag(ctypes.Structure):
     _fields_ = [("z0", _vp), ("levels", _vp), ("visits", _vp), ("opens", _vp),
-                ("visits0", _vp), ("opens0", _vp), ("kernel_ms", ctypes.POINTER(ctypes.c_float))]
+                ("visits0", _vp), ("opens0", _vp), ("kernel_ms", ctypes.POINTER(ctypes.c_float)),
+                ("wave_steps", _vp)]
 
 
 _SIGS = {
@@ -201,8 +202,9 @@ def find_targets(tree: Octree, neuron_type: torch.Tensor, vac_axon: torch.Tensor
                  counters: bool = False, timing: dict | None = None, stream=None):
     """Returns (target[S], elem_offset[n+1]); with diag also (z0[S], levels[S]); with
     counters also a dict of visits/opens/visits0/opens0 [S]. target_out may be a
-    preallocated int32 buffer of any capacity >= S. If `timing` is a dict, the search
-    kernel's duration (HIP events on the launch stream) is stored under "kernel_ms"."""
+    preallocated int32 buffer of any capacity >= S. If `timing` is a dict, the kernel
+    durations (HIP events on the launch stream) are stored under "sweep_ms" (level-0
+    sweep), "draw_ms" (draws and restarts) and "kernel_ms" (both)."""
     n = tree.n
     dev = tree.device
     ty = _dev(neuron_type, torch.uint8, "neuron_type", n)
@@ -211,7 +213,7 @@ def find_targets(tree: Octree, neuron_type: torch.Tensor, vac_axon: torch.Tensor
         elem_offset_out = torch.empty(n + 1, dtype=torch.int64, device=dev)
     off = _dev(elem_offset_out, torch.int64, "elem_offset_out", n + 1)
     st = _stream(stream)
-    ms = ctypes.c_float(0.0)
+    ms = (ctypes.c_float * 2)(0.0, 0.0)
     extra = {}
     for attempt in range(2):
         cap = 0 if target_out is None else target_out.numel()
@@ -222,10 +224,11 @@ def find_targets(tree: Octree, neuron_type: torch.Tensor, vac_axon: torch.Tensor
         if counters:
             for k in ("visits", "opens", "visits0", "opens0"):
                 extra[k] = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+            extra["wave_steps"] = torch.zeros(1, dtype=torch.int64, device=dev)
         for k, v in extra.items():
             setattr(d, k, v.data_ptr())
         if timing is not None:
-            d.kernel_ms = ctypes.pointer(ms)
+            d.kernel_ms = ctypes.cast(ms, ctypes.POINTER(ctypes.c_float))
         tp = None if target_out is None else _dev(target_out, torch.int32, "target_out")
         rc = lib().msp_find_targets_diag(tree.handle, ty, a, float(sigma), float(theta), int(seed),
                                          int(step), tp, off, cap, ctypes.byref(d), st)
@@ -239,12 +242,16 @@ def find_targets(tree: Octree, neuron_type: torch.Tensor, vac_axon: torch.Tensor
     if target_out is None:
         target_out = torch.empty(0, dtype=torch.int32, device=dev)
     if timing is not None:
-        timing["kernel_ms"] = float(ms.value)
+        timing["sweep_ms"] = float(ms[0])
+        timing["draw_ms"] = float(ms[1])
+        timing["kernel_ms"] = float(ms[0]) + float(ms[1])
     out = [target_out[:S], elem_offset_out]
     if diag:
         out += [extra["z0"][:S], extra["levels"][:S]]
     if counters:
-        out.append({k: extra[k][:S] for k in ("visits", "opens", "visits0", "opens0")})
+        c = {k: extra[k][:S] for k in ("visits", "opens", "visits0", "opens0")}
+        c["wave_steps"] = extra["wave_steps"]
+        out.append(c)
     return tuple(out)
 
 

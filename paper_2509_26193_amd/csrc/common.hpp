@@ -65,7 +65,7 @@ struct msp_octree_s {
   int32_t* nend;         // [N]
   int32_t* level_nodes;  // [N] node ids grouped by depth
   int64_t level_off[msp::kMaxDepth + 2];
-  msp::NodeRec* rec[2];  // [N] per type
+  msp::NodeRec* rec[2];  // [N + 1] per type (index N: zero sentinel, never visited)
   int32_t* vs[2];        // [n] per type: counts in sorted order (bucket members)
   int32_t* err;          // [1] sticky device error flags
   bool refreshed;

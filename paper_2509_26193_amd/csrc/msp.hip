@@ -174,8 +174,10 @@ msp_status msp_build_octree(const double* pos, int64_t n, const double box_min[3
     TRY(dalloc(&t->nbeg, N));
     TRY(dalloc(&t->nend, N));
     TRY(dalloc(&t->level_nodes, N));
-    TRY(dalloc(&t->rec[0], N));
-    TRY(dalloc(&t->rec[1], N));
+    TRY(dalloc(&t->rec[0], N + 1));           // + a sentinel record at index N
+    TRY(dalloc(&t->rec[1], N + 1));
+    TRY(hipMemsetAsync(t->rec[0] + N, 0, sizeof(NodeRec), s));
+    TRY(hipMemsetAsync(t->rec[1] + N, 0, sizeof(NodeRec), s));
     TRY(lvl.alloc(sizeof(int32_t) * 2 * (kMaxDepth + 1)));
     int32_t* lcnt = lvl.as<int32_t>();
     TRY(hipMemsetAsync(lcnt, 0, sizeof(int32_t) * 2 * (kMaxDepth + 1), s));
@@ -319,7 +321,7 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
   A.err = t->err;
   A.L2 = t->box_edge * t->box_edge;
   A.theta2 = theta * theta;
-  A.inv_s2 = 1.0 / (sigma_um * sigma_um);
+  A.k2 = kLog2e / (sigma_um * sigma_um);
   A.seed = seed;
   A.step = step;
   DiagOut D{};
@@ -328,12 +330,10 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
     D = DiagOut{diag->z0, diag->levels, diag->visits, diag->opens, diag->visits0, diag->opens0};
     any = D.z0 || D.levels || D.visits || D.opens || D.visits0 || D.opens0;
   }
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   const bool timed = diag && diag->kernel_ms;
-  if (timed) {
-    MSP_HIP_TRY(hipEventCreate(&ev[0]));
-    MSP_HIP_TRY(hipEventCreate(&ev[1]));
-  }
+  if (timed)
+    for (auto& e : ev) MSP_HIP_TRY(hipEventCreate(&e));
   // the coherent sweep needs the exact tile count to size its checkpoint buffers
   int32_t ntiles = 0;
   if (!simple) {
@@ -360,19 +360,18 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
     const int64_t ns = nt * kWave;
     const int64_t nc = nt * kCkpt * kWave;
     const size_t bytes = sizeof(double) * (size_t)(ns + nc) +
-                         sizeof(int32_t) * (size_t)(3 * ns + nt + nt * kCkpt + 2 * nc);
+                         sizeof(int32_t) * (size_t)(2 * ns + nt + nt * kCkpt + nc);
     MSP_HIP_TRY(ck.alloc(bytes));
     W.Z = ck.as<double>();
     W.ck_P = W.Z + ns;
-    W.s = reinterpret_cast<int32_t*>(W.ck_P + nc);
-    W.v0 = W.s + ns;
+    W.v0 = reinterpret_cast<int32_t*>(W.ck_P + nc);
     W.o0 = W.v0 + ns;
     W.nck = W.o0 + ns;
     W.ck_x = W.nck + nt;
-    W.ck_s = W.ck_x + nt * kCkpt;
-    W.ck_me = W.ck_s + nc;
+    W.ck_me = W.ck_x + nt * kCkpt;
     W.tile_count = tiles;
     W.queue = queue;
+    W.wave_steps = diag ? reinterpret_cast<unsigned long long*>(diag->wave_steps) : nullptr;
   }
   if (timed) MSP_HIP_TRY(hipEventRecord(ev[0], s));
   if (simple) {
@@ -382,23 +381,27 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
       search_simple_k<false><<<grid_for(slots, 256), 256, 0, s>>>(A, D);
   } else if (ntiles > 0) {
     const unsigned draw_grid = grid_for((int64_t)ntiles * kWave, 256);
-    if (any) {
+    if (any)
       search_sweep_k<true><<<sweep_blocks, kWaveBlock, 0, s>>>(A, W);
-      search_draw_k<true><<<draw_grid, 256, 0, s>>>(A, D, W);
-    } else {
+    else
       search_sweep_k<false><<<sweep_blocks, kWaveBlock, 0, s>>>(A, W);
+    if (timed) MSP_HIP_TRY(hipEventRecord(ev[1], s));
+    if (any)
+      search_draw_k<true><<<draw_grid, 256, 0, s>>>(A, D, W);
+    else
       search_draw_k<false><<<draw_grid, 256, 0, s>>>(A, D, W);
-    }
   }
+  if (timed && (simple || ntiles == 0)) MSP_HIP_TRY(hipEventRecord(ev[1], s));
   hipError_t le = hipGetLastError();
   if (timed) {
-    float ms = 0.0f;
-    (void)hipEventRecord(ev[1], s);
-    (void)hipEventSynchronize(ev[1]);
-    (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
-    *diag->kernel_ms = ms;
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
+    float a = 0.0f, b = 0.0f;
+    (void)hipEventRecord(ev[2], s);
+    (void)hipEventSynchronize(ev[2]);
+    (void)hipEventElapsedTime(&a, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&b, ev[1], ev[2]);
+    diag->kernel_ms[0] = a;
+    diag->kernel_ms[1] = b;
+    for (auto& e : ev) (void)hipEventDestroy(e);
   }
   MSP_HIP_TRY(le);
   return MSP_OK;

@@ -9,8 +9,7 @@
 //     take the first entry whose running sum exceeds u * Z;
 //   * a neuron ends the search; a cell becomes the next start cell (restart).
 // Acceptance decisions are evaluated in float64 exactly as written (no contraction),
-// weight mantissas in float32 with an exact power-of-two shift so that no list
-// underflows, and running sums in float64.
+// weight mantissas in float32, weights and running sums in float64.
 #pragma once
 
 #include <math.h>
@@ -41,48 +40,40 @@ struct SearchArgs {
   int32_t* err;
   double L2;                     // box_edge * box_edge
   double theta2;                 // theta * theta
-  double inv_s2;                 // 1 / (sigma * sigma)
+  double k2;                     // log2(e) / (sigma * sigma)
   uint64_t seed, step;
 };
 
-// Kernel weights v * exp(-x), x = d^2 / sigma^2, with y = x log2(e) split as
-// y = fl + fr (fl integer, 0 <= fr < 1): mantissa 2^-fr in float32, then an exact
-// power-of-two scale 2^(s - fl) relative to a running shift s = min fl (so the
-// largest weight of a list is in (v/2, v]). Rescaling a partial sum when s drops
-// is exact, so the sum pass and the selection pass see identical weights and sums.
-__device__ __forceinline__ bool weight_parts(double d2, double inv_s2, double& mant, int& fl) {
-  const double x = d2 * inv_s2;
-  if (!(x <= kUnderflowX)) return false;        // exp(-x) is 0 in float64
-  const double y = x * kLog2e;
-  const double f = floor(y);
-  // y - f is in [0, 1): 2^-(y-f) is in (1/2, 1], a normal float32, so the bare
-  // hardware exp2 needs no range reduction
-  mant = (double)__builtin_amdgcn_exp2f(-(float)(y - f));
-  fl = (int)f;
-  return true;
+// Kernel weight v * exp(-x), x = d^2 / sigma^2, built in float64 from y = x log2(e):
+// y = fl + fr (fl integer, 0 <= fr < 1), weight = ldexp(v * 2^-fr, -fl), with the
+// mantissa 2^-fr from the float32 hardware exp2 (fr is in [0, 1), so 2^-fr is a
+// normal float in (1/2, 1] and needs no range reduction). The float64 exponent range
+// holds every weight the float64 definition does not flush to zero, so running sums
+// need no rescaling and the sum and selection passes add identical terms in the same
+// order (bitwise equal prefix sums).
+constexpr double kMaxY = kUnderflowX * kLog2e;   // exp(-x) == 0 in float64 beyond this
+
+__device__ __forceinline__ double kernel_weight(int32_t v, double d2, double k2) {
+  const double y = d2 * k2;
+  if (!(y <= kMaxY)) return 0.0;
+  const double fr = __builtin_amdgcn_fract(y);
+  const int fl = (int)y;                          // truncation = floor for y >= 0
+  const double mant = (double)__builtin_amdgcn_exp2f(-(float)fr);
+  return ldexp((double)v * mant, -fl);
 }
 
 struct SumPass {
-  double inv_s2;
+  double k2;                                      // log2(e) / sigma^2
   double Z = 0.0;
-  int s = 0x7FFFFFFF;                           // running shift (min fl)
   __device__ __forceinline__ bool operator()(int32_t, bool, int32_t v, double d2) {
-    double mant;
-    int fl;
-    if (!weight_parts(d2, inv_s2, mant, fl)) return false;
-    if (fl < s) {
-      Z = (s == 0x7FFFFFFF) ? 0.0 : ldexp(Z, fl - s);
-      s = fl;
-    }
-    Z = Z + ldexp((double)v * mant, s - fl);
+    Z = Z + kernel_weight(v, d2, k2);
     return false;
   }
 };
 
-// First entry whose running sum exceeds T (same weights as SumPass with its final s).
+// First entry whose running sum exceeds T (same weights, same order as SumPass).
 struct SelectPass {
-  double inv_s2;
-  int s;
+  double k2;
   double T;
   double P = 0.0;
   int32_t chosen = -1;
@@ -90,10 +81,7 @@ struct SelectPass {
   int32_t last = -1;
   bool last_neuron = false;
   __device__ __forceinline__ bool operator()(int32_t id, bool neuron, int32_t v, double d2) {
-    double mant;
-    int fl;
-    if (!weight_parts(d2, inv_s2, mant, fl)) return false;
-    const double w = ldexp((double)v * mant, s - fl);
+    const double w = kernel_weight(v, d2, k2);
     if (w > 0.0) {
       last = id;
       last_neuron = neuron;
@@ -207,12 +195,12 @@ __device__ int32_t restart_search(const SearchArgs& A, const NodeRec* R, const i
                                   double yi, double zi, int* levels_out, Count& cnt) {
   Count none;
   for (int level = 1; level < kMaxLevels; ++level) {
-    SumPass s{A.inv_s2};
+    SumPass s{A.k2};
     expand<COUNT>(A, R, vs, S, i, li, xi, yi, zi, s, cnt);
     *levels_out = level + 1;
     if (!(s.Z > 0.0)) return -1;
     const double T = draw_u(A.seed, i, j, A.step, level) * s.Z;
-    SelectPass p{A.inv_s2, s.s, T};
+    SelectPass p{A.k2, T};
     expand<false>(A, R, vs, S, i, li, xi, yi, zi, p, none);
     const int32_t id = p.chosen >= 0 ? p.chosen : p.last;
     const bool neuron = p.chosen >= 0 ? p.chosen_neuron : p.last_neuron;
@@ -234,7 +222,7 @@ __device__ int32_t finish_search(const SearchArgs& A, const NodeRec* R, const in
   *levels_out = 1;
   if (!(s0.Z > 0.0)) return -1;
   const double T = draw_u(A.seed, i, j, A.step, 0) * s0.Z;
-  SelectPass p{A.inv_s2, s0.s, T};
+  SelectPass p{A.k2, T};
   expand<false>(A, R, vs, 0, i, li, xi, yi, zi, p, none);
   const int32_t id = p.chosen >= 0 ? p.chosen : p.last;
   const bool neuron = p.chosen >= 0 ? p.chosen_neuron : p.last_neuron;
@@ -267,10 +255,10 @@ __global__ void __launch_bounds__(256) search_simple_k(SearchArgs A, DiagOut D) 
   const double xi = A.pos[3 * (int64_t)i], yi = A.pos[3 * (int64_t)i + 1],
                zi = A.pos[3 * (int64_t)i + 2];
   const int64_t off = A.elem_off[i];
-  SumPass s0{A.inv_s2};
+  SumPass s0{A.k2};
   Count c0;
   expand<DIAG>(A, R, vs, 0, i, li, xi, yi, zi, s0, c0);
-  const double z0 = s0.Z > 0.0 ? ldexp(s0.Z, -s0.s) : 0.0;
+  const double z0 = s0.Z;
   for (int32_t j = 0; j < a; ++j) {
     int lev = 0;
     Count c = c0;

@@ -22,24 +22,22 @@
 
 namespace msp {
 
-constexpr int kCkpt = 32;          // checkpoint slots per tile
-constexpr int kCkptStep0 = 32;     // initial checkpoint interval, wave steps
+constexpr int kCkpt = 64;          // checkpoint slots per tile
+constexpr int kCkptStepMin = 16;   // smallest checkpoint interval, wave steps
 constexpr int kWaveBlock = 256;    // 4 independent waves per block
 constexpr int kXcd = 8;            // accelerator dies; workgroup b runs on die b % 8
-constexpr int32_t kNoShift = 0x7FFFFFFF;
 
 struct SweepOut {
-  double* Z;                       // [slots] level-0 sum at shift s
-  int32_t* s;                      // [slots]
+  double* Z;                       // [slots] level-0 sum
   int32_t* v0;                     // [slots] level-0 visits (counting launches only)
   int32_t* o0;                     // [slots] level-0 opens
   int32_t* nck;                    // [tiles] checkpoints written
   int32_t* ck_x;                   // [tiles][kCkpt] wave position
   double* ck_P;                    // [tiles][kCkpt][64] running sum
-  int32_t* ck_s;                   // [tiles][kCkpt][64] shift of the running sum
   int32_t* ck_me;                  // [tiles][kCkpt][64] mask_end
   const int32_t* tile_count;       // device scalar
   int32_t* queue;                  // [kXcd] tile counters, zero at launch
+  unsigned long long* wave_steps;  // counting launches: total wave steps (nullable)
 };
 
 // Read-only data seen through the constant address space: wave-uniform loads from
@@ -62,9 +60,12 @@ __device__ __forceinline__ NodeRec load_rec(cptr<NodeRec> R, int64_t x) {
   return r;
 }
 
+// `step0`: initial checkpoint interval (a power of two), chosen from the length of
+// the wave's previous sweep so that the buffer rarely has to be thinned out.
+// Returns the number of wave steps of this tile.
 template <bool DIAG>
-__device__ __forceinline__ void sweep_tile(const SearchArgs& A, const SweepOut& W, int tile,
-                                           int lane) {
+__device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W, int tile,
+                                          int lane, int step0) {
   const int64_t slot = (int64_t)tile * kWave + lane;
   const int32_t i = A.work[slot];                                // -1: padding lane
   const bool valid = i >= 0;
@@ -79,9 +80,14 @@ __device__ __forceinline__ void sweep_tile(const SearchArgs& A, const SweepOut& 
     yi = A.pos[3 * (int64_t)i + 1];
     zi = A.pos[3 * (int64_t)i + 2];
   }
-  SumPass sum{A.inv_s2};
+  // complete the source loads before the walk: inside it, checkpoint stores share
+  // the vector-memory counter and would otherwise make every use of the source
+  // coordinates wait for them
+  __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0)
+  SumPass sum{A.k2};
   Count c0;
   int nck = 0;
+  int steps = 0;
   const NodeRec root = load_rec(R, 0);
   if (root.meta & kLeafBit) {
     // a one-neuron tree: the only neuron is the source itself, so the list is empty
@@ -90,7 +96,6 @@ __device__ __forceinline__ void sweep_tile(const SearchArgs& A, const SweepOut& 
     const int32_t end = (int32_t)(root.meta & kSkipMask);
     int32_t* ckx = W.ck_x + (int64_t)tile * kCkpt;
     double* ckP = W.ck_P + (int64_t)tile * kCkpt * kWave + lane;
-    int32_t* cks = W.ck_s + (int64_t)tile * kCkpt * kWave + lane;
     int32_t* ckme = W.ck_me + (int64_t)tile * kCkpt * kWave + lane;
     if (DIAG && valid) {
       c0.visits = 1;
@@ -98,33 +103,39 @@ __device__ __forceinline__ void sweep_tile(const SearchArgs& A, const SweepOut& 
     }
     int32_t x = 1;
     int32_t me = valid ? 0 : 0x7FFFFFFF;     // padding lanes are never active
-    int steps = 0, imask = kCkptStep0 - 1;   // checkpoint interval - 1 (a power of 2)
+    int imask = __builtin_amdgcn_readfirstlane(step0 - 1);   // interval - 1 (power of 2)
+    NodeRec cur = load_rec(R, x);
     while (x < end) {
       if ((steps & imask) == 0) {
         if (nck == kCkpt) {                   // full: keep every other checkpoint
 #pragma unroll 1
           for (int k = 1; k < kCkpt / 2; ++k) {
             ckP[k * kWave] = ckP[2 * k * kWave];
-            cks[k * kWave] = cks[2 * k * kWave];
             ckme[k * kWave] = ckme[2 * k * kWave];
             if (lane == 0) ckx[k] = ckx[2 * k];
           }
           nck = kCkpt / 2;
-          imask = 2 * imask + 1;
+          imask = __builtin_amdgcn_readfirstlane(2 * imask + 1);
         }
         if ((steps & imask) == 0) {
           ckP[nck * kWave] = sum.Z;
-          cks[nck * kWave] = sum.s;
           ckme[nck * kWave] = me;
           if (lane == 0) ckx[nck] = x;
-          ++nck;
+          nck = __builtin_amdgcn_readfirstlane(nck + 1);
         }
       }
       ++steps;
-      const NodeRec cur = load_rec(R, x);
+      // scalar loads may complete out of order, so the compiler can only wait for
+      // "all of them": wait for this node's record here, before the next ones are
+      // requested, so the wait below them is already satisfied
+      __builtin_amdgcn_s_waitcnt(0xC07F);    // lgkmcnt(0)
       const bool active = x >= me;
       if (DIAG && active) c0.visits += 1;
       const uint32_t meta = cur.meta;
+      // the next node is x + 1 (descend, or a leaf's successor) or the subtree end:
+      // fetch both now so the loads overlap this node's arithmetic (the record array
+      // ends with a sentinel, so both indices, at most N, are in bounds)
+      const NodeRec nx = load_rec(R, x + 1);
       if (meta & kLeafBit) {
         if (cur.v != 0) {
           if (!(meta & kBucketBit)) {
@@ -145,12 +156,16 @@ __device__ __forceinline__ void sweep_tile(const SearchArgs& A, const SweepOut& 
           }
         }
         x = x + 1;
+        cur = nx;
         continue;
       }
       int32_t sk = (int32_t)(meta & kSkipMask);
       sk = sk > x ? sk : x + 1;
+      sk = sk < end ? sk : end;
+      const NodeRec ns = load_rec(R, sk);
       if (cur.v == 0) {
         x = sk;
+        cur = ns;
         continue;
       }
       const bool contains = li >= x && li < sk;
@@ -163,16 +178,23 @@ __device__ __forceinline__ void sweep_tile(const SearchArgs& A, const SweepOut& 
         me = sk;
       }
       if (DIAG && open) c0.opens += 1;
-      x = __any(open) ? x + 1 : sk;
+      if (__any(open)) {
+        x = x + 1;
+        cur = nx;
+      } else {
+        x = sk;
+        cur = ns;
+      }
     }
   }
   if (lane == 0) W.nck[tile] = nck;
   W.Z[slot] = sum.Z;
-  W.s[slot] = sum.s;
   if (DIAG) {
     W.v0[slot] = c0.visits;
     W.o0[slot] = c0.opens;
+    if (W.wave_steps && lane == 0) atomicAdd(W.wave_steps, (unsigned long long)steps);
   }
+  return steps;
 }
 
 // Persistent waves pull 64-source tiles: first from the Morton range of their own
@@ -184,6 +206,7 @@ __global__ void __launch_bounds__(kWaveBlock) search_sweep_k(SearchArgs A, Sweep
   const int home = blockIdx.x % kXcd;
   const int ntiles = *W.tile_count;
   int q = 0;
+  int step0 = 2 * kCkptStepMin;
   while (q < kXcd) {
     const int qq = (home + q) % kXcd;
     const int lo = (int)((int64_t)ntiles * qq / kXcd);
@@ -195,7 +218,10 @@ __global__ void __launch_bounds__(kWaveBlock) search_sweep_k(SearchArgs A, Sweep
       ++q;
       continue;
     }
-    sweep_tile<DIAG>(A, W, lo + got, lane);
+    const int steps = sweep_tile<DIAG>(A, W, lo + got, lane, step0);
+    // next interval: about kCkpt checkpoints over a sweep as long as this one
+    step0 = kCkptStepMin;
+    while (step0 * kCkpt < steps) step0 <<= 1;
   }
 }
 
@@ -215,17 +241,14 @@ __global__ void __launch_bounds__(256) search_draw_k(SearchArgs A, DiagOut D, Sw
   const double xi = A.pos[3 * (int64_t)i], yi = A.pos[3 * (int64_t)i + 1],
                zi = A.pos[3 * (int64_t)i + 2];
   const double Z = W.Z[slot];
-  const int32_t s = W.s[slot];
   const int nck = W.nck[tile];
   const NodeRec root = R[0];             // Z > 0 implies an inner root
   const int32_t end = (int32_t)(root.meta & kSkipMask);
   const int32_t* ckx = W.ck_x + tile * kCkpt;
   const double* ckP = W.ck_P + tile * kCkpt * kWave + lane;
-  const int32_t* cks = W.ck_s + tile * kCkpt * kWave + lane;
   const int32_t* ckme = W.ck_me + tile * kCkpt * kWave + lane;
   const int32_t a = A.vac_axon[i];
   const int64_t off = A.elem_off[i];
-  const double z0 = Z > 0.0 ? ldexp(Z, -s) : 0.0;
   Count c0;
   if (DIAG) {
     c0.visits = W.v0[slot];
@@ -237,25 +260,20 @@ __global__ void __launch_bounds__(256) search_draw_k(SearchArgs A, DiagOut D, Sw
     int32_t tgt = -1;
     if (Z > 0.0) {
       const double T = draw_u(A.seed, i, j, A.step, 0) * Z;
-      SelectPass p{A.inv_s2, s, T};
+      SelectPass p{A.k2, T};
       Count none;
-      {
-        // last checkpoint whose running sum (at the final shift) does not exceed T
-        int lo = 0, hi = nck - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          const int32_t sm = cks[mid * kWave];
-          const double pm = sm == kNoShift ? 0.0 : ldexp(ckP[mid * kWave], s - sm);
-          if (pm <= T) lo = mid; else hi = mid - 1;
-        }
-        const int32_t sl = cks[lo * kWave];
-        p.P = sl == kNoShift ? 0.0 : ldexp(ckP[lo * kWave], s - sl);
-        const int32_t cx = ckx[lo], cm = ckme[lo * kWave];
-        expand_range<false>(A, R, vs, cx > cm ? cx : cm, end, i, li, xi, yi, zi, p, none);
-        if (p.chosen < 0) {                       // not crossed (rounding): full walk
-          p = SelectPass{A.inv_s2, s, T};
-          expand_range<false>(A, R, vs, 1, end, i, li, xi, yi, zi, p, none);
-        }
+      // last checkpoint whose running sum does not exceed T (checkpoint 0 holds 0)
+      int lo = 0, hi = nck - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ckP[mid * kWave] <= T) lo = mid; else hi = mid - 1;
+      }
+      p.P = ckP[lo * kWave];
+      const int32_t cx = ckx[lo], cm = ckme[lo * kWave];
+      expand_range<false>(A, R, vs, cx > cm ? cx : cm, end, i, li, xi, yi, zi, p, none);
+      if (p.chosen < 0) {                       // not crossed (rounding): full walk
+        p = SelectPass{A.k2, T};
+        expand_range<false>(A, R, vs, 1, end, i, li, xi, yi, zi, p, none);
       }
       const int32_t id = p.chosen >= 0 ? p.chosen : p.last;
       const bool neuron = p.chosen >= 0 ? p.chosen_neuron : p.last_neuron;
@@ -264,7 +282,7 @@ __global__ void __launch_bounds__(256) search_draw_k(SearchArgs A, DiagOut D, Sw
     }
     A.target[off + j] = tgt;
     if (DIAG) {
-      if (D.z0) D.z0[off + j] = z0;
+      if (D.z0) D.z0[off + j] = Z;
       if (D.levels) D.levels[off + j] = lev;
       if (D.visits) D.visits[off + j] = c.visits;
       if (D.opens) D.opens[off + j] = c.opens;
