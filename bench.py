@@ -134,6 +134,89 @@ def cpu_baseline(w, gpu_target, sample, threads):
                 parity=dict(sampled=m, differing=differ, outside_window=outside))
 
 
+def bench_plain_update(msp, torch, w, steps, warmup):
+    """Whole-update throughput (build + refresh + search + commit) of one workload."""
+    dev = torch.device("cuda:0")
+    T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    pos = T(w.pos, torch.float64)
+    ty = T(w.neuron_type, torch.uint8)
+    va0, ve0, vi0 = T(w.vac_axon, torch.int32), T(w.vac_exc, torch.int32), T(w.vac_inh, torch.int32)
+    va, ve, vi = va0.clone(), ve0.clone(), vi0.clone()
+    S = w.searches
+    tgt_buf = torch.empty(max(S, 1), dtype=torch.int32, device=dev)
+    kern = []
+
+    def step():
+        tree = msp.build_octree(pos, w.box_min, w.box_edge)
+        va.copy_(va0); ve.copy_(ve0); vi.copy_(vi0)
+        msp.update_vacant_counts(tree, ve, vi)
+        tm = {}
+        tgt, off = msp.find_targets(tree, ty, va, w.sigma, w.theta, w.seed, w.step,
+                                    target_out=tgt_buf, timing=tm)
+        msp.commit_synapses(tgt, off, ty, va, ve, vi, w.seed, w.step, syn_capacity=S)
+        tree.free()
+        kern.append(tm["kernel_ms"])
+
+    for _ in range(warmup):
+        step()
+    kern.clear()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    return dict(workload=w.name, neurons=w.n, searches=S, theta=w.theta, ms_per_update=sec * 1e3,
+                searches_per_s=S / sec, search_kernels_ms=float(np.mean(kern)))
+
+
+def bench_batched(msp, torch, reps=5):
+    """64 simulations of 2^12..2^18 neurons: one batched launch (HIP graph) against 64
+    per-simulation find_targets calls, same stream, same results (checked)."""
+    from synth_inputs import config_batched
+    dev = torch.device("cuda:0")
+    T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    ws = config_batched()
+    sims = []
+    for k, w in enumerate(ws):
+        tree = msp.build_octree(T(w.pos, torch.float64), w.box_min, w.box_edge)
+        msp.update_vacant_counts(tree, T(w.vac_exc, torch.int32), T(w.vac_inh, torch.int32))
+        sims.append(dict(tree=tree, neuron_type=T(w.neuron_type, torch.uint8),
+                         vac_axon=T(w.vac_axon, torch.int32), sigma=w.sigma, seed=w.seed + k))
+    S = sum(w.searches for w in ws)
+    log(f"batched: {len(ws)} simulations, {sum(w.n for w in ws)} neurons, {S} searches")
+    b = msp.Batch(sims, graph=True, autotune=True)
+    b.run(0.3, 0)                       # tunes, captures
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(reps):
+        b.run(0.3, r)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    assert b.status() == [0] * len(ws)
+    bt = [b.results(k)[0].cpu().numpy().copy() for k in range(len(ws))]
+    bufs = [torch.empty(max(w.searches, 1), dtype=torch.int32, device=dev) for w in ws]
+    for d, buf in zip(sims, bufs):     # warm-up of the per-simulation path
+        msp.find_targets(d["tree"], d["neuron_type"], d["vac_axon"], d["sigma"], 0.3, d["seed"],
+                         reps - 1, target_out=buf)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(reps):
+        outs = [msp.find_targets(d["tree"], d["neuron_type"], d["vac_axon"], d["sigma"], 0.3,
+                                 d["seed"], r, target_out=buf)[0] for d, buf in zip(sims, bufs)]
+    torch.cuda.synchronize()
+    tp = (time.perf_counter() - t0) / reps
+    same = all(np.array_equal(o.cpu().numpy(), x) for o, x in zip(outs, bt))
+    b.free()
+    for d in sims:
+        d["tree"].free()
+    return dict(workload=f"batched_{len(ws)}_simulations", simulations=len(ws),
+                neurons=int(sum(w.n for w in ws)), searches=int(S),
+                batched_ms=tb * 1e3, batched_searches_per_s=S / tb,
+                per_simulation_ms=tp * 1e3, per_simulation_searches_per_s=S / tp,
+                speedup=tp / tb, identical_targets=bool(same))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +229,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain-copy kernel used to scale HBM counters")
+    ap.add_argument("--no-also", action="store_true",
+                    help="skip the 2^20-neuron and batched measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -269,6 +354,16 @@ def main():
         "search_kernels_searches_per_s": S / (sweep_s + draw_s),
         "roofline": roof,
     }
+    if not args.no_also:
+        from synth_inputs import config_clusters
+        also = {}
+        wc = config_clusters(theta=0.3)
+        log(f"also: {wc.name}")
+        also["plain_1M_clusters"] = bench_plain_update(msp, torch, wc, steps=5, warmup=1)
+        del wc
+        log("also: batched")
+        also["batched"] = bench_batched(msp, torch)
+        out["also"] = also
     if not args.no_cpu:
         threads = args.cpu_threads or min(os.cpu_count() or 1, 64)
         out["cpu_baseline"] = cpu_baseline(w, gpu_target, args.cpu_sample, threads)

@@ -144,6 +144,56 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
                                  const msp_search_diag* diag, hipStream_t s);
 
 /*
+ * Batched search: many independent simulations (each with its own octree, built and
+ * refreshed as above, and its own sources, kernel width, seed and outputs) searched
+ * by one set of launches. Per simulation the result is bitwise equal to
+ * msp_find_targets with the same arguments. Intended for ensembles of simulations
+ * too small to fill the GPU one at a time.
+ *
+ * A plan fixes the simulations' octrees (their sizes determine its scratch, which
+ * the plan owns: a run allocates nothing and does not synchronise with the host).
+ * Each run may pass new buffers, kernel widths and seeds for the same octrees.
+ */
+typedef struct msp_sim {
+  msp_octree tree;
+  const uint8_t* neuron_type;   /* [n] device */
+  const int32_t* vac_axon;      /* [n] device */
+  double sigma_um;              /* > 0 */
+  uint64_t seed;                /* Philox key word 0 of this simulation's draws */
+  int32_t* target_out;          /* [capacity_S] device */
+  int64_t* elem_offset_out;     /* [n + 1] device */
+  int64_t capacity_S;
+} msp_sim;
+
+typedef struct msp_batch_s* msp_batch;
+
+#define MSP_BATCH_GRAPH    1    /* capture the launches in a HIP graph on the first run,
+                                   replay it afterwards */
+#define MSP_BATCH_AUTOTUNE 2    /* on the first run, time several launch shapes (sweep
+                                   occupancy, draw block size) and keep the fastest */
+
+/* Create a plan over n_sims >= 1 simulations on the current device (host array sims,
+ * copied). Errors: MSP_ERR_INVALID (bad handle, unrefreshed octree, bad sigma,
+ * n_sims < 1), MSP_ERR_OOM. */
+msp_status msp_batch_create(const msp_sim* sims, int32_t n_sims, int32_t flags, msp_batch* out);
+
+/* Run the batched search on stream s with a shared theta and step. `sims` (host,
+ * nullable = reuse the previous run's) must name the plan's octrees in the same order.
+ * Asynchronous: per-simulation errors (capacity exceeded, negative vac_axon, type > 1)
+ * are reported by msp_batch_status; such a simulation's target_out is not written, its
+ * elem_offset_out is. */
+msp_status msp_find_targets_batched(msp_batch b, const msp_sim* sims, double theta,
+                                    uint64_t step, hipStream_t s);
+
+/* Wait for the last run on stream s and copy the per-simulation status to status_out
+ * (host [n_sims]; MSP_OK, MSP_ERR_CAPACITY or MSP_ERR_INVALID each). Returns MSP_OK if
+ * every simulation succeeded, else the first failing status. */
+msp_status msp_batch_status(msp_batch b, hipStream_t s, int32_t* status_out);
+
+/* Release the plan (waits for the device). */
+void msp_batch_free(msp_batch b);
+
+/*
  * Accept or decline every request (Sec. III-A, "Update of synapses"; Sec. III-B:
  * requests are exchanged, accepted locally and answered yes/no).
  *   target [S], elem_offset [n+1]: as produced by msp_find_targets.

@@ -43,6 +43,12 @@ class SearchDiag(ctypes.Structure):
                 ("wave_steps", _vp)]
 
 
+class SimSpec(ctypes.Structure):
+    _fields_ = [("tree", _vp), ("neuron_type", _vp), ("vac_axon", _vp), ("sigma_um", _dbl),
+                ("seed", _u64), ("target_out", _vp), ("elem_offset_out", _vp),
+                ("capacity_S", _i64)]
+
+
 _SIGS = {
     "msp_status_string": (ctypes.c_char_p, [_i32]),
     "msp_sync": (_i32, [_vp]),
@@ -60,7 +66,14 @@ _SIGS = {
     "msp_octree_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "msp_octree_export_topology": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "msp_octree_export_aggregates": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "msp_batch_create": (_i32, [ctypes.POINTER(SimSpec), _i32, _i32, ctypes.POINTER(_vp)]),
+    "msp_find_targets_batched": (_i32, [_vp, ctypes.POINTER(SimSpec), _dbl, _u64, _vp]),
+    "msp_batch_status": (_i32, [_vp, _vp, ctypes.POINTER(_i32)]),
+    "msp_batch_free": (None, [_vp]),
 }
+
+MSP_BATCH_GRAPH = 1
+MSP_BATCH_AUTOTUNE = 2
 
 _lib = None
 
@@ -289,3 +302,74 @@ def commit_synapses(target: torch.Tensor, elem_offset: torch.Tensor, neuron_type
 
 def sync(stream=None) -> None:
     _check(lib().msp_sync(_stream(stream)), "sync")
+
+
+class Batch:
+    """A plan for searching many independent simulations with one set of launches.
+
+    sims: list of dicts with keys tree (Octree), neuron_type (uint8), vac_axon (int32),
+    sigma (float), seed (int), and optionally target_out (int32, capacity >= searches)
+    and elem_offset_out (int64, n + 1). Missing outputs are allocated from the
+    searches implied by vac_axon. Per simulation the targets equal find_targets'."""
+
+    def __init__(self, sims, graph: bool = False, autotune: bool = False):
+        self._h = None
+        self.n_sims = len(sims)
+        self.sims = [dict(s) for s in sims]
+        for d in self.sims:
+            n = d["tree"].n
+            dev = d["tree"].device
+            if d.get("elem_offset_out") is None:
+                d["elem_offset_out"] = torch.empty(n + 1, dtype=torch.int64, device=dev)
+            if d.get("target_out") is None:
+                S = int(torch.clamp(d["vac_axon"], min=0).sum().item())
+                d["target_out"] = torch.empty(max(S, 1), dtype=torch.int32, device=dev)
+        arr = self._specs()
+        flags = (MSP_BATCH_GRAPH if graph else 0) | (MSP_BATCH_AUTOTUNE if autotune else 0)
+        h = _vp()
+        _check(lib().msp_batch_create(arr, self.n_sims, flags, ctypes.byref(h)), "batch_create")
+        self._h = h.value
+
+    def _specs(self):
+        arr = (SimSpec * self.n_sims)()
+        for k, d in enumerate(self.sims):
+            n = d["tree"].n
+            arr[k].tree = d["tree"].handle
+            arr[k].neuron_type = _dev(d["neuron_type"], torch.uint8, "neuron_type", n)
+            arr[k].vac_axon = _dev(d["vac_axon"], torch.int32, "vac_axon", n)
+            arr[k].sigma_um = float(d["sigma"])
+            arr[k].seed = int(d["seed"])
+            arr[k].target_out = _dev(d["target_out"], torch.int32, "target_out")
+            arr[k].elem_offset_out = _dev(d["elem_offset_out"], torch.int64, "elem_offset_out", n + 1)
+            arr[k].capacity_S = d["target_out"].numel()
+        return arr
+
+    def run(self, theta: float, step: int, update: bool = False, stream=None) -> None:
+        """Queue one batched search (asynchronous). With update=True the current
+        buffers and parameters in self.sims are re-sent."""
+        arr = self._specs() if update else None
+        _check(lib().msp_find_targets_batched(self._h, arr, float(theta), int(step),
+                                              _stream(stream)), "find_targets_batched")
+
+    def status(self, stream=None) -> list:
+        st = (_i32 * self.n_sims)()
+        lib().msp_batch_status(self._h, _stream(stream), st)
+        return [int(x) for x in st]
+
+    def results(self, k: int):
+        """(target[S], elem_offset[n+1]) of simulation k after a run."""
+        d = self.sims[k]
+        off = d["elem_offset_out"]
+        S = int(off[-1].item())
+        return d["target_out"][:S], off
+
+    def free(self) -> None:
+        if self._h:
+            lib().msp_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

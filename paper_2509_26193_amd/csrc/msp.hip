@@ -3,6 +3,7 @@
 #include <cstring>
 #include <cstdlib>
 #include <new>
+#include <vector>
 
 #include "common.hpp"
 #include "scan.hpp"
@@ -10,6 +11,7 @@
 #include "refresh.hpp"
 #include "search.hpp"
 #include "search_wave.hpp"
+#include "batch.hpp"
 #include "commit.hpp"
 
 using namespace msp;
@@ -35,55 +37,57 @@ void release(msp_octree_s* t) {
   delete t;
 }
 
-struct CountPos {
-  __device__ int64_t operator()(int32_t a, int64_t) const { return a > 0 ? (int64_t)a : 0; }
-};
-
-struct SrcFlag {
-  const int32_t* a;
-  const uint8_t* ty;
-  uint8_t want;
-  __device__ int32_t operator()(int32_t id, int64_t) const {
-    return (a[id] > 0 && (ty[id] ? 1 : 0) == want) ? 1 : 0;
-  }
-};
-
 struct AccFlag {
   __device__ int64_t operator()(uint8_t a, int64_t) const { return (int64_t)a; }
 };
 
-__global__ void check_axon_k(const int32_t* __restrict__ a, const uint8_t* __restrict__ ty,
-                             int64_t n, int32_t* flag) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (a[i] < 0 || ty[i] > 1) atomicOr(flag, 1);
+// Fill the device descriptor of one simulation.
+SimDesc make_desc(const msp_octree_s* t, const uint8_t* neuron_type, const int32_t* vac_axon,
+                  double sigma_um, double theta, uint64_t seed, uint64_t step, int32_t* target_out,
+                  int64_t* elem_offset_out, int64_t capacity_S) {
+  SimDesc d{};
+  d.rec[0] = t->rec[0];
+  d.rec[1] = t->rec[1];
+  d.vs[0] = t->vs[0];
+  d.vs[1] = t->vs[1];
+  d.pos = t->pos;
+  d.order = t->order;
+  d.nbeg = t->nbeg;
+  d.nend = t->nend;
+  d.leaf_of = t->leaf_of;
+  d.err = t->err;
+  d.type = neuron_type;
+  d.vac_axon = vac_axon;
+  d.elem_off = elem_offset_out;
+  d.target = target_out;
+  d.capacity = target_out ? capacity_S : 0;
+  d.n = t->n;
+  d.L2 = t->box_edge * t->box_edge;
+  d.theta2 = theta * theta;
+  d.k2 = kLog2e / (sigma_um * sigma_um);
+  d.seed = seed;
+  d.step = step;
+  return d;
 }
 
-// Sources with a_i > 0 in Morton order: excitatory ones first, then inhibitory ones
-// from the next multiple of 64, so that no 64-source tile mixes the two types.
-// Unused slots hold -1. count[0] = number of tiles.
-__global__ void worklist_k(const int32_t* __restrict__ order, const int32_t* __restrict__ a,
-                           const uint8_t* __restrict__ ty, int64_t n,
-                           const int32_t* __restrict__ p0, const int32_t* __restrict__ p1,
-                           int32_t* __restrict__ work, int32_t* __restrict__ count) {
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t base1 = (p0[n] + kWave - 1) / kWave * kWave;
-  if (m == 0) *count = (base1 + (p1[n] + kWave - 1) / kWave * kWave) / kWave;
-  if (m >= n) return;
-  const int32_t id = order[m];
-  if (a[id] <= 0) return;
-  if (ty[id]) work[base1 + p1[m]] = id;
-  else work[p0[m]] = id;
-}
-
-// One thread per worklist slot (the first, per-source kernel).
-__global__ void tiles_to_slots_k(const int32_t* __restrict__ tiles, int32_t* __restrict__ slots) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *slots = *tiles * kWave;
-}
-
-bool use_simple_kernel() {
-  const char* e = getenv("MSP_SEARCH_KERNEL");
-  return e && std::strcmp(e, "simple") == 0;
+// Persistent sweep blocks: occupancy x CUs (times `frac` in [0, 1]), at most one
+// wave per tile.
+hipError_t sweep_blocks_for(int device, bool diag, int64_t max_tiles, double frac,
+                            unsigned* blocks_out) {
+  int ncu = 0, per_cu = 0;
+  hipError_t e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, diag ? (const void*)search_sweep_k<true> : (const void*)search_sweep_k<false>,
+      kWaveBlock, 0);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) per_cu = 1;
+  int64_t blocks = (int64_t)((double)ncu * per_cu * frac);
+  const int64_t need = (max_tiles + (kWaveBlock / kWave) - 1) / (kWaveBlock / kWave);
+  if (blocks > need) blocks = need;
+  if (blocks < 1) blocks = 1;
+  *blocks_out = (unsigned)blocks;
+  return hipSuccess;
 }
 
 }  // namespace
@@ -267,132 +271,47 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
     return MSP_ERR_INVALID;
   if (capacity_S < 0) return MSP_ERR_INVALID;
   const int64_t n = t->n;
-  Temp flag(s), p0(s), p1(s), work(s), ck(s);
-  MSP_HIP_TRY(flag.alloc(sizeof(int32_t) * (4 + kXcd)));
-  MSP_HIP_TRY(hipMemsetAsync(flag.p, 0, sizeof(int32_t) * (4 + kXcd), s));
-  check_axon_k<<<grid_for(n, 256), 256, 0, s>>>(vac_axon, neuron_type, n, flag.as<int32_t>());
-  MSP_HIP_TRY(hipGetLastError());
-  MSP_HIP_TRY((exclusive_scan<int64_t, int32_t, CountPos>(vac_axon, elem_offset_out, n, CountPos(),
-                                                          true, s)));
-  int64_t S = 0;
-  int32_t bad = 0;
-  MSP_HIP_TRY(hipMemcpyAsync(&S, elem_offset_out + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  MSP_HIP_TRY(hipMemcpyAsync(&bad, flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  MSP_HIP_TRY(hipStreamSynchronize(s));
-  if (bad) return MSP_ERR_INVALID;
-  if (S > capacity_S) return MSP_ERR_CAPACITY;
-  if (S == 0) return MSP_OK;
-  if (!target_out) return MSP_ERR_INVALID;
 
-  MSP_HIP_TRY(p0.alloc(sizeof(int32_t) * (n + 1)));
-  MSP_HIP_TRY(p1.alloc(sizeof(int32_t) * (n + 1)));
-  const int64_t slots = n + 2 * kWave;
-  MSP_HIP_TRY(work.alloc(sizeof(int32_t) * slots));
-  MSP_HIP_TRY(hipMemsetAsync(work.p, 0xFF, sizeof(int32_t) * slots, s));
-  MSP_HIP_TRY((exclusive_scan<int32_t, int32_t, SrcFlag>(t->order, p0.as<int32_t>(), n,
-                                                         SrcFlag{vac_axon, neuron_type, 0}, true, s)));
-  MSP_HIP_TRY((exclusive_scan<int32_t, int32_t, SrcFlag>(t->order, p1.as<int32_t>(), n,
-                                                         SrcFlag{vac_axon, neuron_type, 1}, true, s)));
-  int32_t* tiles = flag.as<int32_t>() + 1;
-  int32_t* nslots = flag.as<int32_t>() + 2;
-  int32_t* queue = flag.as<int32_t>() + 4;
-  worklist_k<<<grid_for(n, 256), 256, 0, s>>>(t->order, vac_axon, neuron_type, n,
-                                              p0.as<int32_t>(), p1.as<int32_t>(),
-                                              work.as<int32_t>(), tiles);
-  MSP_HIP_TRY(hipGetLastError());
-  const bool simple = use_simple_kernel();
-
-  SearchArgs A;
-  A.rec[0] = t->rec[0];
-  A.rec[1] = t->rec[1];
-  A.vs[0] = t->vs[0];
-  A.vs[1] = t->vs[1];
-  A.pos = t->pos;
-  A.order = t->order;
-  A.nbeg = t->nbeg;
-  A.nend = t->nend;
-  A.leaf_of = t->leaf_of;
-  A.type = neuron_type;
-  A.vac_axon = vac_axon;
-  A.elem_off = elem_offset_out;
-  A.work = work.as<int32_t>();
-  A.work_count = nslots;
-  A.target = target_out;
-  A.err = t->err;
-  A.L2 = t->box_edge * t->box_edge;
-  A.theta2 = theta * theta;
-  A.k2 = kLog2e / (sigma_um * sigma_um);
-  A.seed = seed;
-  A.step = step;
-  DiagOut D{};
+  // the plain search is the batch of one simulation
+  SimDesc h = make_desc(t, neuron_type, vac_axon, sigma_um, theta, seed, step, target_out,
+                        elem_offset_out, capacity_S);
   bool any = false;
   if (diag) {
-    D = DiagOut{diag->z0, diag->levels, diag->visits, diag->opens, diag->visits0, diag->opens0};
-    any = D.z0 || D.levels || D.visits || D.opens || D.visits0 || D.opens0;
+    h.diag = DiagOut{diag->z0, diag->levels, diag->visits, diag->opens, diag->visits0,
+                     diag->opens0};
+    any = h.diag.z0 || h.diag.levels || h.diag.visits || h.diag.opens || h.diag.visits0 ||
+          h.diag.opens0;
   }
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  const int64_t hbase[2] = {0, n};
+  Temp dsim(s), dbase(s), scratch(s);
+  MSP_HIP_TRY(dsim.alloc(sizeof(SimDesc)));
+  MSP_HIP_TRY(dbase.alloc(sizeof(hbase)));
+  MSP_HIP_TRY(scratch.alloc(scratch_sizes(n, 1).total));
+  MSP_HIP_TRY(hipMemcpyAsync(dsim.p, &h, sizeof(SimDesc), hipMemcpyHostToDevice, s));
+  MSP_HIP_TRY(hipMemcpyAsync(dbase.p, hbase, sizeof(hbase), hipMemcpyHostToDevice, s));
+  SearchScratch S = carve(scratch.p, n, 1, dsim.as<SimDesc>(), dbase.as<int64_t>());
+  if (any) S.W.wave_steps = reinterpret_cast<unsigned long long*>(diag->wave_steps);
+  MSP_HIP_TRY(enqueue_prep(S, n, s));
+  int32_t status = 0, ntiles = 0;
+  MSP_HIP_TRY(hipMemcpyAsync(&status, S.B.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MSP_HIP_TRY(hipMemcpyAsync(&ntiles, S.counters, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MSP_HIP_TRY(hipStreamSynchronize(s));
+  if (status & kSimInvalid) return MSP_ERR_INVALID;
+  if (status & kSimCapacity) return MSP_ERR_CAPACITY;
+
   const bool timed = diag && diag->kernel_ms;
-  if (timed)
+  if (ntiles == 0) {
+    if (timed) diag->kernel_ms[0] = diag->kernel_ms[1] = 0.0f;
+    return MSP_OK;
+  }
+  unsigned blocks = 0;
+  MSP_HIP_TRY(sweep_blocks_for(t->device, any, ntiles, 1.0, &blocks));
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  if (timed) {
     for (auto& e : ev) MSP_HIP_TRY(hipEventCreate(&e));
-  // the coherent sweep needs the exact tile count to size its checkpoint buffers
-  int32_t ntiles = 0;
-  if (!simple) {
-    MSP_HIP_TRY(hipMemcpyAsync(&ntiles, tiles, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    MSP_HIP_TRY(hipStreamSynchronize(s));
+    MSP_HIP_TRY(hipEventRecord(ev[0], s));
   }
-  SweepOut W{};
-  unsigned sweep_blocks = 0;
-  if (simple) {
-    tiles_to_slots_k<<<1, 64, 0, s>>>(tiles, nslots);
-  } else {
-    int ncu = 0, per_cu = 0;
-    MSP_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, t->device));
-    MSP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, any ? (const void*)search_sweep_k<true> : (const void*)search_sweep_k<false>,
-        kWaveBlock, 0));
-    if (per_cu < 1) per_cu = 1;
-    int64_t blocks = (int64_t)ncu * per_cu;
-    const int64_t need = ((int64_t)ntiles + (kWaveBlock / kWave) - 1) / (kWaveBlock / kWave);
-    if (blocks > need) blocks = need;
-    if (blocks < 1) blocks = 1;
-    sweep_blocks = (unsigned)blocks;
-    const int64_t nt = ntiles > 0 ? ntiles : 1;
-    const int64_t ns = nt * kWave;
-    const int64_t nc = nt * kCkpt * kWave;
-    const size_t bytes = sizeof(double) * (size_t)(ns + nc) +
-                         sizeof(int32_t) * (size_t)(2 * ns + nt + nt * kCkpt + nc);
-    MSP_HIP_TRY(ck.alloc(bytes));
-    W.Z = ck.as<double>();
-    W.ck_P = W.Z + ns;
-    W.v0 = reinterpret_cast<int32_t*>(W.ck_P + nc);
-    W.o0 = W.v0 + ns;
-    W.nck = W.o0 + ns;
-    W.ck_x = W.nck + nt;
-    W.ck_me = W.ck_x + nt * kCkpt;
-    W.tile_count = tiles;
-    W.queue = queue;
-    W.wave_steps = diag ? reinterpret_cast<unsigned long long*>(diag->wave_steps) : nullptr;
-  }
-  if (timed) MSP_HIP_TRY(hipEventRecord(ev[0], s));
-  if (simple) {
-    if (any)
-      search_simple_k<true><<<grid_for(slots, 256), 256, 0, s>>>(A, D);
-    else
-      search_simple_k<false><<<grid_for(slots, 256), 256, 0, s>>>(A, D);
-  } else if (ntiles > 0) {
-    const unsigned draw_grid = grid_for((int64_t)ntiles * kWave, 256);
-    if (any)
-      search_sweep_k<true><<<sweep_blocks, kWaveBlock, 0, s>>>(A, W);
-    else
-      search_sweep_k<false><<<sweep_blocks, kWaveBlock, 0, s>>>(A, W);
-    if (timed) MSP_HIP_TRY(hipEventRecord(ev[1], s));
-    if (any)
-      search_draw_k<true><<<draw_grid, 256, 0, s>>>(A, D, W);
-    else
-      search_draw_k<false><<<draw_grid, 256, 0, s>>>(A, D, W);
-  }
-  if (timed && (simple || ntiles == 0)) MSP_HIP_TRY(hipEventRecord(ev[1], s));
-  hipError_t le = hipGetLastError();
+  hipError_t le = enqueue_search(S, any, blocks, 256, s, timed ? ev[1] : nullptr);
   if (timed) {
     float a = 0.0f, b = 0.0f;
     (void)hipEventRecord(ev[2], s);
@@ -541,6 +460,226 @@ msp_status msp_octree_export_aggregates(msp_octree t, int32_t type, int64_t* cou
   export_agg_k<<<grid_for(t->N, 256), 256, 0, s>>>(t->rec[type], t->N, count, centroid);
   MSP_HIP_TRY(hipGetLastError());
   return MSP_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------- batched
+struct msp_batch_s {
+  uint32_t magic;
+  int device;
+  int32_t nsims;
+  int32_t flags;
+  int64_t total_n;
+  std::vector<msp_sim> sims;
+  SimDesc* h_sims;          // pinned staging of the descriptor table
+  SimDesc* d_sims;
+  int64_t* d_nbase;
+  void* scratch;
+  SearchScratch S;
+  hipEvent_t staged;        // the descriptor upload of the last run has completed
+  bool staged_pending;
+  unsigned sweep_blocks;
+  int draw_block;
+  bool tuned;
+  hipGraphExec_t exec;
+  bool captured;
+  hipStream_t cap_stream;   // private stream for graph capture (the caller's may be the
+                            // null stream, which cannot be captured)
+};
+
+namespace {
+
+void batch_release(msp_batch_s* b) {
+  if (!b) return;
+  if (b->captured) (void)hipGraphExecDestroy(b->exec);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->staged) (void)hipEventDestroy(b->staged);
+  if (b->h_sims) (void)hipHostFree(b->h_sims);
+  if (b->d_sims) (void)hipFree(b->d_sims);
+  if (b->d_nbase) (void)hipFree(b->d_nbase);
+  if (b->scratch) (void)hipFree(b->scratch);
+  b->magic = kDead;
+  delete b;
+}
+
+bool sim_ok(const msp_sim& m) {
+  return handle_ok(m.tree) && m.tree->refreshed && m.neuron_type && m.vac_axon &&
+         m.elem_offset_out && std::isfinite(m.sigma_um) && m.sigma_um > 0.0 && m.capacity_S >= 0;
+}
+
+hipError_t batch_enqueue(msp_batch_s* b, hipStream_t s) {
+  hipError_t e = enqueue_prep(b->S, b->total_n, s);
+  if (e != hipSuccess) return e;
+  return enqueue_search(b->S, false, b->sweep_blocks, b->draw_block, s);
+}
+
+// Time launch shapes on the current descriptors and keep the fastest.
+hipError_t batch_autotune(msp_batch_s* b, hipStream_t s) {
+  const double fracs[] = {1.0, 0.75, 0.5};
+  const int draws[] = {256, 128, 64};
+  const int64_t max_tiles = max_tiles_for(b->total_n, b->nsims);
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e != hipSuccess) return e;
+  e = hipEventCreate(&e1);
+  if (e != hipSuccess) return e;
+  float best = 1e30f;
+  unsigned best_blocks = b->sweep_blocks;
+  int best_draw = b->draw_block;
+  for (double f : fracs) {
+    for (int d : draws) {
+      unsigned blocks = 0;
+      if ((e = sweep_blocks_for(b->device, false, max_tiles, f, &blocks)) != hipSuccess) break;
+      b->sweep_blocks = blocks;
+      b->draw_block = d;
+      float ms = 0.0f;
+      if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
+      if ((e = batch_enqueue(b, s)) != hipSuccess) break;
+      if ((e = hipEventRecord(e1, s)) != hipSuccess) break;
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) {
+        best = ms;
+        best_blocks = blocks;
+        best_draw = d;
+      }
+    }
+    if (e != hipSuccess) break;
+  }
+  b->sweep_blocks = best_blocks;
+  b->draw_block = best_draw;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+msp_status msp_batch_create(const msp_sim* sims, int32_t n_sims, int32_t flags, msp_batch* out) {
+  if (!out) return MSP_ERR_INVALID;
+  *out = nullptr;
+  if (!sims || n_sims < 1) return MSP_ERR_INVALID;
+  int dev = -1;
+  MSP_HIP_TRY(hipGetDevice(&dev));
+  int64_t total = 0;
+  std::vector<int64_t> base(n_sims + 1, 0);
+  for (int k = 0; k < n_sims; ++k) {
+    if (!sim_ok(sims[k]) || sims[k].tree->device != dev) return MSP_ERR_INVALID;
+    base[k] = total;
+    total += sims[k].tree->n;
+  }
+  base[n_sims] = total;
+  if (total >= ((int64_t)1 << 31) - 4096) return MSP_ERR_INVALID;
+  msp_batch_s* b = new (std::nothrow) msp_batch_s();
+  if (!b) return MSP_ERR_OOM;
+  b->magic = kMagic;
+  b->device = dev;
+  b->nsims = n_sims;
+  b->flags = flags;
+  b->total_n = total;
+  b->sims.assign(sims, sims + n_sims);
+  b->h_sims = nullptr;
+  b->d_sims = nullptr;
+  b->d_nbase = nullptr;
+  b->scratch = nullptr;
+  b->staged = nullptr;
+  b->staged_pending = false;
+  b->tuned = false;
+  b->captured = false;
+  b->cap_stream = nullptr;
+  b->draw_block = 256;
+  hipError_t e = hipHostMalloc((void**)&b->h_sims, sizeof(SimDesc) * n_sims, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_sims, sizeof(SimDesc) * n_sims);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_nbase, sizeof(int64_t) * (n_sims + 1));
+  if (e == hipSuccess) e = hipMalloc(&b->scratch, scratch_sizes(total, n_sims).total);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
+  b->cap_stream = nullptr;
+  if (e == hipSuccess && (flags & MSP_BATCH_GRAPH))
+    e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_nbase, base.data(), sizeof(int64_t) * (n_sims + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = sweep_blocks_for(dev, false, max_tiles_for(total, n_sims), 1.0, &b->sweep_blocks);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    batch_release(b);
+    return e == hipErrorOutOfMemory ? MSP_ERR_OOM : MSP_ERR_HIP;
+  }
+  b->S = carve(b->scratch, total, n_sims, b->d_sims, b->d_nbase);
+  *out = b;
+  return MSP_OK;
+}
+
+msp_status msp_find_targets_batched(msp_batch b, const msp_sim* sims, double theta,
+                                    uint64_t step, hipStream_t s) {
+  if (!b || b->magic != kMagic) return MSP_ERR_INVALID;
+  if (!std::isfinite(theta) || !(theta >= 0.0)) return MSP_ERR_INVALID;
+  if (sims) {
+    for (int k = 0; k < b->nsims; ++k)
+      if (!sim_ok(sims[k]) || sims[k].tree != b->sims[k].tree) return MSP_ERR_INVALID;
+    b->sims.assign(sims, sims + b->nsims);
+  }
+  // the staging buffer is reused: wait until the previous upload has been read
+  if (b->staged_pending) MSP_HIP_TRY(hipEventSynchronize(b->staged));
+  for (int k = 0; k < b->nsims; ++k) {
+    const msp_sim& m = b->sims[k];
+    b->h_sims[k] = make_desc(m.tree, m.neuron_type, m.vac_axon, m.sigma_um, theta, m.seed, step,
+                             m.target_out, m.elem_offset_out, m.capacity_S);
+  }
+  MSP_HIP_TRY(hipMemcpyAsync(b->d_sims, b->h_sims, sizeof(SimDesc) * b->nsims,
+                             hipMemcpyHostToDevice, s));
+  MSP_HIP_TRY(hipEventRecord(b->staged, s));
+  b->staged_pending = true;
+  if ((b->flags & MSP_BATCH_AUTOTUNE) && !b->tuned) {
+    MSP_HIP_TRY(batch_autotune(b, s));
+    b->tuned = true;
+  }
+  if (b->flags & MSP_BATCH_GRAPH) {
+    if (!b->captured) {
+      hipGraph_t g;
+      MSP_HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t e = batch_enqueue(b, b->cap_stream);
+      hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        (void)hipGetLastError();
+        return MSP_ERR_HIP;
+      }
+      e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return MSP_ERR_HIP;
+      b->captured = true;
+    }
+    MSP_HIP_TRY(hipGraphLaunch(b->exec, s));
+    return MSP_OK;
+  }
+  MSP_HIP_TRY(batch_enqueue(b, s));
+  return MSP_OK;
+}
+
+msp_status msp_batch_status(msp_batch b, hipStream_t s, int32_t* status_out) {
+  if (!b || b->magic != kMagic) return MSP_ERR_INVALID;
+  std::vector<int32_t> st(b->nsims, 0);
+  MSP_HIP_TRY(hipMemcpyAsync(st.data(), b->S.B.status, sizeof(int32_t) * b->nsims,
+                             hipMemcpyDeviceToHost, s));
+  MSP_HIP_TRY(hipStreamSynchronize(s));
+  msp_status first = MSP_OK;
+  for (int k = 0; k < b->nsims; ++k) {
+    const msp_status v = (st[k] & kSimInvalid) ? MSP_ERR_INVALID
+                         : (st[k] & kSimCapacity) ? MSP_ERR_CAPACITY : MSP_OK;
+    if (status_out) status_out[k] = v;
+    if (first == MSP_OK) first = v;
+  }
+  return first;
+}
+
+void msp_batch_free(msp_batch b) {
+  if (!b || b->magic != kMagic) return;
+  (void)hipSetDevice(b->device);
+  (void)hipDeviceSynchronize();
+  batch_release(b);
 }
 
 }  // extern "C"

@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(kScanBlock) scan_reduce_k(const Tin* in, int64
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     int64_t idx = base + (int64_t)k * kScanBlock + threadIdx.x;
-    if (idx < n) s += f(in[idx], idx);
+    if (idx < n) s += f(in ? in[idx] : Tin(), idx);
   }
   T tot;
   (void)block_exclusive_scan<T>(s, lds4, &tot);
@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(kScanBlock) scan_apply_k(const Tin* in, int64_
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     int64_t idx = base + k;
-    v[k] = idx < n ? f(in[idx], idx) : T(0);
+    v[k] = idx < n ? f(in ? in[idx] : Tin(), idx) : T(0);
     s += v[k];
   }
   T tot;
@@ -76,16 +76,38 @@ __global__ void __launch_bounds__(kScanBlock) scan_apply_k(const Tin* in, int64_
 }
 
 template <class T>
+__global__ void fill_scalar_k(T* p, T v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+template <class T>
 struct Ident {
   __device__ T operator()(T x, int64_t) const { return x; }
 };
 
-// Exclusive scan of f(in[i]) into out[0..n) (and out[n] = total if write_total).
-// `in` and `out` may alias element-for-element.
+// Bytes of block-sum scratch an exclusive scan of n elements of T needs.
+template <class T>
+size_t scan_tmp_bytes(int64_t n) {
+  size_t bytes = 0;
+  while (n > kScanTile) {
+    n = (n + kScanTile - 1) / kScanTile;
+    bytes += (sizeof(T) * (size_t)n + 255) & ~(size_t)255;
+  }
+  return bytes + 256;
+}
+
+// Exclusive scan of f(in[i], i) into out[0..n) (and out[n] = total if write_total).
+// `in` may be null (f then sees a default value) and may alias `out` element for
+// element. Block sums go to `tmp` (scan_tmp_bytes<T>(n) bytes) or, if null, to
+// stream-ordered temporary memory.
 template <class T, class Tin, class F>
-hipError_t exclusive_scan(const Tin* in, T* out, int64_t n, F f, bool write_total, hipStream_t s) {
+hipError_t exclusive_scan(const Tin* in, T* out, int64_t n, F f, bool write_total, hipStream_t s,
+                          void* tmp = nullptr) {
   if (n <= 0) {
-    if (write_total) return hipMemsetAsync(out, 0, sizeof(T), s);
+    if (write_total) {
+      fill_scalar_k<T><<<1, 64, 0, s>>>(out, T(0));
+      return hipGetLastError();
+    }
     return hipSuccess;
   }
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
@@ -93,15 +115,23 @@ hipError_t exclusive_scan(const Tin* in, T* out, int64_t n, F f, bool write_tota
     scan_apply_k<T, Tin, F><<<1, kScanBlock, 0, s>>>(in, n, out, nullptr, f, write_total ? 1 : 0);
     return hipGetLastError();
   }
-  Temp sums(s);
-  hipError_t e = sums.alloc(sizeof(T) * (size_t)nb);
+  Temp own(s);
+  T* sums;
+  void* rest = nullptr;
+  if (tmp) {
+    sums = static_cast<T*>(tmp);
+    rest = static_cast<char*>(tmp) + ((sizeof(T) * (size_t)nb + 255) & ~(size_t)255);
+  } else {
+    hipError_t e = own.alloc(sizeof(T) * (size_t)nb);
+    if (e != hipSuccess) return e;
+    sums = own.as<T>();
+  }
+  scan_reduce_k<T, Tin, F><<<(unsigned)nb, kScanBlock, 0, s>>>(in, n, sums, f);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  scan_reduce_k<T, Tin, F><<<(unsigned)nb, kScanBlock, 0, s>>>(in, n, sums.as<T>(), f);
-  e = hipGetLastError();
+  e = exclusive_scan<T, T, Ident<T>>(sums, sums, nb, Ident<T>(), false, s, rest);
   if (e != hipSuccess) return e;
-  e = exclusive_scan<T, T, Ident<T>>(sums.as<T>(), sums.as<T>(), nb, Ident<T>(), false, s);
-  if (e != hipSuccess) return e;
-  scan_apply_k<T, Tin, F><<<(unsigned)nb, kScanBlock, 0, s>>>(in, n, out, sums.as<T>(), f,
+  scan_apply_k<T, Tin, F><<<(unsigned)nb, kScanBlock, 0, s>>>(in, n, out, sums, f,
                                                              write_total ? 1 : 0);
   return hipGetLastError();
 }

@@ -34,8 +34,7 @@ struct SearchArgs {
   const uint8_t* type;
   const int32_t* vac_axon;
   const int64_t* elem_off;
-  const int32_t* work;           // sources with a_i > 0, in search order
-  const int32_t* work_count;     // device scalar: number of sources in `work`
+  const int32_t* work;           // sources with a_i > 0, in search order (-1: padding)
   int32_t* target;
   int32_t* err;
   double L2;                     // box_edge * box_edge
@@ -212,25 +211,6 @@ __device__ int32_t restart_search(const SearchArgs& A, const NodeRec* R, const i
   return -1;
 }
 
-// Complete one search from its level-0 normaliser. The selection passes re-walk a
-// prefix of a list already walked by its sum pass and are not counted.
-template <bool COUNT>
-__device__ int32_t finish_search(const SearchArgs& A, const NodeRec* R, const int32_t* vs,
-                                 int32_t i, int32_t j, int32_t li, double xi, double yi, double zi,
-                                 const SumPass& s0, int* levels_out, Count& cnt) {
-  Count none;
-  *levels_out = 1;
-  if (!(s0.Z > 0.0)) return -1;
-  const double T = draw_u(A.seed, i, j, A.step, 0) * s0.Z;
-  SelectPass p{A.k2, T};
-  expand<false>(A, R, vs, 0, i, li, xi, yi, zi, p, none);
-  const int32_t id = p.chosen >= 0 ? p.chosen : p.last;
-  const bool neuron = p.chosen >= 0 ? p.chosen_neuron : p.last_neuron;
-  if (id < 0) return -1;
-  if (neuron) return id;
-  return restart_search<COUNT>(A, R, vs, id, i, j, li, xi, yi, zi, levels_out, cnt);
-}
-
 struct DiagOut {
   double* z0;
   int32_t* levels;
@@ -239,40 +219,5 @@ struct DiagOut {
   int32_t* visits0;
   int32_t* opens0;
 };
-
-// One thread per source: the level-0 normaliser is shared by the source's elements.
-template <bool DIAG>
-__global__ void __launch_bounds__(256) search_simple_k(SearchArgs A, DiagOut D) {
-  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= *A.work_count) return;
-  const int32_t i = A.work[w];
-  if (i < 0) return;                           // padding slot
-  const int t = A.type[i] ? 1 : 0;
-  const NodeRec* R = A.rec[t];
-  const int32_t* vs = A.vs[t];
-  const int32_t a = A.vac_axon[i];
-  const int32_t li = A.leaf_of[i];
-  const double xi = A.pos[3 * (int64_t)i], yi = A.pos[3 * (int64_t)i + 1],
-               zi = A.pos[3 * (int64_t)i + 2];
-  const int64_t off = A.elem_off[i];
-  SumPass s0{A.k2};
-  Count c0;
-  expand<DIAG>(A, R, vs, 0, i, li, xi, yi, zi, s0, c0);
-  const double z0 = s0.Z;
-  for (int32_t j = 0; j < a; ++j) {
-    int lev = 0;
-    Count c = c0;
-    const int32_t tgt = finish_search<DIAG>(A, R, vs, i, j, li, xi, yi, zi, s0, &lev, c);
-    A.target[off + j] = tgt;
-    if (DIAG) {
-      if (D.z0) D.z0[off + j] = z0;
-      if (D.levels) D.levels[off + j] = lev;
-      if (D.visits) D.visits[off + j] = c.visits;
-      if (D.opens) D.opens[off + j] = c.opens;
-      if (D.visits0) D.visits0[off + j] = c0.visits;
-      if (D.opens0) D.opens0[off + j] = c0.opens;
-    }
-  }
-}
 
 }  // namespace msp

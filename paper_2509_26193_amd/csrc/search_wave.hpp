@@ -197,39 +197,10 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
   return steps;
 }
 
-// Persistent waves pull 64-source tiles: first from the Morton range of their own
-// die (neighbouring sources share upper-tree nodes in that die's L2), then from the
-// other dies' ranges.
+// The draws and restarts of the source in worklist slot `slot`.
 template <bool DIAG>
-__global__ void __launch_bounds__(kWaveBlock) search_sweep_k(SearchArgs A, SweepOut W) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int home = blockIdx.x % kXcd;
-  const int ntiles = *W.tile_count;
-  int q = 0;
-  int step0 = 2 * kCkptStepMin;
-  while (q < kXcd) {
-    const int qq = (home + q) % kXcd;
-    const int lo = (int)((int64_t)ntiles * qq / kXcd);
-    const int hi = (int)((int64_t)ntiles * (qq + 1) / kXcd);
-    int got = 0;
-    if (lane == 0) got = atomicAdd(&W.queue[qq], 1);
-    got = __shfl(got, 0, kWave);
-    if (lo + got >= hi) {
-      ++q;
-      continue;
-    }
-    const int steps = sweep_tile<DIAG>(A, W, lo + got, lane, step0);
-    // next interval: about kCkpt checkpoints over a sweep as long as this one
-    step0 = kCkptStepMin;
-    while (step0 * kCkpt < steps) step0 <<= 1;
-  }
-}
-
-// One thread per worklist slot (source): its elements' draws and restarts.
-template <bool DIAG>
-__global__ void __launch_bounds__(256) search_draw_k(SearchArgs A, DiagOut D, SweepOut W) {
-  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= (int64_t)(*W.tile_count) * kWave) return;
+__device__ __forceinline__ void draw_slot(const SearchArgs& A, const DiagOut& D, const SweepOut& W,
+                                          int64_t slot) {
   const int32_t i = A.work[slot];
   if (i < 0) return;
   const int64_t tile = slot / kWave;
