@@ -217,6 +217,38 @@ def bench_batched(msp, torch, reps=5):
                 speedup=tp / tb, identical_targets=bool(same))
 
 
+def bench_attraction(msp, torch, reps=5):
+    """Expected attraction forward and adjoint (dL/dx, dL/dsigma of sum log Z) on 2^18
+    neurons in a 5000 um cube."""
+    from synth_inputs import config_attraction
+    dev = torch.device("cuda:0")
+    T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    w = config_attraction()
+    tree = msp.build_octree(T(w.pos, torch.float64), w.box_min, w.box_edge)
+    msp.update_vacant_counts(tree, T(w.vac_exc, torch.int32), T(w.vac_inh, torch.int32))
+    ty, va = T(w.neuron_type, torch.uint8), T(w.vac_axon, torch.int32)
+    src = va > 0
+    Z = msp.attraction_fwd(tree, ty, va, w.sigma, w.theta)
+    gZ = torch.where(src, 1.0 / torch.where(src, Z, torch.ones_like(Z)), torch.zeros_like(Z))
+    msp.attraction_bwd(tree, ty, va, w.sigma, w.theta, gZ)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        msp.attraction_fwd(tree, ty, va, w.sigma, w.theta)
+    torch.cuda.synchronize()
+    tf = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        msp.attraction_bwd(tree, ty, va, w.sigma, w.theta, gZ)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    tree.free()
+    ns = int(src.sum().item())
+    return dict(workload=w.name, neurons=w.n, sources=ns, forward_ms=tf * 1e3,
+                backward_ms=tb * 1e3, sources_per_s_forward=ns / tf,
+                sources_per_s_backward=ns / tb)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -363,6 +395,8 @@ def main():
         del wc
         log("also: batched")
         also["batched"] = bench_batched(msp, torch)
+        log("also: attraction")
+        also["attraction"] = bench_attraction(msp, torch)
         out["also"] = also
     if not args.no_cpu:
         threads = args.cpu_threads or min(os.cpu_count() or 1, 64)

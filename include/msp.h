@@ -194,6 +194,29 @@ msp_status msp_batch_status(msp_batch b, hipStream_t s, int32_t* status_out);
 void msp_batch_free(msp_batch b);
 
 /*
+ * Expected attraction (the differentiated form). For every neuron i with vac_axon > 0,
+ * Z_out[i] = the normaliser of its level-0 Barnes-Hut list: the sum over the accepted
+ * cells and neurons e (type of i, acceptance as in msp_find_targets) of
+ * v_e * exp(-|x_i - c_e|^2 / sigma^2); Z_out[i] = 0 for the other neurons. float32
+ * output, float64 accumulation. The octree must be refreshed; its positions are the
+ * positions differentiated.
+ */
+msp_status msp_attraction_fwd(msp_octree t, const uint8_t* neuron_type, const int32_t* vac_axon,
+                              double sigma_um, double theta, float* Z_out, hipStream_t s);
+
+/*
+ * Adjoint of msp_attraction_fwd with every acceptance decision held fixed (the
+ * function is piecewise smooth in the positions): given gZ[n] = dLoss/dZ_i (float32,
+ * entries of neurons without vacant axonal elements are ignored), writes
+ * dpos[n][3] = dLoss/dx (float32) and dsigma (device float64 scalar) = dLoss/dsigma.
+ * Centroid gradients reach the neurons of a cell as v_j / v_C. Uses float64 atomics:
+ * the result is deterministic up to the order of floating-point additions.
+ */
+msp_status msp_attraction_bwd(msp_octree t, const uint8_t* neuron_type, const int32_t* vac_axon,
+                              double sigma_um, double theta, const float* gZ, float* dpos,
+                              double* dsigma, hipStream_t s);
+
+/*
  * Accept or decline every request (Sec. III-A, "Update of synapses"; Sec. III-B:
  * requests are exchanged, accepted locally and answered yes/no).
  *   target [S], elem_offset [n+1]: as produced by msp_find_targets.

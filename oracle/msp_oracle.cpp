@@ -616,15 +616,16 @@ int oracle_attraction(const OracleTree* t, const uint8_t* neuron_type, const int
 
 // L at positions pos_new and width sigma_new, with the topology, the memberships
 // and every acceptance decision taken at the tree's own geometry (frozen sets).
+// Z_out[n] (nullable) receives every Z_i.
 double oracle_attraction_frozen(const OracleTree* t, const uint8_t* neuron_type,
                                 const int32_t* vac_axon, double sigma_new, double theta,
-                                const double* pos_new, int nthreads) {
+                                const double* pos_new, double* Z_out, int nthreads) {
   OracleTree moved = *t;                           // same topology and counts
   moved.pos.assign(pos_new, pos_new + 3 * t->n);
   for (int ty = 0; ty < 2; ++ty) aggregate(moved, ty, 0, moved.pos);
   Geometry acc[2] = {{&t->pos, &t->cen[0]}, {&t->pos, &t->cen[1]}};
   Geometry wgt[2] = {{&moved.pos, &moved.cen[0]}, {&moved.pos, &moved.cen[1]}};
-  return attraction_sum(moved, neuron_type, vac_axon, sigma_new, theta, acc, wgt, nullptr,
+  return attraction_sum(moved, neuron_type, vac_axon, sigma_new, theta, acc, wgt, Z_out,
                         nthreads);
 }
 

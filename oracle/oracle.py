@@ -66,7 +66,8 @@ def lib():
         L.oracle_attraction.argtypes = [_ptr, _ptr, _ptr, _dbl, _dbl, _ptr, _ptr, _ptr, _ptr,
                                         ctypes.c_int]
         L.oracle_attraction_frozen.restype = _dbl
-        L.oracle_attraction_frozen.argtypes = [_ptr, _ptr, _ptr, _dbl, _dbl, _ptr, ctypes.c_int]
+        L.oracle_attraction_frozen.argtypes = [_ptr, _ptr, _ptr, _dbl, _dbl, _ptr, _ptr,
+                                               ctypes.c_int]
         _lib = L
     return _lib
 
@@ -173,12 +174,38 @@ class OracleTree:
             raise ValueError("oracle_attraction rejected the input")
         return Z, float(L[0]), dX, float(ds[0])
 
-    def attraction_frozen(self, neuron_type, vac_axon, sigma, theta, pos_new, nthreads=0) -> float:
+    def attraction_frozen(self, neuron_type, vac_axon, sigma, theta, pos_new, nthreads=0,
+                          return_z=False):
+        """L (and, with return_z, every Z_i) at positions pos_new / width sigma with the
+        accepted sets of the tree's own geometry."""
         t = np.ascontiguousarray(neuron_type, dtype=np.uint8)
         a = np.ascontiguousarray(vac_axon, dtype=np.int32)
         p = np.ascontiguousarray(pos_new, dtype=np.float64)
-        return float(lib().oracle_attraction_frozen(self._h, _p(t), _p(a), float(sigma),
-                                                    float(theta), _p(p), int(nthreads)))
+        Z = np.zeros(self.n, np.float64) if return_z else None
+        L = float(lib().oracle_attraction_frozen(self._h, _p(t), _p(a), float(sigma),
+                                                 float(theta), _p(p), _p(Z), int(nthreads)))
+        return (L, Z) if return_z else L
+
+    def frozen_derivative(self, neuron_type, vac_axon, sigma, theta, h, coord=None,
+                          nthreads=0):
+        """Central difference of L = sum_i log Z_i in one position coordinate
+        coord = (i, axis), or in sigma if coord is None, with frozen sets. The
+        difference is summed per source as log1p((Z+ - Z-) / Z-), which keeps its
+        precision where L itself is large."""
+        if coord is None:
+            _, zp = self.attraction_frozen(neuron_type, vac_axon, sigma + h, theta, self.pos,
+                                           nthreads, True)
+            _, zm = self.attraction_frozen(neuron_type, vac_axon, sigma - h, theta, self.pos,
+                                           nthreads, True)
+        else:
+            i, ax = coord
+            p = self.pos.copy()
+            p[i, ax] += h
+            _, zp = self.attraction_frozen(neuron_type, vac_axon, sigma, theta, p, nthreads, True)
+            p[i, ax] -= 2 * h
+            _, zm = self.attraction_frozen(neuron_type, vac_axon, sigma, theta, p, nthreads, True)
+        ok = (zp > 0) & (zm > 0)
+        return float(np.sum(np.log1p((zp[ok] - zm[ok]) / zm[ok]))) / (2 * h)
 
 
 def commit(elem_offset, target, neuron_type, vac_axon, vac_exc, vac_inh, seed, step):

@@ -70,6 +70,8 @@ _SIGS = {
     "msp_find_targets_batched": (_i32, [_vp, ctypes.POINTER(SimSpec), _dbl, _u64, _vp]),
     "msp_batch_status": (_i32, [_vp, _vp, ctypes.POINTER(_i32)]),
     "msp_batch_free": (None, [_vp]),
+    "msp_attraction_fwd": (_i32, [_vp, _vp, _vp, _dbl, _dbl, _vp, _vp]),
+    "msp_attraction_bwd": (_i32, [_vp, _vp, _vp, _dbl, _dbl, _vp, _vp, _vp, _vp]),
 }
 
 MSP_BATCH_GRAPH = 1
@@ -373,3 +375,55 @@ class Batch:
             self.free()
         except Exception:
             pass
+
+
+def attraction_fwd(tree: Octree, neuron_type, vac_axon, sigma: float, theta: float,
+                   stream=None) -> torch.Tensor:
+    """Z[n] (float32): level-0 normaliser of every neuron with vacant axonal elements."""
+    n = tree.n
+    Z = torch.empty(n, dtype=torch.float32, device=tree.device)
+    _check(lib().msp_attraction_fwd(tree.handle, _dev(neuron_type, torch.uint8, "neuron_type", n),
+                                    _dev(vac_axon, torch.int32, "vac_axon", n), float(sigma),
+                                    float(theta), Z.data_ptr(), _stream(stream)), "attraction_fwd")
+    return Z
+
+
+def attraction_bwd(tree: Octree, neuron_type, vac_axon, sigma: float, theta: float,
+                   gZ: torch.Tensor, stream=None):
+    """(dpos[n][3] float32, dsigma float64 0-d tensor) for upstream gradient gZ[n]."""
+    n = tree.n
+    dpos = torch.empty((n, 3), dtype=torch.float32, device=tree.device)
+    ds = torch.empty((), dtype=torch.float64, device=tree.device)
+    g = gZ.to(torch.float32).contiguous()
+    _check(lib().msp_attraction_bwd(tree.handle, _dev(neuron_type, torch.uint8, "neuron_type", n),
+                                    _dev(vac_axon, torch.int32, "vac_axon", n), float(sigma),
+                                    float(theta), _dev(g, torch.float32, "gZ", n), dpos.data_ptr(),
+                                    ds.data_ptr(), _stream(stream)), "attraction_bwd")
+    return dpos, ds
+
+
+class AttractionFn(torch.autograd.Function):
+    """Z = expected attraction of each axon-bearing neuron, differentiable in the
+    positions and in sigma (acceptance decisions held fixed). The octree must have
+    been built from `pos` and refreshed with the current dendritic vacancies."""
+
+    @staticmethod
+    def forward(ctx, pos, sigma, tree, neuron_type, vac_axon, theta):
+        s = float(sigma.detach())
+        Z = attraction_fwd(tree, neuron_type, vac_axon, s, theta)
+        ctx.tree = tree
+        ctx.args = (neuron_type, vac_axon, s, theta)
+        ctx.sigma_dtype = sigma.dtype
+        return Z
+
+    @staticmethod
+    def backward(ctx, gZ):
+        neuron_type, vac_axon, s, theta = ctx.args
+        dpos, ds = attraction_bwd(ctx.tree, neuron_type, vac_axon, s, theta, gZ)
+        return dpos.to(torch.float64), ds.to(ctx.sigma_dtype), None, None, None, None
+
+
+def attraction(pos: torch.Tensor, sigma: torch.Tensor, tree: Octree, neuron_type, vac_axon,
+               theta: float) -> torch.Tensor:
+    """Differentiable Z (see AttractionFn)."""
+    return AttractionFn.apply(pos, sigma, tree, neuron_type, vac_axon, theta)

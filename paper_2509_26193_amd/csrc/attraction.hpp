@@ -1,0 +1,231 @@
+// Expected attraction and its adjoint (the differentiated form of the search).
+//
+// For a source i with vacant axonal elements, Z_i is the normaliser of its level-0
+// list: the sum over the accepted entries e (cells and neurons, type of i) of
+// w_e = v_e exp(-|x_i - c_e|^2 / sigma^2). Given upstream gradients g_i = dLoss/dZ_i,
+// with every acceptance decision held at the current geometry:
+//   dZ_i/dx_i     = sum_e w_e * (-2 (x_i - c_e) / sigma^2)
+//   dZ_i/dc_e     = w_e * 2 (x_i - c_e) / sigma^2        (a neuron entry: c_e = x_j)
+//   dZ_i/dsigma   = sum_e w_e * 2 |x_i - c_e|^2 / sigma^3
+//   dc_C/dx_j     = (v_j / v_C) I for every neuron j of cell C (a centroid is the
+//                   vacancy-weighted mean of its neurons).
+// The sweep walks the sources' lists coherently (as the search does); per node, the
+// contributions of all lanes of the wave are summed in registers first and added to
+// the node's gradient with one float64 atomic per component. A top-down pass then
+// carries sum_{C containing j} G_C / v_C to each neuron.
+#pragma once
+
+#include "batch.hpp"
+
+namespace msp {
+
+struct AttractArgs {
+  const float* gZ;              // [n] upstream gradient (backward), by neuron id
+  float* Z;                     // [n] output (forward), by neuron id
+  double* G;                    // [2][N][3] per-node centroid gradients (backward)
+  double* dpos;                 // [n][3] float64 accumulator (backward)
+  double* dsigma;               // scalar accumulator (backward)
+  double two_over_s2;           // 2 / sigma^2
+  double two_over_s3;           // 2 / sigma^3
+  int64_t N;
+  const int32_t* tile_count;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Add the wave's contributions (fx, fy, fz) to dst[3] (skipped if all are zero).
+__device__ __forceinline__ void wave_add3(double fx, double fy, double fz, double* dst, int lane) {
+  if (!__any(fx != 0.0 || fy != 0.0 || fz != 0.0)) return;
+  fx = wave_sum(fx);
+  fy = wave_sum(fy);
+  fz = wave_sum(fz);
+  if (lane == 0) {
+    atomicAdd(dst + 0, fx);
+    atomicAdd(dst + 1, fy);
+    atomicAdd(dst + 2, fz);
+  }
+}
+
+template <bool BWD>
+__device__ void attract_tile(const SearchArgs& A, const AttractArgs& O, int tile, int lane) {
+  const int64_t slot = (int64_t)tile * kWave + lane;
+  const int32_t i = A.work[slot];
+  const bool valid = i >= 0;
+  const int32_t i0 = __builtin_amdgcn_readfirstlane(i);
+  const int t = A.type[i0] ? 1 : 0;
+  const cptr<NodeRec> R = as_const(A.rec[t]);
+  int32_t li = -1;
+  double xi = 0.0, yi = 0.0, zi = 0.0, g = 0.0;
+  if (valid) {
+    li = A.leaf_of[i];
+    xi = A.pos[3 * (int64_t)i];
+    yi = A.pos[3 * (int64_t)i + 1];
+    zi = A.pos[3 * (int64_t)i + 2];
+    if (BWD) g = (double)O.gZ[i];
+  }
+  double Z = 0.0, dxi = 0.0, dyi = 0.0, dzi = 0.0, ds = 0.0;
+  double* G = BWD ? O.G + (int64_t)t * O.N * 3 : nullptr;
+  // one accepted entry of this lane: weight, and in the backward pass the gradient
+  // factor f = g * w * 2 / sigma^2 applied to the offset (x_i - c)
+  auto take = [&](bool on, int32_t v, double cx, double cy, double cz, double& fx, double& fy,
+                  double& fz) {
+    fx = fy = fz = 0.0;
+    if (!on) return;
+    const double dx = xi - cx, dy = yi - cy, dz = zi - cz;
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    const double w = kernel_weight(v, d2, A.k2);
+    if (!BWD) {
+      Z = Z + w;
+      return;
+    }
+    const double f = g * w * O.two_over_s2;
+    fx = f * dx;
+    fy = f * dy;
+    fz = f * dz;
+    dxi -= fx;
+    dyi -= fy;
+    dzi -= fz;
+    ds += g * w * d2 * O.two_over_s3;
+  };
+  const NodeRec root = load_rec(R, 0);
+  if (!(root.meta & kLeafBit)) {
+    const int32_t end = (int32_t)(root.meta & kSkipMask);
+    int32_t x = 1;
+    int32_t me = valid ? 0 : 0x7FFFFFFF;
+    while (x < end) {
+      const NodeRec cur = load_rec(R, x);
+      const bool active = x >= me;
+      const uint32_t meta = cur.meta;
+      if (meta & kLeafBit) {
+        if (cur.v != 0) {
+          if (!(meta & kBucketBit)) {
+            const int32_t id = (int32_t)(meta & kIdMask);
+            double fx, fy, fz;
+            take(active && id != i, cur.v, cur.x, cur.y, cur.z, fx, fy, fz);
+            if (BWD) wave_add3(fx, fy, fz, O.dpos + 3 * (int64_t)id, lane);
+          } else {
+            const cptr<int32_t> vs = as_const(A.vs[t]);
+            const cptr<int32_t> order = as_const(A.order);
+            const cptr<double> pos = as_const(A.pos);
+            const int32_t pe = as_const(A.nend)[x];
+            for (int32_t p = as_const(A.nbeg)[x]; p < pe; ++p) {
+              const int32_t id = order[p];
+              const int32_t v = vs[p];
+              double fx, fy, fz;
+              take(active && id != i && v != 0, v, pos[3 * (int64_t)id], pos[3 * (int64_t)id + 1],
+                   pos[3 * (int64_t)id + 2], fx, fy, fz);
+              if (BWD) wave_add3(fx, fy, fz, O.dpos + 3 * (int64_t)id, lane);
+            }
+          }
+        }
+        x = x + 1;
+        continue;
+      }
+      int32_t sk = (int32_t)(meta & kSkipMask);
+      sk = sk > x ? sk : x + 1;
+      if (cur.v == 0) {
+        x = sk;
+        continue;
+      }
+      const bool contains = li >= x && li < sk;
+      const double d2 = dist2(xi, yi, zi, cur.x, cur.y, cur.z);
+      const int dep = (int)((meta >> kSkipBits) & 31u);
+      const bool acc_ok = ldexp(A.L2, -2 * dep) < A.theta2 * d2;
+      const bool open = active && (contains || !acc_ok);
+      const bool accept = active && !contains && acc_ok;
+      double fx, fy, fz;
+      take(accept, cur.v, cur.x, cur.y, cur.z, fx, fy, fz);
+      if (BWD) wave_add3(fx, fy, fz, G + 3 * (int64_t)x, lane);
+      if (accept) me = sk;
+      x = __any(open) ? x + 1 : sk;
+    }
+  }
+  if (!BWD) {
+    if (valid) O.Z[i] = (float)Z;
+  } else {
+    if (valid) {
+      atomicAdd(O.dpos + 3 * (int64_t)i + 0, dxi);
+      atomicAdd(O.dpos + 3 * (int64_t)i + 1, dyi);
+      atomicAdd(O.dpos + 3 * (int64_t)i + 2, dzi);
+    }
+    ds = wave_sum(ds);
+    if (lane == 0 && ds != 0.0) atomicAdd(O.dsigma, ds);
+  }
+}
+
+// One wave per tile (the batch path's worklist of sources with a_i > 0).
+template <bool BWD>
+__global__ void __launch_bounds__(256) attract_k(BatchDev B, AttractArgs O) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  if (tile >= *O.tile_count) return;
+  const SearchArgs A = args_of(B.sims, 0, B.work);
+  attract_tile<BWD>(A, O, (int)tile, lane);
+}
+
+__global__ void fill_f64_k(double* p, int64_t n, double v) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+
+// Top-down: H(child) = H(node) + G(child) / v(child), per type; the root's H is
+// G(root) / v(root) (zero: the root is never accepted). One launch per depth.
+__global__ void push_level_k(const int32_t* __restrict__ nodes, int64_t cnt,
+                             const NodeRec* __restrict__ r0, const NodeRec* __restrict__ r1,
+                             const double* __restrict__ G, double* __restrict__ H, int64_t N) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= cnt) return;
+  const int32_t x = nodes[q];
+  const uint32_t meta = r0[x].meta;
+  if (meta & kLeafBit) return;
+  const int32_t end = (int32_t)(meta & kSkipMask);
+  for (int t = 0; t < 2; ++t) {
+    const NodeRec* r = t ? r1 : r0;
+    const double* Gt = G + (int64_t)t * N * 3;
+    double* Ht = H + (int64_t)t * N * 3;
+    const double hx = Ht[3 * (int64_t)x], hy = Ht[3 * (int64_t)x + 1], hz = Ht[3 * (int64_t)x + 2];
+    int32_t c = x + 1;
+    while (c < end) {
+      const NodeRec rc = r[c];
+      double ax = hx, ay = hy, az = hz;
+      if (rc.v > 0) {
+        const double iv = 1.0 / (double)rc.v;
+        ax += Gt[3 * (int64_t)c] * iv;
+        ay += Gt[3 * (int64_t)c + 1] * iv;
+        az += Gt[3 * (int64_t)c + 2] * iv;
+      }
+      Ht[3 * (int64_t)c] = ax;
+      Ht[3 * (int64_t)c + 1] = ay;
+      Ht[3 * (int64_t)c + 2] = az;
+      c = (rc.meta & kLeafBit) ? c + 1 : (int32_t)(rc.meta & kSkipMask);
+    }
+  }
+}
+
+// Neurons: dpos_j += sum_t v_j^t H^t(leaf of j); then convert to float32.
+__global__ void push_leaves_k(const int32_t* __restrict__ leaf_of, const int32_t* __restrict__ nbeg,
+                              const int32_t* __restrict__ nend, const int32_t* __restrict__ order,
+                              const int32_t* __restrict__ vs0, const int32_t* __restrict__ vs1,
+                              const double* __restrict__ H, int64_t N, int64_t n,
+                              const double* __restrict__ dpos64, float* __restrict__ dpos) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int32_t x = leaf_of[j];
+  // the neuron's position in sorted order, to read its per-type counts
+  int32_t p = nbeg[x];
+  while (p < nend[x] && order[p] != (int32_t)j) ++p;
+  double a[3] = {dpos64[3 * j], dpos64[3 * j + 1], dpos64[3 * j + 2]};
+  for (int t = 0; t < 2; ++t) {
+    const int32_t v = t ? vs1[p] : vs0[p];
+    if (v <= 0) continue;
+    const double* Ht = H + (int64_t)t * N * 3 + 3 * (int64_t)x;
+    for (int k = 0; k < 3; ++k) a[k] += (double)v * Ht[k];
+  }
+  for (int k = 0; k < 3; ++k) dpos[3 * j + k] = (float)a[k];
+}
+
+}  // namespace msp

@@ -12,6 +12,7 @@
 #include "search.hpp"
 #include "search_wave.hpp"
 #include "batch.hpp"
+#include "attraction.hpp"
 #include "commit.hpp"
 
 using namespace msp;
@@ -680,6 +681,89 @@ void msp_batch_free(msp_batch b) {
   (void)hipSetDevice(b->device);
   (void)hipDeviceSynchronize();
   batch_release(b);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------- attraction
+namespace {
+
+msp_status attraction(msp_octree t, const uint8_t* neuron_type, const int32_t* vac_axon,
+                      double sigma_um, double theta, bool bwd, float* Z_out, const float* gZ,
+                      float* dpos, double* dsigma, hipStream_t s) {
+  if (!handle_ok(t) || !t->refreshed || !neuron_type || !vac_axon) return MSP_ERR_INVALID;
+  if (!std::isfinite(sigma_um) || !(sigma_um > 0.0) || !std::isfinite(theta) || !(theta >= 0.0))
+    return MSP_ERR_INVALID;
+  if (bwd ? (!gZ || !dpos || !dsigma) : !Z_out) return MSP_ERR_INVALID;
+  const int64_t n = t->n, N = t->N;
+  Temp dsim(s), dbase(s), scratch(s), off(s), grads(s);
+  MSP_HIP_TRY(off.alloc(sizeof(int64_t) * (n + 1)));
+  // the search's preparation gives the worklist; targets are not written here
+  SimDesc h = make_desc(t, neuron_type, vac_axon, sigma_um, theta, 0, 0,
+                        reinterpret_cast<int32_t*>(off.p), off.as<int64_t>(), INT64_MAX);
+  const int64_t hbase[2] = {0, n};
+  MSP_HIP_TRY(dsim.alloc(sizeof(SimDesc)));
+  MSP_HIP_TRY(dbase.alloc(sizeof(hbase)));
+  MSP_HIP_TRY(scratch.alloc(scratch_sizes(n, 1).total));
+  MSP_HIP_TRY(hipMemcpyAsync(dsim.p, &h, sizeof(SimDesc), hipMemcpyHostToDevice, s));
+  MSP_HIP_TRY(hipMemcpyAsync(dbase.p, hbase, sizeof(hbase), hipMemcpyHostToDevice, s));
+  SearchScratch S = carve(scratch.p, n, 1, dsim.as<SimDesc>(), dbase.as<int64_t>());
+  MSP_HIP_TRY(enqueue_prep(S, n, s));
+  int32_t status = 0;
+  MSP_HIP_TRY(hipMemcpyAsync(&status, S.B.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MSP_HIP_TRY(hipStreamSynchronize(s));
+  if (status & kSimInvalid) return MSP_ERR_INVALID;
+
+  AttractArgs O{};
+  O.gZ = gZ;
+  O.Z = Z_out;
+  O.two_over_s2 = 2.0 / (sigma_um * sigma_um);
+  O.two_over_s3 = 2.0 / (sigma_um * sigma_um * sigma_um);
+  O.N = N;
+  O.tile_count = S.counters;
+  const unsigned grid = grid_for(S.B.max_slots, 256);
+  if (!bwd) {
+    fill_i32_k<<<grid_for(n, 256), 256, 0, s>>>(reinterpret_cast<int32_t*>(Z_out), n, 0);
+    attract_k<false><<<grid, 256, 0, s>>>(S.B, O);
+    MSP_HIP_TRY(hipGetLastError());
+    return MSP_OK;
+  }
+  const int64_t ng = 2 * N * 3, nh = 2 * N * 3, np = 3 * n;
+  MSP_HIP_TRY(grads.alloc(sizeof(double) * (size_t)(ng + nh + np)));
+  O.G = grads.as<double>();
+  double* H = O.G + ng;
+  O.dpos = H + nh;
+  O.dsigma = dsigma;
+  fill_f64_k<<<grid_for(ng + nh + np, 256), 256, 0, s>>>(O.G, ng + nh + np, 0.0);
+  fill_f64_k<<<1, 64, 0, s>>>(dsigma, 1, 0.0);
+  attract_k<true><<<grid, 256, 0, s>>>(S.B, O);
+  for (int k = 0; k <= kMaxDepth; ++k) {
+    const int64_t cnt = t->level_off[k + 1] - t->level_off[k];
+    if (cnt == 0) continue;
+    push_level_k<<<grid_for(cnt, 256), 256, 0, s>>>(t->level_nodes + t->level_off[k], cnt,
+                                                     t->rec[0], t->rec[1], O.G, H, N);
+  }
+  push_leaves_k<<<grid_for(n, 256), 256, 0, s>>>(t->leaf_of, t->nbeg, t->nend, t->order,
+                                                  t->vs[0], t->vs[1], H, N, n, O.dpos, dpos);
+  MSP_HIP_TRY(hipGetLastError());
+  return MSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+msp_status msp_attraction_fwd(msp_octree t, const uint8_t* neuron_type, const int32_t* vac_axon,
+                              double sigma_um, double theta, float* Z_out, hipStream_t s) {
+  return attraction(t, neuron_type, vac_axon, sigma_um, theta, false, Z_out, nullptr, nullptr,
+                    nullptr, s);
+}
+
+msp_status msp_attraction_bwd(msp_octree t, const uint8_t* neuron_type, const int32_t* vac_axon,
+                              double sigma_um, double theta, const float* gZ, float* dpos,
+                              double* dsigma, hipStream_t s) {
+  return attraction(t, neuron_type, vac_axon, sigma_um, theta, true, nullptr, gZ, dpos, dsigma,
+                    s);
 }
 
 }  // extern "C"

@@ -1,0 +1,121 @@
+"""Differentiated form: the expected attraction Z_i and the adjoint of sum_i log Z_i
+with respect to the positions and sigma, against the fp64 oracle (its analytic
+gradient is pinned on the CPU by closed forms, central differences and the theta = 0
+direct gradient), against central differences of the oracle's frozen-set forward, and
+against a direct fp64 gradient at theta = 0."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2509_26193_amd as msp
+from oracle import oracle as orc
+from synth_inputs import config_attraction, uniform_cube
+from gpu_util import T, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(w, theta):
+    tree = msp.build_octree(T(w.pos, torch.float64), w.box_min, w.box_edge)
+    msp.update_vacant_counts(tree, T(w.vac_exc, torch.int32), T(w.vac_inh, torch.int32))
+    ty, va = T(w.neuron_type, torch.uint8), T(w.vac_axon, torch.int32)
+    Z = msp.attraction_fwd(tree, ty, va, w.sigma, theta)
+    src = va > 0
+    gZ = torch.where(src, 1.0 / torch.where(src, Z, torch.ones_like(Z)), torch.zeros_like(Z))
+    dpos, ds = msp.attraction_bwd(tree, ty, va, w.sigma, theta, gZ)
+    torch.cuda.synchronize()
+    out = dict(Z=Z.cpu().numpy().astype(np.float64), dpos=dpos.cpu().numpy().astype(np.float64),
+               ds=float(ds.item()), tree=tree, ty=ty, va=va)
+    return out
+
+
+def _close(g, o, label, rtol=1e-4, atol_frac=1e-5):
+    err = np.abs(g - o)
+    tol = rtol * np.abs(o) + atol_frac * np.abs(o).max()
+    say(f"[{label}] max abs err {err.max():.3e}, max |ref| {np.abs(o).max():.3e}, "
+        f"worst ratio {(err / tol).max():.3f}")
+    assert np.all(err <= tol), label
+
+
+def test_forward_and_backward_match_oracle_262144():
+    w = config_attraction()
+    say(f"attraction n={w.n} sources={(w.vac_axon > 0).sum()} sigma={w.sigma} theta={w.theta}")
+    g = _gpu(w, w.theta)
+    t = orc.OracleTree(w.pos, w.box_min, w.box_edge)
+    t.update_counts(w.vac_exc, w.vac_inh)
+    Z, L, dX, ds = t.attraction(w.neuron_type, w.vac_axon, w.sigma, w.theta)
+    src = w.vac_axon > 0
+    rel = np.abs(g["Z"][src] - Z[src]) / Z[src]
+    say(f"Z: max rel err {rel.max():.3e}")
+    assert rel.max() < 1e-5
+    assert np.all(g["Z"][~src] == 0.0)
+    _close(g["dpos"], dX, "dL/dx")
+    assert g["ds"] == pytest.approx(ds, rel=1e-5)
+    g["tree"].free()
+
+
+def test_backward_matches_central_differences():
+    # same density as the 262144 case, smaller box so the fp64 forward is cheap
+    w = uniform_cube(32768, 2500.0, seed=7)
+    g = _gpu(w, 0.3)
+    t = orc.OracleTree(w.pos, w.box_min, w.box_edge)
+    t.update_counts(w.vac_exc, w.vac_inh)
+    h = 1e-3
+    rng = np.random.default_rng(3)
+    for _ in range(10):
+        i, a = int(rng.integers(0, w.n)), int(rng.integers(0, 3))
+        fd = t.frozen_derivative(w.neuron_type, w.vac_axon, w.sigma, 0.3, h, coord=(i, a))
+        say(f"x[{i},{a}]: fd {fd:.8e} gpu {g['dpos'][i, a]:.8e}")
+        assert g["dpos"][i, a] == pytest.approx(fd, rel=1e-4, abs=1e-9)
+    fd = t.frozen_derivative(w.neuron_type, w.vac_axon, w.sigma, 0.3, h)
+    say(f"sigma: fd {fd:.8e} gpu {g['ds']:.8e}")
+    assert g["ds"] == pytest.approx(fd, rel=1e-5)
+    g["tree"].free()
+
+
+def test_theta0_direct_gradient_on_4096_subset():
+    full = config_attraction()
+    n = 4096
+    w = uniform_cube(n, 5000.0, seed=42)          # same generator, then take the subset
+    w.pos = full.pos[:n].copy()
+    w.neuron_type = full.neuron_type[:n].copy()
+    w.vac_axon = full.vac_axon[:n].copy()
+    w.vac_exc = full.vac_exc[:n].copy()
+    w.vac_inh = full.vac_inh[:n].copy()
+    g = _gpu(w, 0.0)
+    sigma = w.sigma
+    X = w.pos
+    D = X[:, None, :] - X[None, :, :]
+    D2 = (D ** 2).sum(-1)
+    V = np.where(w.neuron_type[:, None] == 1, w.vac_inh[None, :], w.vac_exc[None, :]).astype(float)
+    np.fill_diagonal(V, 0.0)
+    W = V * np.exp(-D2 / sigma ** 2)
+    Zr = W.sum(1)
+    src = w.vac_axon > 0
+    F = np.where(src[:, None], W / np.where(Zr > 0, Zr, 1)[:, None], 0.0)
+    dX = (F[:, :, None] * (-2 * D / sigma ** 2)).sum(1) + (F[:, :, None] * (2 * D / sigma ** 2)).sum(0)
+    dsr = (F * 2 * D2 / sigma ** 3).sum()
+    rel = np.abs(g["Z"][src] - Zr[src]) / Zr[src]
+    assert rel.max() < 1e-5
+    _close(g["dpos"], dX, "theta0 dL/dx")
+    assert g["ds"] == pytest.approx(dsr, rel=1e-5)
+    g["tree"].free()
+
+
+def test_autograd_function():
+    w = uniform_cube(20000, 2000.0, seed=9)
+    pos = torch.tensor(w.pos, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    sigma = torch.tensor(w.sigma, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    tree = msp.build_octree(pos.detach(), w.box_min, w.box_edge)
+    msp.update_vacant_counts(tree, T(w.vac_exc, torch.int32), T(w.vac_inh, torch.int32))
+    ty, va = T(w.neuron_type, torch.uint8), T(w.vac_axon, torch.int32)
+    Z = msp.attraction(pos, sigma, tree, ty, va, 0.3)
+    src = va > 0
+    loss = torch.log(Z[src].double()).sum()
+    loss.backward()
+    gZ = torch.where(src, 1.0 / torch.where(src, Z.detach(), torch.ones_like(Z)),
+                     torch.zeros_like(Z))
+    dpos, ds = msp.attraction_bwd(tree, ty, va, w.sigma, 0.3, gZ)
+    assert torch.allclose(pos.grad, dpos.double(), rtol=1e-5, atol=1e-9)
+    assert float(sigma.grad) == pytest.approx(float(ds), rel=1e-6)
+    tree.free()

@@ -432,14 +432,10 @@ def test_attraction_finite_differences():
     rng = np.random.default_rng(0)
     for _ in range(12):
         i, a = int(rng.integers(0, w.n)), int(rng.integers(0, 3))
-        p = w.pos.copy(); p[i, a] += h
-        m = w.pos.copy(); m[i, a] -= h
-        fd = (t.attraction_frozen(w.neuron_type, w.vac_axon, sigma, theta, p)
-              - t.attraction_frozen(w.neuron_type, w.vac_axon, sigma, theta, m)) / (2 * h)
-        assert fd == pytest.approx(dX[i, a], rel=1e-5, abs=1e-9)
-    fd = (t.attraction_frozen(w.neuron_type, w.vac_axon, sigma + h, theta, w.pos)
-          - t.attraction_frozen(w.neuron_type, w.vac_axon, sigma - h, theta, w.pos)) / (2 * h)
-    assert fd == pytest.approx(ds, rel=1e-6)
+        fd = t.frozen_derivative(w.neuron_type, w.vac_axon, sigma, theta, h, coord=(i, a))
+        assert fd == pytest.approx(dX[i, a], rel=1e-6, abs=1e-12)
+    fd = t.frozen_derivative(w.neuron_type, w.vac_axon, sigma, theta, h)
+    assert fd == pytest.approx(ds, rel=1e-7)
 
 
 # --------------------------------------------------------------------------- resume
