@@ -159,8 +159,21 @@ __global__ void b_check_k(BatchDev B, int64_t total) {
   const int s = find_sim(B.nbase, B.nsims, g);
   const int64_t i = g - B.nbase[s];
   const SimDesc& d = B.sims[s];
-  if (d.vac_axon[i] < 0 || d.type[i] > 1) atomicOr(&B.status[s], kSimInvalid);
-  if (d.vac_axon[i] > 0 && d.target == nullptr) atomicOr(&B.status[s], kSimCapacity);
+  const int32_t a = d.vac_axon[i];
+  int32_t f = (a < 0 || d.type[i] > 1) ? kSimInvalid : 0;
+  if (a > 0 && d.target == nullptr) f |= kSimCapacity;
+  // one atomic per wave and flag where the wave's lanes share a simulation (the
+  // usual case); a wave that straddles two simulations reports lane by lane
+  const int s0 = __builtin_amdgcn_readfirstlane(s);
+  if (__all(s == s0)) {
+    const bool inv = __ballot((f & kSimInvalid) != 0) != 0;
+    const bool cap = __ballot((f & kSimCapacity) != 0) != 0;
+    const int first = __ffsll((unsigned long long)__ballot(1)) - 1;
+    if ((inv || cap) && (int)(threadIdx.x & (kWave - 1)) == first)
+      atomicOr(&B.status[s0], (inv ? kSimInvalid : 0) | (cap ? kSimCapacity : 0));
+  } else if (f) {
+    atomicOr(&B.status[s], f);
+  }
 }
 
 struct FlatAxon {               // vac_axon of flat neuron g (by id), clamped at 0

@@ -52,13 +52,22 @@ struct SearchArgs {
 // order (bitwise equal prefix sums).
 constexpr double kMaxY = kUnderflowX * kLog2e;   // exp(-x) == 0 in float64 beyond this
 
+// Barnes-Hut acceptance of an inner node at depth dep (edge L 2^-dep) seen from
+// squared distance d2: (L 2^-dep)^2 < theta^2 d2, evaluated as L^2 < theta^2 d2 4^dep
+// (scaling by a power of two is exact, so both forms decide identically).
+// `meta_hi` = meta >> (kSkipBits - 1): its bits 1..5 are 2*dep for an inner node.
+__device__ __forceinline__ bool bh_accept(double L2, double theta2, double d2, uint32_t meta_hi) {
+  return L2 < ldexp(theta2 * d2, (int)(meta_hi & 62u));
+}
+
+// Branch-free (the walks evaluate it for every lane and mask the result).
 __device__ __forceinline__ double kernel_weight(int32_t v, double d2, double k2) {
-  const double y = d2 * k2;
-  if (!(y <= kMaxY)) return 0.0;
+  const double y = fmin(d2 * k2, 2048.0);         // keeps the integer part in range
   const double fr = __builtin_amdgcn_fract(y);
   const int fl = (int)y;                          // truncation = floor for y >= 0
   const double mant = (double)__builtin_amdgcn_exp2f(-(float)fr);
-  return ldexp((double)v * mant, -fl);
+  const double w = ldexp((double)v * mant, -fl);
+  return y <= kMaxY ? w : 0.0;
 }
 
 struct SumPass {
@@ -154,9 +163,7 @@ __device__ void expand_range(const SearchArgs& A, const NodeRec* __restrict__ R,
       continue;
     }
     const double d2 = dist2(xi, yi, zi, r.x, r.y, r.z);
-    const int dep = (int)((r.meta >> kSkipBits) & 31u);
-    const double l2 = ldexp(A.L2, -2 * dep);       // (L 2^-k)^2, exact scaling
-    if (l2 < A.theta2 * d2) {
+    if (bh_accept(A.L2, A.theta2, d2, r.meta >> (kSkipBits - 1))) {
       if (f(x, false, r.v, d2)) return;
       x = sk;
     } else {

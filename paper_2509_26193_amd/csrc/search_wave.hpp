@@ -50,6 +50,25 @@ __device__ __forceinline__ cptr<T> as_const(const T* p) {
   return (cptr<T>)(p);
 }
 
+// Record x as one 32-byte scalar load with a 32-bit byte offset in a register (no
+// per-node 64-bit address arithmetic; the empty asm keeps the compiler from widening
+// the offset computation to 64 bits).
+typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ NodeRec load_rec_u(cptr<NodeRec> R, uint32_t x) {
+  uint32_t off = x * (uint32_t)sizeof(NodeRec);
+  asm("" : "+s"(off));
+  const u32x8 w =
+      *(cptr<u32x8>)((const __attribute__((address_space(4))) char*)R + off);
+  NodeRec r;
+  r.x = __builtin_bit_cast(double, ((uint64_t)w[1] << 32) | w[0]);
+  r.y = __builtin_bit_cast(double, ((uint64_t)w[3] << 32) | w[2]);
+  r.z = __builtin_bit_cast(double, ((uint64_t)w[5] << 32) | w[4]);
+  r.v = (int32_t)w[6];
+  r.meta = w[7];
+  return r;
+}
+
 __device__ __forceinline__ NodeRec load_rec(cptr<NodeRec> R, int64_t x) {
   NodeRec r;
   r.x = R[x].x;
@@ -104,87 +123,84 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
     int32_t x = 1;
     int32_t me = valid ? 0 : 0x7FFFFFFF;     // padding lanes are never active
     int imask = __builtin_amdgcn_readfirstlane(step0 - 1);   // interval - 1 (power of 2)
-    NodeRec cur = load_rec(R, x);
+    NodeRec cur = load_rec_u(R, 1);
     while (x < end) {
-      if ((steps & imask) == 0) {
-        if (nck == kCkpt) {                   // full: keep every other checkpoint
+      // checkpoints at multiples of the interval; a full buffer keeps every other one
+      // and doubles the interval
+      if (nck == kCkpt) {
 #pragma unroll 1
-          for (int k = 1; k < kCkpt / 2; ++k) {
-            ckP[k * kWave] = ckP[2 * k * kWave];
-            ckme[k * kWave] = ckme[2 * k * kWave];
-            if (lane == 0) ckx[k] = ckx[2 * k];
-          }
-          nck = kCkpt / 2;
-          imask = __builtin_amdgcn_readfirstlane(2 * imask + 1);
+        for (int k = 1; k < kCkpt / 2; ++k) {
+          ckP[k * kWave] = ckP[2 * k * kWave];
+          ckme[k * kWave] = ckme[2 * k * kWave];
+          if (lane == 0) ckx[k] = ckx[2 * k];
         }
-        if ((steps & imask) == 0) {
-          ckP[nck * kWave] = sum.Z;
-          ckme[nck * kWave] = me;
-          if (lane == 0) ckx[nck] = x;
-          nck = __builtin_amdgcn_readfirstlane(nck + 1);
-        }
+        nck = kCkpt / 2;
+        imask = __builtin_amdgcn_readfirstlane(2 * imask + 1);
       }
-      ++steps;
-      // scalar loads may complete out of order, so the compiler can only wait for
-      // "all of them": wait for this node's record here, before the next ones are
-      // requested, so the wait below them is already satisfied
-      __builtin_amdgcn_s_waitcnt(0xC07F);    // lgkmcnt(0)
-      const bool active = x >= me;
-      if (DIAG && active) c0.visits += 1;
-      const uint32_t meta = cur.meta;
-      // the next node is x + 1 (descend, or a leaf's successor) or the subtree end:
-      // fetch both now so the loads overlap this node's arithmetic (the record array
-      // ends with a sentinel, so both indices, at most N, are in bounds)
-      const NodeRec nx = load_rec(R, x + 1);
-      if (meta & kLeafBit) {
-        if (cur.v != 0) {
-          if (!(meta & kBucketBit)) {
-            const int32_t id = (int32_t)(meta & kIdMask);
-            if (active && id != i) sum(id, true, cur.v, dist2(xi, yi, zi, cur.x, cur.y, cur.z));
-          } else {
-            const cptr<int32_t> vs = as_const(A.vs[t]);
-            const cptr<int32_t> order = as_const(A.order);
-            const cptr<double> pos = as_const(A.pos);
-            const int32_t pe = as_const(A.nend)[x];
-            for (int32_t p = as_const(A.nbeg)[x]; p < pe; ++p) {
-              const int32_t id = order[p];
-              const int32_t v = vs[p];
-              if (active && id != i && v != 0)
-                sum(id, true, v, dist2(xi, yi, zi, pos[3 * (int64_t)id], pos[3 * (int64_t)id + 1],
-                                       pos[3 * (int64_t)id + 2]));
+      if ((steps & imask) == 0) {
+        ckP[nck * kWave] = sum.Z;
+        ckme[nck * kWave] = me;
+        if (lane == 0) ckx[nck] = x;
+        nck = __builtin_amdgcn_readfirstlane(nck + 1);
+      }
+      const int chunk = (imask + 1) - (steps & imask);   // steps to the next multiple
+      int left = chunk;
+      do {
+        // one node: uniform branches on its kind, per-lane decisions as lane masks, the
+        // weight evaluated on every lane and added where the lane takes the entry
+        const uint32_t meta = cur.meta;
+        const bool active = x >= me;
+        if (DIAG && active) c0.visits += 1;
+        int32_t next = x + 1;
+        if ((int32_t)meta < 0) {                               // leaf
+          if (cur.v != 0) {
+            if (!(meta & kBucketBit)) {
+              const int32_t id = (int32_t)(meta & kIdMask);
+              const double w = kernel_weight(cur.v, dist2(xi, yi, zi, cur.x, cur.y, cur.z), A.k2);
+              sum.Z = sum.Z + ((active && id != i) ? w : 0.0);
+            } else {                            // several neurons at one finest cell
+              const cptr<int32_t> vs = as_const(A.vs[t]);
+              const cptr<int32_t> order = as_const(A.order);
+              const cptr<double> pos = as_const(A.pos);
+              const int32_t pe = as_const(A.nend)[x];
+              for (int32_t p = as_const(A.nbeg)[x]; p < pe; ++p) {
+                const int32_t id = order[p];
+                const int32_t v = vs[p];
+                if (v == 0) continue;
+                const double w = kernel_weight(
+                    v, dist2(xi, yi, zi, pos[3 * (int64_t)id], pos[3 * (int64_t)id + 1],
+                             pos[3 * (int64_t)id + 2]),
+                    A.k2);
+                sum.Z = sum.Z + ((active && id != i) ? w : 0.0);
+              }
             }
           }
+        } else {
+          int32_t sk = (int32_t)(meta & kSkipMask);
+          sk = sk > x ? sk : x + 1;
+          next = sk;
+          if (cur.v != 0) {
+            const double d2 = dist2(xi, yi, zi, cur.x, cur.y, cur.z);
+            // li in [x, sk) (padding lanes have li = -1, far above sk - x unsigned)
+            const bool contains = (uint32_t)(li - x) < (uint32_t)(sk - x);
+            const bool far = !contains && bh_accept(A.L2, A.theta2, d2, meta >> (kSkipBits - 1));
+            const bool take = active && far;
+            const bool open = active && !far;
+            const double w = kernel_weight(cur.v, d2, A.k2);
+            sum.Z = sum.Z + (take ? w : 0.0);
+            me = take ? sk : me;
+            if (DIAG && open) c0.opens += 1;
+            if (__any(open)) next = x + 1;
+          }
         }
-        x = x + 1;
-        cur = nx;
-        continue;
-      }
-      int32_t sk = (int32_t)(meta & kSkipMask);
-      sk = sk > x ? sk : x + 1;
-      sk = sk < end ? sk : end;
-      const NodeRec ns = load_rec(R, sk);
-      if (cur.v == 0) {
-        x = sk;
-        cur = ns;
-        continue;
-      }
-      const bool contains = li >= x && li < sk;
-      const double d2 = dist2(xi, yi, zi, cur.x, cur.y, cur.z);
-      const int dep = (int)((meta >> kSkipBits) & 31u);
-      const bool acc_ok = ldexp(A.L2, -2 * dep) < A.theta2 * d2;
-      const bool open = active && (contains || !acc_ok);
-      if (active && !contains && acc_ok) {
-        sum(x, false, cur.v, d2);
-        me = sk;
-      }
-      if (DIAG && open) c0.opens += 1;
-      if (__any(open)) {
-        x = x + 1;
-        cur = nx;
-      } else {
-        x = sk;
-        cur = ns;
-      }
+        x = next < end ? next : end;
+        cur = load_rec_u(R, (uint32_t)x);     // index end = N: the sentinel record
+        if (x >= end) {
+          --left;
+          break;
+        }
+      } while (--left > 0);
+      steps += chunk - left;
     }
   }
   if (lane == 0) W.nck[tile] = nck;
