@@ -71,13 +71,17 @@ def sweep_bytes(cnt, off):
 
 
 def kernel_sources_hash():
-    """Hash of the search kernel sources: measured HBM traffic is reported only for
-    the kernel version it was measured on."""
+    """Hash of the search kernel sources with comments and whitespace removed: measured
+    HBM traffic is reported only for the kernel code it was measured on."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("search.hpp", "search_wave.hpp", "common.hpp"):
-        with open(os.path.join(ROOT, "paper_2509_26193_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2509_26193_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 
@@ -217,6 +221,42 @@ def bench_batched(msp, torch, reps=5):
                 speedup=tp / tb, identical_targets=bool(same))
 
 
+def bench_plasticity(msp, torch, updates=3):
+    """The first updates of the 100-update workload (2^23 neurons uniform in a 20,000 um
+    cube): the octree is built once (positions are fixed); each update refreshes the
+    vacancies, searches and commits on the device. The host-side element growth and
+    synapse deletion between updates is not timed."""
+    from synth_inputs import config_large, plasticity_init, plasticity_record, plasticity_step
+    dev = torch.device("cuda:0")
+    T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    w = config_large()
+    tree = msp.build_octree(T(w.pos, torch.float64), w.box_min, w.box_edge)
+    ty = T(w.neuron_type, torch.uint8)
+    state = plasticity_init(w)
+    vac = (w.vac_axon, w.vac_exc, w.vac_inh)
+    per = []
+    for step in range(updates):
+        ga, ge, gi = (T(v, torch.int32) for v in vac)
+        S = int(np.maximum(vac[0], 0).sum())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        msp.update_vacant_counts(tree, ge, gi)
+        tgt, off = msp.find_targets(tree, ty, ga, w.sigma, w.theta, w.seed, step)
+        res = msp.commit_synapses(tgt, off, ty, ga, ge, gi, w.seed, step, syn_capacity=S)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        m = int(res["n_formed"])
+        per.append(dict(update=step, searches=S, formed=m, ms=dt * 1e3, searches_per_s=S / dt))
+        log(f"plasticity update {step}: {S} searches, {m} formed, {dt * 1e3:.1f} ms")
+        plasticity_record(state, res["syn_src"].cpu().numpy(), res["syn_tgt"].cpu().numpy(),
+                          res["syn_type"].cpu().numpy())
+        vac = plasticity_step(state, w.neuron_type, w.seed, step)
+    tree.free()
+    return dict(workload=f"plasticity_{w.n}_uniform_20000um", updates=per,
+                note="refresh + search + commit per update on a fixed octree; the host growth "
+                     "and deletion between updates are not timed")
+
+
 def bench_attraction(msp, torch, reps=5):
     """Expected attraction forward and adjoint (dL/dx, dL/dsigma of sum log Z) on 2^18
     neurons in a 5000 um cube."""
@@ -262,10 +302,12 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain-copy kernel used to scale HBM counters")
     ap.add_argument("--no-also", action="store_true",
-                    help="skip the 2^20-neuron and batched measurements")
+                    help="skip the 2^20-neuron, batched, attraction and multi-update measurements")
+    ap.add_argument("--updates", type=int, default=3,
+                    help="updates of the multi-update workload measured with the others")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: this benchmark runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding of the search is a design note, not implemented)",
               file=sys.stderr)
         sys.exit(2)
@@ -397,6 +439,9 @@ def main():
         also["batched"] = bench_batched(msp, torch)
         log("also: attraction")
         also["attraction"] = bench_attraction(msp, torch)
+        if args.updates > 0:
+            log(f"also: {args.updates} updates of the multi-update workload")
+            also["plasticity"] = bench_plasticity(msp, torch, args.updates)
         out["also"] = also
     if not args.no_cpu:
         threads = args.cpu_threads or min(os.cpu_count() or 1, 64)

@@ -11,7 +11,8 @@
 //     simulation domain" (Morton-indexed cells).
 //   * aggregation: Sec. III-B, "Division of work" paragraph (leaf = neuron position
 //     and count; inner node = sum of children, position = weighted average of the
-//     children; refreshed bottom-up before each connectivity update; Alg. 1 first lines).
+//     children; refreshed bottom-up before each connectivity update, which is how Alg. 1
+//     begins).
 //   * search: Sec. III-A "Update of synapses" (each vacant axonal element scores
 //     partners with a distance kernel and draws one) and Sec. III-B "Division of
 //     work" (acceptance test cell length / distance < theta, which always rejects the
@@ -27,7 +28,10 @@
 // Readings where the paper is silent (kernel exp(-d^2/sigma^2), strict "<", cell
 // length = cube edge L/2^k, autapses excluded, depth cap 21 with bucket leaves,
 // octant digit 4x+2y+z, draws u = top 24 bits of Philox word 0, priorities for the
-// random acceptance) are listed with the design notes of the repository.
+// random acceptance) are listed with the design notes of the repository. The paper
+// prints no value that fixes the kernel's form, so that reading is parity unpinned
+// with respect to the paper; every function here is pinned to its own definition by
+// the CPU tests (brute force, closed forms, invariants, published known answers).
 //
 // Build: g++ -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math), so every
 // expression is evaluated exactly as written, one rounding per operation.

@@ -127,11 +127,18 @@ __global__ void __launch_bounds__(kWaveBlock) search_sweep_k(BatchDev B, SweepOu
 
 // One thread per worklist slot (source): its elements' draws and restarts. The 64
 // slots of a wavefront form one tile, so the simulation is uniform across the wave.
+// The blocks that run on die d (block % 8 == d) take the d-th eighth of the
+// Morton-ordered tile range, as the sweep does: neighbouring sources re-walk the same
+// records, and those stay in that die's L2. The grid holds draw_grid_for() blocks.
 template <bool DIAG>
 __global__ void __launch_bounds__(256) search_draw_k(BatchDev B, SweepOut W) {
-  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t tile = slot / kWave;
-  if (tile >= *W.tile_count) return;
+  const int ntiles = *W.tile_count;
+  const int die = (int)(blockIdx.x % kXcd);
+  const int64_t hi = (int64_t)ntiles * (die + 1) / kXcd;
+  const int64_t tile = (int64_t)ntiles * die / kXcd +
+                       (int64_t)(blockIdx.x / kXcd) * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (tile >= hi) return;
+  const int64_t slot = tile * kWave + (threadIdx.x & (kWave - 1));
   const int sim = __builtin_amdgcn_readfirstlane(find_sim(as_const(B.tile_base), B.nsims, tile));
   const SearchArgs A = args_of(B.sims, sim, B.work);
   DiagOut D{};
@@ -347,9 +354,17 @@ inline hipError_t enqueue_prep(SearchScratch& S, int64_t total_n, hipStream_t s)
 
 // The sweep and draw launches. `sweep_blocks` persistent blocks; the draw covers
 // every possible slot (threads past the tile count return at once).
+// Draw grid: every die gets enough blocks for the largest eighth of the tile range.
+inline unsigned draw_grid_for(int64_t max_slots, int draw_block) {
+  const int64_t max_tiles = (max_slots + kWave - 1) / kWave;
+  const int64_t per_die = (max_tiles + kXcd - 1) / kXcd;
+  const int64_t tpb = draw_block / kWave;
+  return (unsigned)(kXcd * ((per_die + tpb - 1) / tpb));
+}
+
 inline hipError_t enqueue_search(SearchScratch& S, bool diag, unsigned sweep_blocks,
                                  int draw_block, hipStream_t s, hipEvent_t mid = nullptr) {
-  const unsigned draw_grid = grid_for(S.B.max_slots, draw_block);
+  const unsigned draw_grid = draw_grid_for(S.B.max_slots, draw_block);
   if (diag)
     search_sweep_k<true><<<sweep_blocks, kWaveBlock, 0, s>>>(S.B, S.W);
   else

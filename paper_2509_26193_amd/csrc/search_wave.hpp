@@ -9,9 +9,8 @@
 //     own depth-first walk, in the same order;
 //   - the wave descends into x if any active lane opens it, otherwise jumps over
 //     the subtree.
-// It produces each source's level-0 normaliser (sum and shift) and, every
-// `interval` wave steps, a checkpoint per lane (running sum, shift, mask_end) with
-// the wave position.
+// It produces each source's level-0 normaliser Z and, every `interval` wave steps,
+// a checkpoint per lane (running sum, mask_end) with the wave position.
 //
 // search_draw_k: one thread per source and element j: T = u Z, then the source's
 // own walk restarts from the last checkpoint whose running sum does not exceed T

@@ -147,6 +147,19 @@ class PlasticityState:
     syn_tgt: np.ndarray        # int64 [m]
     syn_type: np.ndarray       # uint8 [m]
 
+    def copy(self) -> "PlasticityState":
+        return PlasticityState(self.z.copy(), self.bound.copy(), self.syn_src.copy(),
+                               self.syn_tgt.copy(), self.syn_type.copy())
+
+    def save(self, path) -> None:
+        np.savez(path, z=self.z, bound=self.bound, syn_src=self.syn_src, syn_tgt=self.syn_tgt,
+                 syn_type=self.syn_type)
+
+    @staticmethod
+    def load(path) -> "PlasticityState":
+        with np.load(path) as f:
+            return PlasticityState(f["z"], f["bound"], f["syn_src"], f["syn_tgt"], f["syn_type"])
+
 
 def plasticity_init(w: Workload) -> PlasticityState:
     z = np.stack([w.vac_axon, w.vac_exc, w.vac_inh]).astype(np.float64)
@@ -154,63 +167,73 @@ def plasticity_init(w: Workload) -> PlasticityState:
                            np.zeros(0, np.int64), np.zeros(0, np.uint8))
 
 
-def plasticity_step(state: PlasticityState, neuron_type, rng, delete_frac=0.1):
-    """Draw Ca ~ N(0.7, 0.1), grow/retract elements, delete 10% of synapses at random
-    (each frees one axonal and one dendritic element), then return the vacant counts
-    (axon, exc, inh) as int32 for the next update."""
+def _unbind(state: PlasticityState, gone: np.ndarray) -> None:
+    """Remove the synapses flagged in `gone`: each frees one axonal element of its
+    source and one dendritic element (of the synapse's type) of its target."""
+    if not gone.any():
+        return
     n = state.z.shape[1]
-    for k in range(3):
-        ca = rng.normal(0.7, 0.1, size=n)
-        state.z[k] = np.maximum(state.z[k] + growth_delta(ca), 0.0)
-    m = state.syn_src.size
-    n_del = int(round(delete_frac * m))
-    keep = np.ones(m, dtype=bool)
-    if n_del > 0:
-        keep[rng.choice(m, size=n_del, replace=False)] = False
-    # deleting a synapse frees one axonal element of the source and one dendritic
-    # element (of the synapse's type) of the target
-    gone = ~keep
-    np.subtract.at(state.bound[0], state.syn_src[gone], 1)
-    tgt_kind = 1 + state.syn_type[gone].astype(np.int64)
-    for kind in (1, 2):
-        sel = tgt_kind == kind
-        np.subtract.at(state.bound[kind], state.syn_tgt[gone][sel], 1)
+    state.bound[0] -= np.bincount(state.syn_src[gone], minlength=n)
+    ty = state.syn_type[gone]
+    tg = state.syn_tgt[gone]
+    state.bound[1] -= np.bincount(tg[ty == 0], minlength=n)
+    state.bound[2] -= np.bincount(tg[ty == 1], minlength=n)
+    keep = ~gone
     state.syn_src, state.syn_tgt, state.syn_type = (state.syn_src[keep], state.syn_tgt[keep],
                                                     state.syn_type[keep])
-    # a negative surplus retracts bound elements: break random synapses of that neuron
+
+
+def plasticity_step(state: PlasticityState, neuron_type, seed: int, step: int, delete_frac=0.1):
+    """Host-side change of the network between update `step` and the next: Ca ~
+    N(0.7, 0.1) per neuron and element kind, growth/retraction of the continuous element
+    counts, deletion of 10 % of the synapses at random, then retraction of bound
+    elements where a count fell below the bound ones (random synapses of that neuron
+    break). Returns the vacant counts (axon, exc, inh) as int32 for the next update.
+
+    The random numbers come from a generator seeded by (seed, step) alone, so a run
+    resumed from a saved state continues exactly as an uninterrupted one."""
+    rng = np.random.default_rng([int(seed), 0x5EED, int(step)])
+    n = state.z.shape[1]
+    ca = rng.normal(0.7, 0.1, size=(3, n))
+    state.z = np.maximum(state.z + growth_delta(ca), 0.0)
+    m = state.syn_src.size
+    gone = np.zeros(m, dtype=bool)
+    n_del = int(round(delete_frac * m))
+    if n_del > 0:
+        gone[rng.choice(m, size=n_del, replace=False)] = True
+    _unbind(state, gone)
     cap = np.floor(state.z).astype(np.int64)
     for kind in range(3):
-        over = np.nonzero(state.bound[kind] > cap[kind])[0]
-        for nid in over:
-            excess = int(state.bound[kind][nid] - cap[kind][nid])
-            if kind == 0:
-                cand = np.nonzero(state.syn_src == nid)[0]
-            else:
-                cand = np.nonzero((state.syn_tgt == nid) & (state.syn_type == kind - 1))[0]
-            drop = rng.choice(cand, size=min(excess, cand.size), replace=False)
-            keep = np.ones(state.syn_src.size, dtype=bool)
-            keep[drop] = False
-            s, g, ty = state.syn_src[drop], state.syn_tgt[drop], state.syn_type[drop]
-            np.subtract.at(state.bound[0], s, 1)
-            for kk in (1, 2):
-                sel = (1 + ty.astype(np.int64)) == kk
-                np.subtract.at(state.bound[kk], g[sel], 1)
-            state.syn_src, state.syn_tgt, state.syn_type = (state.syn_src[keep],
-                                                            state.syn_tgt[keep],
-                                                            state.syn_type[keep])
+        excess = state.bound[kind] - cap[kind]
+        if not (excess > 0).any():
+            continue
+        owner = state.syn_src if kind == 0 else state.syn_tgt
+        sel = excess[owner] > 0
+        if kind > 0:
+            sel &= state.syn_type == kind - 1
+        idx = np.nonzero(sel)[0]
+        pri = rng.random(idx.size)
+        o = np.lexsort((pri, owner[idx]))          # by owner, then random priority
+        idx = idx[o]
+        own = owner[idx]
+        start = np.r_[0, np.nonzero(own[1:] != own[:-1])[0] + 1]
+        rank = np.arange(own.size) - np.repeat(start, np.diff(np.r_[start, own.size]))
+        gone = np.zeros(state.syn_src.size, dtype=bool)
+        gone[idx[rank < excess[own]]] = True
+        _unbind(state, gone)
     vac = np.maximum(np.floor(state.z).astype(np.int64) - state.bound, 0).astype(np.int32)
     return vac[0].copy(), vac[1].copy(), vac[2].copy()
 
 
 def plasticity_record(state: PlasticityState, syn_src, syn_tgt, syn_type):
     """Add newly formed synapses to the host state."""
+    n = state.z.shape[1]
     syn_src = np.asarray(syn_src, np.int64)
     syn_tgt = np.asarray(syn_tgt, np.int64)
     syn_type = np.asarray(syn_type, np.uint8)
-    np.add.at(state.bound[0], syn_src, 1)
-    for kind in (1, 2):
-        sel = (1 + syn_type.astype(np.int64)) == kind
-        np.add.at(state.bound[kind], syn_tgt[sel], 1)
+    state.bound[0] += np.bincount(syn_src, minlength=n)
+    state.bound[1] += np.bincount(syn_tgt[syn_type == 0], minlength=n)
+    state.bound[2] += np.bincount(syn_tgt[syn_type == 1], minlength=n)
     state.syn_src = np.concatenate([state.syn_src, syn_src])
     state.syn_tgt = np.concatenate([state.syn_tgt, syn_tgt])
     state.syn_type = np.concatenate([state.syn_type, syn_type])
