@@ -257,6 +257,54 @@ def bench_plasticity(msp, torch, updates=3):
                      "and deletion between updates are not timed")
 
 
+def study_complexity(msp, torch, log2_ns=(12, 14, 16, 18, 20, 22, 23),
+                     thetas=(0.2, 0.3, 0.4, 0.5)):
+    """Visits per search and search throughput over n and theta at the density of the
+    2^23-neuron workload (Sec. II: Barnes-Hut with theta > 0 needs O(log n) work per
+    search). One JSON line per point, then a markdown table on stderr."""
+    from synth_inputs import uniform_cube
+    dev = torch.device("cuda:0")
+    T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    rows = []
+    for lg in log2_ns:
+        n = 1 << lg
+        edge = 20000.0 * (n / float(1 << 23)) ** (1.0 / 3.0)
+        w = uniform_cube(n, edge, seed=42)
+        tree = msp.build_octree(T(w.pos, torch.float64), w.box_min, w.box_edge)
+        msp.update_vacant_counts(tree, T(w.vac_exc, torch.int32), T(w.vac_inh, torch.int32))
+        ty, va = T(w.neuron_type, torch.uint8), T(w.vac_axon, torch.int32)
+        S = w.searches
+        buf = torch.empty(max(S, 1), dtype=torch.int32, device=dev)
+        for theta in thetas:
+            _, off, _, _, cnt = msp.find_targets(tree, ty, va, w.sigma, theta, w.seed, 0,
+                                                 target_out=buf, diag=True, counters=True)
+            v = cnt["visits"].double().mean().item()
+            v0 = cnt["visits0"].double().mean().item()
+            ws = int(cnt["wave_steps"].item())
+            v0h, offh = cnt["visits0"].cpu().numpy(), off.cpu().numpy()
+            first = offh[:-1][np.diff(offh) > 0]          # one search per source
+            lane_visits = int((v0h[first].astype(np.int64) - 1).sum())
+            ms = []
+            for _ in range(3):
+                tm = {}
+                msp.find_targets(tree, ty, va, w.sigma, theta, w.seed, 0, target_out=buf, timing=tm)
+                ms.append(tm["kernel_ms"])
+            t = float(np.median(ms))
+            r = dict(study="complexity", n=n, edge_um=round(edge, 1), theta=theta, searches=S,
+                     visits_per_search=v, level0_visits_per_search=v0,
+                     lane_utilisation=lane_visits / max(1, 64 * ws), search_kernels_ms=t,
+                     searches_per_s=S / (t * 1e-3))
+            rows.append(r)
+            print(json.dumps(r), flush=True)
+        tree.free()
+    log("| n | theta | visits/search | level-0 visits | lane utilisation | search ms | M searches/s |")
+    log("|---:|---:|---:|---:|---:|---:|---:|")
+    for r in rows:
+        log(f"| {r['n']} | {r['theta']} | {r['visits_per_search']:.0f} | "
+            f"{r['level0_visits_per_search']:.0f} | {r['lane_utilisation']:.2f} | "
+            f"{r['search_kernels_ms']:.2f} | {r['searches_per_s'] / 1e6:.1f} |")
+
+
 def bench_attraction(msp, torch, reps=5):
     """Expected attraction forward and adjoint (dL/dx, dL/dsigma of sum log Z) on 2^18
     neurons in a 5000 um cube."""
@@ -303,6 +351,8 @@ def main():
                     help="only run the plain-copy kernel used to scale HBM counters")
     ap.add_argument("--no-also", action="store_true",
                     help="skip the 2^20-neuron, batched, attraction and multi-update measurements")
+    ap.add_argument("--study", choices=["complexity"], default=None,
+                    help="instead of the benchmark: visits and throughput over n and theta")
     ap.add_argument("--updates", type=int, default=3,
                     help="updates of the multi-update workload measured with the others")
     args = ap.parse_args()
@@ -314,6 +364,11 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.study == "complexity":
+        import torch
+        import paper_2509_26193_amd as msp
+        study_complexity(msp, torch)
         return
 
     import torch

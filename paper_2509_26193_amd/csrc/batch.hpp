@@ -96,7 +96,7 @@ __device__ __forceinline__ SearchArgs args_of(const SimDesc* sims, int s, const 
 // Persistent waves pull 64-source tiles: first from the Morton range of their own
 // die (neighbouring sources share upper-tree nodes in that die's L2), then from the
 // other dies' ranges. A tile's simulation is found from the tile bases.
-template <bool DIAG>
+template <bool DIAG, int SLOTS>
 __global__ void __launch_bounds__(kWaveBlock) search_sweep_k(BatchDev B, SweepOut W) {
   const int lane = threadIdx.x & (kWave - 1);
   const int home = blockIdx.x % kXcd;
@@ -118,27 +118,20 @@ __global__ void __launch_bounds__(kWaveBlock) search_sweep_k(BatchDev B, SweepOu
     const int sim = __builtin_amdgcn_readfirstlane(
         find_sim(as_const(B.tile_base), B.nsims, (int64_t)tile));
     const SearchArgs A = args_of(B.sims, sim, B.work);
-    const int steps = sweep_tile<DIAG>(A, W, tile, lane, step0);
-    // next interval: about kCkpt checkpoints over a sweep as long as this one
+    const int steps = sweep_tile<DIAG, SLOTS>(A, W, tile, lane, step0);
+    // next interval: about SLOTS checkpoints over a sweep as long as this one
     step0 = kCkptStepMin;
-    while (step0 * kCkpt < steps) step0 <<= 1;
+    while (step0 * SLOTS < steps) step0 <<= 1;
   }
 }
 
 // One thread per worklist slot (source): its elements' draws and restarts. The 64
 // slots of a wavefront form one tile, so the simulation is uniform across the wave.
-// The blocks that run on die d (block % 8 == d) take the d-th eighth of the
-// Morton-ordered tile range, as the sweep does: neighbouring sources re-walk the same
-// records, and those stay in that die's L2. The grid holds draw_grid_for() blocks.
-template <bool DIAG>
+template <bool DIAG, int SLOTS>
 __global__ void __launch_bounds__(256) search_draw_k(BatchDev B, SweepOut W) {
-  const int ntiles = *W.tile_count;
-  const int die = (int)(blockIdx.x % kXcd);
-  const int64_t hi = (int64_t)ntiles * (die + 1) / kXcd;
-  const int64_t tile = (int64_t)ntiles * die / kXcd +
-                       (int64_t)(blockIdx.x / kXcd) * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (tile >= hi) return;
-  const int64_t slot = tile * kWave + (threadIdx.x & (kWave - 1));
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tile = slot / kWave;
+  if (tile >= *W.tile_count) return;
   const int sim = __builtin_amdgcn_readfirstlane(find_sim(as_const(B.tile_base), B.nsims, tile));
   const SearchArgs A = args_of(B.sims, sim, B.work);
   DiagOut D{};
@@ -151,7 +144,7 @@ __global__ void __launch_bounds__(256) search_draw_k(BatchDev B, SweepOut W) {
     D.visits0 = d->diag.visits0;
     D.opens0 = d->diag.opens0;
   }
-  draw_slot<DIAG>(A, D, W, slot);
+  draw_slot<DIAG, SLOTS>(A, D, W, slot);
 }
 
 __global__ void fill_i32_k(int32_t* p, int64_t n, int32_t v) {
@@ -272,7 +265,12 @@ struct ScratchSizes {
   size_t ea, p, tile_base, status, work, Z, v, nck, ckx, ckP, ckme, counters, scan, total;
 };
 
-inline ScratchSizes scratch_sizes(int64_t total_n, int nsims) {
+// Checkpoint bytes per slot of a tile: the wave position and, per lane, the running
+// sum and the mask end.
+constexpr size_t kCkptSlotBytes = sizeof(int32_t) + kWave * (sizeof(double) + sizeof(int32_t));
+
+// `slots` checkpoint slots per tile (0: no checkpoints, for launches without draws).
+inline ScratchSizes scratch_sizes(int64_t total_n, int nsims, int slots) {
   ScratchSizes z;
   const int64_t mt = max_tiles_for(total_n, nsims);
   const int64_t ms = mt * kWave;
@@ -284,9 +282,9 @@ inline ScratchSizes scratch_sizes(int64_t total_n, int nsims) {
   z.Z = align_up(sizeof(double) * ms);
   z.v = align_up(sizeof(int32_t) * ms);
   z.nck = align_up(sizeof(int32_t) * mt);
-  z.ckx = align_up(sizeof(int32_t) * mt * kCkpt);
-  z.ckP = align_up(sizeof(double) * mt * kCkpt * kWave);
-  z.ckme = align_up(sizeof(int32_t) * mt * kCkpt * kWave);
+  z.ckx = align_up(sizeof(int32_t) * mt * slots);
+  z.ckP = align_up(sizeof(double) * mt * slots * kWave);
+  z.ckme = align_up(sizeof(int32_t) * mt * slots * kWave);
   z.counters = align_up(sizeof(int32_t) * (1 + kXcd));
   z.scan = align_up(std::max(scan_tmp_bytes<int64_t>(total_n), scan_tmp_bytes<int32_t>(total_n)));
   z.total = z.ea + 2 * z.p + z.tile_base + z.status + z.work + z.Z + 2 * z.v + z.nck + z.ckx +
@@ -294,9 +292,9 @@ inline ScratchSizes scratch_sizes(int64_t total_n, int nsims) {
   return z;
 }
 
-inline SearchScratch carve(void* base, int64_t total_n, int nsims, const SimDesc* d_sims,
-                           const int64_t* d_nbase) {
-  const ScratchSizes z = scratch_sizes(total_n, nsims);
+inline SearchScratch carve(void* base, int64_t total_n, int nsims, int slots,
+                           const SimDesc* d_sims, const int64_t* d_nbase) {
+  const ScratchSizes z = scratch_sizes(total_n, nsims, slots);
   char* p = static_cast<char*>(base);
   auto take = [&](size_t bytes) {
     char* q = p;
@@ -321,6 +319,7 @@ inline SearchScratch carve(void* base, int64_t total_n, int nsims, const SimDesc
   S.W.ck_x = reinterpret_cast<int32_t*>(take(z.ckx));
   S.W.ck_P = reinterpret_cast<double*>(take(z.ckP));
   S.W.ck_me = reinterpret_cast<int32_t*>(take(z.ckme));
+  S.W.ck_slots = slots;
   S.counters = reinterpret_cast<int32_t*>(take(z.counters));
   S.W.tile_count = S.counters;
   S.W.queue = S.counters + 1;
@@ -354,29 +353,30 @@ inline hipError_t enqueue_prep(SearchScratch& S, int64_t total_n, hipStream_t s)
 
 // The sweep and draw launches. `sweep_blocks` persistent blocks; the draw covers
 // every possible slot (threads past the tile count return at once).
-// Draw grid: every die gets enough blocks for the largest eighth of the tile range.
-inline unsigned draw_grid_for(int64_t max_slots, int draw_block) {
-  const int64_t max_tiles = (max_slots + kWave - 1) / kWave;
-  const int64_t per_die = (max_tiles + kXcd - 1) / kXcd;
-  const int64_t tpb = draw_block / kWave;
-  return (unsigned)(kXcd * ((per_die + tpb - 1) / tpb));
-}
-
 inline hipError_t enqueue_search(SearchScratch& S, bool diag, unsigned sweep_blocks,
                                  int draw_block, hipStream_t s, hipEvent_t mid = nullptr) {
-  const unsigned draw_grid = draw_grid_for(S.B.max_slots, draw_block);
-  if (diag)
-    search_sweep_k<true><<<sweep_blocks, kWaveBlock, 0, s>>>(S.B, S.W);
+  const unsigned draw_grid = grid_for(S.B.max_slots, draw_block);
+  const bool big = S.W.ck_slots == kCkptMax;
+  if (diag && big)
+    search_sweep_k<true, kCkptMax><<<sweep_blocks, kWaveBlock, 0, s>>>(S.B, S.W);
+  else if (diag)
+    search_sweep_k<true, kCkptMin><<<sweep_blocks, kWaveBlock, 0, s>>>(S.B, S.W);
+  else if (big)
+    search_sweep_k<false, kCkptMax><<<sweep_blocks, kWaveBlock, 0, s>>>(S.B, S.W);
   else
-    search_sweep_k<false><<<sweep_blocks, kWaveBlock, 0, s>>>(S.B, S.W);
+    search_sweep_k<false, kCkptMin><<<sweep_blocks, kWaveBlock, 0, s>>>(S.B, S.W);
   if (mid) {
     hipError_t e = hipEventRecord(mid, s);
     if (e != hipSuccess) return e;
   }
-  if (diag)
-    search_draw_k<true><<<draw_grid, draw_block, 0, s>>>(S.B, S.W);
+  if (diag && big)
+    search_draw_k<true, kCkptMax><<<draw_grid, draw_block, 0, s>>>(S.B, S.W);
+  else if (diag)
+    search_draw_k<true, kCkptMin><<<draw_grid, draw_block, 0, s>>>(S.B, S.W);
+  else if (big)
+    search_draw_k<false, kCkptMax><<<draw_grid, draw_block, 0, s>>>(S.B, S.W);
   else
-    search_draw_k<false><<<draw_grid, draw_block, 0, s>>>(S.B, S.W);
+    search_draw_k<false, kCkptMin><<<draw_grid, draw_block, 0, s>>>(S.B, S.W);
   return hipGetLastError();
 }
 

@@ -118,14 +118,31 @@ __global__ void __launch_bounds__(kBuildBlock) nodes_k(const uint64_t* __restric
   }
 }
 
-// Nodes per depth: block-local counts in LDS, one global atomic per depth and block.
+// Lanes of the wave holding the same depth as this lane (5-bit values; inactive
+// lanes and lanes with d < 0 are excluded).
+__device__ __forceinline__ uint64_t same_depth_lanes(int d) {
+  uint64_t peers = __ballot(d >= 0);
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    const bool bit = (d >> b) & 1;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return peers;
+}
+
+// Nodes per depth: one LDS atomic per distinct depth and wave, one global atomic per
+// depth and block.
 __global__ void __launch_bounds__(kBuildBlock) level_count_k(const uint8_t* __restrict__ depth,
                                                             int64_t N, int32_t* level_cnt) {
   __shared__ int32_t c[kMaxDepth + 1];
   if (threadIdx.x <= kMaxDepth) c[threadIdx.x] = 0;
   __syncthreads();
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x < N) atomicAdd(&c[depth[x]], 1);
+  const int d = x < N ? (int)depth[x] : -1;
+  const uint64_t peers = same_depth_lanes(d);
+  const int lane = (int)(threadIdx.x & (kWave - 1));
+  if (d >= 0 && lane == __ffsll((unsigned long long)peers) - 1) atomicAdd(&c[d], __popcll(peers));
   __syncthreads();
   if (threadIdx.x <= kMaxDepth && c[threadIdx.x]) atomicAdd(&level_cnt[threadIdx.x], c[threadIdx.x]);
 }
@@ -140,11 +157,14 @@ __global__ void __launch_bounds__(kBuildBlock) level_scatter_k(const uint8_t* __
   if (threadIdx.x <= kMaxDepth) c[threadIdx.x] = 0;
   __syncthreads();
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int d = -1, r = 0;
-  if (x < N) {
-    d = depth[x];
-    r = atomicAdd(&c[d], 1);
-  }
+  const int d = x < N ? (int)depth[x] : -1;
+  const uint64_t peers = same_depth_lanes(d);
+  const int lane = (int)(threadIdx.x & (kWave - 1));
+  const int leader = __ffsll((unsigned long long)peers) - 1;
+  int r0 = 0;
+  if (d >= 0 && lane == leader) r0 = atomicAdd(&c[d], __popcll(peers));
+  const int r = __shfl(r0, leader < 0 ? 0 : leader, kWave) +
+                __popcll(peers & ((1ull << lane) - 1ull));
   __syncthreads();
   if (threadIdx.x <= kMaxDepth && c[threadIdx.x])
     base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], c[threadIdx.x]);

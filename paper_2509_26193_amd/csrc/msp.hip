@@ -79,7 +79,8 @@ hipError_t sweep_blocks_for(int device, bool diag, int64_t max_tiles, double fra
   hipError_t e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
   if (e != hipSuccess) return e;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, diag ? (const void*)search_sweep_k<true> : (const void*)search_sweep_k<false>,
+      &per_cu,
+      diag ? (const void*)search_sweep_k<true, kCkptMax> : (const void*)search_sweep_k<false, kCkptMax>,
       kWaveBlock, 0);
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
@@ -90,6 +91,84 @@ hipError_t sweep_blocks_for(int device, bool diag, int64_t max_tiles, double fra
   *blocks_out = (unsigned)blocks;
   return hipSuccess;
 }
+
+// Checkpoint slots per tile: kCkptMax if those arrays fit in an eighth of the device's
+// memory, else kCkptMin. More slots mean shorter re-walks in the draw kernel; the
+// targets do not depend on the choice.
+hipError_t ck_slots_for(int device, int64_t total_n, int nsims, int* slots_out) {
+  static size_t mem[64] = {};
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  if (mem[device] == 0) {
+    hipDeviceProp_t p;
+    hipError_t e = hipGetDeviceProperties(&p, device);
+    if (e != hipSuccess) return e;
+    mem[device] = p.totalGlobalMem;
+  }
+  const double tiles = (double)max_tiles_for(total_n, nsims);
+  *slots_out = tiles * kCkptMax * (double)kCkptSlotBytes <= (double)(mem[device] / 8) ? kCkptMax
+                                                                                      : kCkptMin;
+  return hipSuccess;
+}
+
+// The search's working memory (worklist and checkpoints: gigabytes for millions of
+// neurons) is kept per device between calls and grown when a larger search needs more:
+// mapping it anew on every call would cost more than the search. Calls on one device
+// take turns (a mutex held for the whole call); a call's stream waits for the kernels
+// of the previous user before they are overwritten.
+struct Workspace {
+  std::mutex m;
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;      // recorded after the last user's kernels
+};
+
+Workspace& workspace(int device) {
+  static Workspace w[64];
+  return w[device];
+}
+
+class WorkspaceLease {
+ public:
+  explicit WorkspaceLease(int device) : w_(workspace(device)), lock_(w_.m) {}
+  WorkspaceLease(const WorkspaceLease&) = delete;
+  WorkspaceLease& operator=(const WorkspaceLease&) = delete;
+  hipError_t acquire(size_t bytes, hipStream_t s, void** out) {
+    hipError_t e = hipSuccess;
+    if (!w_.done && (e = hipEventCreateWithFlags(&w_.done, hipEventDisableTiming)) != hipSuccess)
+      return e;
+    if (bytes > w_.bytes) {
+      if (w_.p) {
+        if ((e = hipEventSynchronize(w_.done)) != hipSuccess) return e;
+        (void)hipFree(w_.p);
+        w_.p = nullptr;
+        w_.bytes = 0;
+      }
+      const size_t want = bytes + bytes / 8;          // some room for a larger next call
+      if ((e = hipMalloc(&w_.p, want)) != hipSuccess) {
+        (void)hipGetLastError();
+        if ((e = hipMalloc(&w_.p, bytes)) != hipSuccess) return e;
+        w_.bytes = bytes;
+      } else {
+        w_.bytes = want;
+      }
+    } else if ((e = hipStreamWaitEvent(s, w_.done, 0)) != hipSuccess) {
+      return e;
+    }
+    s_ = s;
+    leased_ = true;
+    *out = w_.p;
+    return hipSuccess;
+  }
+  ~WorkspaceLease() {
+    if (leased_) (void)hipEventRecord(w_.done, s_);
+  }
+
+ private:
+  Workspace& w_;
+  std::lock_guard<std::mutex> lock_;
+  hipStream_t s_ = nullptr;
+  bool leased_ = false;
+};
 
 }  // namespace
 
@@ -284,13 +363,17 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
           h.diag.opens0;
   }
   const int64_t hbase[2] = {0, n};
-  Temp dsim(s), dbase(s), scratch(s);
+  Temp dsim(s), dbase(s);
   MSP_HIP_TRY(dsim.alloc(sizeof(SimDesc)));
   MSP_HIP_TRY(dbase.alloc(sizeof(hbase)));
-  MSP_HIP_TRY(scratch.alloc(scratch_sizes(n, 1).total));
+  int slots = 0;
+  MSP_HIP_TRY(ck_slots_for(t->device, n, 1, &slots));
+  WorkspaceLease ws(t->device);
+  void* scratch = nullptr;
+  MSP_HIP_TRY(ws.acquire(scratch_sizes(n, 1, slots).total, s, &scratch));
   MSP_HIP_TRY(hipMemcpyAsync(dsim.p, &h, sizeof(SimDesc), hipMemcpyHostToDevice, s));
   MSP_HIP_TRY(hipMemcpyAsync(dbase.p, hbase, sizeof(hbase), hipMemcpyHostToDevice, s));
-  SearchScratch S = carve(scratch.p, n, 1, dsim.as<SimDesc>(), dbase.as<int64_t>());
+  SearchScratch S = carve(scratch, n, 1, slots, dsim.as<SimDesc>(), dbase.as<int64_t>());
   if (any) S.W.wave_steps = reinterpret_cast<unsigned long long*>(diag->wave_steps);
   MSP_HIP_TRY(enqueue_prep(S, n, s));
   int32_t status = 0, ntiles = 0;
@@ -482,6 +565,7 @@ struct msp_batch_s {
   bool staged_pending;
   unsigned sweep_blocks;
   int draw_block;
+  int ck_slots;             // checkpoint slots per tile
   bool tuned;
   hipGraphExec_t exec;
   bool captured;
@@ -592,10 +676,12 @@ msp_status msp_batch_create(const msp_sim* sims, int32_t n_sims, int32_t flags, 
   b->captured = false;
   b->cap_stream = nullptr;
   b->draw_block = 256;
+  b->ck_slots = kCkptMin;
   hipError_t e = hipHostMalloc((void**)&b->h_sims, sizeof(SimDesc) * n_sims, hipHostMallocDefault);
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_sims, sizeof(SimDesc) * n_sims);
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_nbase, sizeof(int64_t) * (n_sims + 1));
-  if (e == hipSuccess) e = hipMalloc(&b->scratch, scratch_sizes(total, n_sims).total);
+  if (e == hipSuccess) e = ck_slots_for(dev, total, n_sims, &b->ck_slots);
+  if (e == hipSuccess) e = hipMalloc(&b->scratch, scratch_sizes(total, n_sims, b->ck_slots).total);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
   b->cap_stream = nullptr;
   if (e == hipSuccess && (flags & MSP_BATCH_GRAPH))
@@ -609,7 +695,7 @@ msp_status msp_batch_create(const msp_sim* sims, int32_t n_sims, int32_t flags, 
     batch_release(b);
     return e == hipErrorOutOfMemory ? MSP_ERR_OOM : MSP_ERR_HIP;
   }
-  b->S = carve(b->scratch, total, n_sims, b->d_sims, b->d_nbase);
+  b->S = carve(b->scratch, total, n_sims, b->ck_slots, b->d_sims, b->d_nbase);
   *out = b;
   return MSP_OK;
 }
@@ -704,10 +790,11 @@ msp_status attraction(msp_octree t, const uint8_t* neuron_type, const int32_t* v
   const int64_t hbase[2] = {0, n};
   MSP_HIP_TRY(dsim.alloc(sizeof(SimDesc)));
   MSP_HIP_TRY(dbase.alloc(sizeof(hbase)));
-  MSP_HIP_TRY(scratch.alloc(scratch_sizes(n, 1).total));
+  // the worklist only: no draws, so no checkpoints
+  MSP_HIP_TRY(scratch.alloc(scratch_sizes(n, 1, 0).total));
   MSP_HIP_TRY(hipMemcpyAsync(dsim.p, &h, sizeof(SimDesc), hipMemcpyHostToDevice, s));
   MSP_HIP_TRY(hipMemcpyAsync(dbase.p, hbase, sizeof(hbase), hipMemcpyHostToDevice, s));
-  SearchScratch S = carve(scratch.p, n, 1, dsim.as<SimDesc>(), dbase.as<int64_t>());
+  SearchScratch S = carve(scratch.p, n, 1, 0, dsim.as<SimDesc>(), dbase.as<int64_t>());
   MSP_HIP_TRY(enqueue_prep(S, n, s));
   int32_t status = 0;
   MSP_HIP_TRY(hipMemcpyAsync(&status, S.B.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));

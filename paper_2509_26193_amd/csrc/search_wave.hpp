@@ -21,7 +21,8 @@
 
 namespace msp {
 
-constexpr int kCkpt = 64;          // checkpoint slots per tile
+constexpr int kCkptMax = 256;      // checkpoint slots per tile: this many where memory
+constexpr int kCkptMin = 32;       // allows, else this many (both powers of two)
 constexpr int kCkptStepMin = 16;   // smallest checkpoint interval, wave steps
 constexpr int kWaveBlock = 256;    // 4 independent waves per block
 constexpr int kXcd = 8;            // accelerator dies; workgroup b runs on die b % 8
@@ -31,9 +32,10 @@ struct SweepOut {
   int32_t* v0;                     // [slots] level-0 visits (counting launches only)
   int32_t* o0;                     // [slots] level-0 opens
   int32_t* nck;                    // [tiles] checkpoints written
-  int32_t* ck_x;                   // [tiles][kCkpt] wave position
-  double* ck_P;                    // [tiles][kCkpt][64] running sum
-  int32_t* ck_me;                  // [tiles][kCkpt][64] mask_end
+  int32_t* ck_x;                   // [tiles][ck_slots] wave position
+  double* ck_P;                    // [tiles][ck_slots][64] running sum
+  int32_t* ck_me;                  // [tiles][ck_slots][64] mask_end
+  int ck_slots;                    // checkpoint slots per tile: kCkptMax or kCkptMin
   const int32_t* tile_count;       // device scalar
   int32_t* queue;                  // [kXcd] tile counters, zero at launch
   unsigned long long* wave_steps;  // counting launches: total wave steps (nullable)
@@ -81,7 +83,7 @@ __device__ __forceinline__ NodeRec load_rec(cptr<NodeRec> R, int64_t x) {
 // `step0`: initial checkpoint interval (a power of two), chosen from the length of
 // the wave's previous sweep so that the buffer rarely has to be thinned out.
 // Returns the number of wave steps of this tile.
-template <bool DIAG>
+template <bool DIAG, int SLOTS>
 __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W, int tile,
                                           int lane, int step0) {
   const int64_t slot = (int64_t)tile * kWave + lane;
@@ -112,9 +114,9 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
     if (DIAG && valid) c0.visits = 1;
   } else {
     const int32_t end = (int32_t)(root.meta & kSkipMask);
-    int32_t* ckx = W.ck_x + (int64_t)tile * kCkpt;
-    double* ckP = W.ck_P + (int64_t)tile * kCkpt * kWave + lane;
-    int32_t* ckme = W.ck_me + (int64_t)tile * kCkpt * kWave + lane;
+    int32_t* ckx = W.ck_x + (int64_t)tile * SLOTS;
+    double* ckP = W.ck_P + (int64_t)tile * SLOTS * kWave + lane;
+    int32_t* ckme = W.ck_me + (int64_t)tile * SLOTS * kWave + lane;
     if (DIAG && valid) {
       c0.visits = 1;
       c0.opens = 1;
@@ -126,14 +128,14 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
     while (x < end) {
       // checkpoints at multiples of the interval; a full buffer keeps every other one
       // and doubles the interval
-      if (nck == kCkpt) {
+      if (nck == SLOTS) {
 #pragma unroll 1
-        for (int k = 1; k < kCkpt / 2; ++k) {
+        for (int k = 1; k < SLOTS / 2; ++k) {
           ckP[k * kWave] = ckP[2 * k * kWave];
           ckme[k * kWave] = ckme[2 * k * kWave];
           if (lane == 0) ckx[k] = ckx[2 * k];
         }
-        nck = kCkpt / 2;
+        nck = SLOTS / 2;
         imask = __builtin_amdgcn_readfirstlane(2 * imask + 1);
       }
       if ((steps & imask) == 0) {
@@ -213,7 +215,7 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
 }
 
 // The draws and restarts of the source in worklist slot `slot`.
-template <bool DIAG>
+template <bool DIAG, int SLOTS>
 __device__ __forceinline__ void draw_slot(const SearchArgs& A, const DiagOut& D, const SweepOut& W,
                                           int64_t slot) {
   const int32_t i = A.work[slot];
@@ -230,9 +232,9 @@ __device__ __forceinline__ void draw_slot(const SearchArgs& A, const DiagOut& D,
   const int nck = W.nck[tile];
   const NodeRec root = R[0];             // Z > 0 implies an inner root
   const int32_t end = (int32_t)(root.meta & kSkipMask);
-  const int32_t* ckx = W.ck_x + tile * kCkpt;
-  const double* ckP = W.ck_P + tile * kCkpt * kWave + lane;
-  const int32_t* ckme = W.ck_me + tile * kCkpt * kWave + lane;
+  const int32_t* ckx = W.ck_x + tile * SLOTS;
+  const double* ckP = W.ck_P + tile * SLOTS * kWave + lane;
+  const int32_t* ckme = W.ck_me + tile * SLOTS * kWave + lane;
   const int32_t a = A.vac_axon[i];
   const int64_t off = A.elem_off[i];
   Count c0;

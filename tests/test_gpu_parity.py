@@ -167,6 +167,41 @@ def test_deterministic_and_order_independent():
     b["tree"].free()
 
 
+def test_searches_on_two_streams_share_the_workspace():
+    """Searches of different sizes on two streams, without host waits between them,
+    give the targets of the same searches run one at a time (the library's search
+    workspace is shared and grows between the calls)."""
+    ws = [uniform_cube(150000, 3000.0, seed=31), uniform_cube(400000, 4000.0, seed=32),
+          uniform_cube(90000, 2500.0, seed=33)]
+    trees, args = [], []
+    for w in ws:
+        tree = msp.build_octree(T(w.pos, torch.float64), w.box_min, w.box_edge)
+        msp.update_vacant_counts(tree, T(w.vac_exc, torch.int32), T(w.vac_inh, torch.int32))
+        trees.append(tree)
+        args.append((T(w.neuron_type, torch.uint8), T(w.vac_axon, torch.int32), w.sigma))
+    plan = [(0, 1), (1, 2), (2, 3), (0, 4), (1, 5)]          # (workload, step)
+    ref = []
+    for k, step in plan:
+        tgt, _ = msp.find_targets(trees[k], args[k][0], args[k][1], args[k][2], 0.3, 5, step)
+        torch.cuda.synchronize()
+        ref.append(tgt.cpu().numpy().copy())
+    outs = [(torch.full((ws[k].searches,), -7, dtype=torch.int32, device=DEV),
+             torch.empty(ws[k].n + 1, dtype=torch.int64, device=DEV)) for k, _ in plan]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    for c, (k, step) in enumerate(plan):
+        st = streams[c % 2]
+        with torch.cuda.stream(st):
+            msp.find_targets(trees[k], args[k][0], args[k][1], args[k][2], 0.3, 5, step,
+                             target_out=outs[c][0], elem_offset_out=outs[c][1], stream=st)
+    torch.cuda.synchronize()
+    for c, (k, step) in enumerate(plan):
+        assert np.array_equal(outs[c][0].cpu().numpy(), ref[c]), (c, k, step)
+    say(f"{len(plan)} searches on 2 streams equal the serial ones")
+    for tree in trees:
+        tree.free()
+
+
 def test_commit_parity_with_gpu_proposals():
     w = config_small()
     g = gpu_search(w)
