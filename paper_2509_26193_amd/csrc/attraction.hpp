@@ -9,27 +9,42 @@
 //   dZ_i/dsigma   = sum_e w_e * 2 |x_i - c_e|^2 / sigma^3
 //   dc_C/dx_j     = (v_j / v_C) I for every neuron j of cell C (a centroid is the
 //                   vacancy-weighted mean of its neurons).
-// The sweep walks the sources' lists coherently (as the search does); per node, the
-// contributions of all lanes of the wave are summed in registers first and added to
-// the node's gradient with one float64 atomic per component. A top-down pass then
-// carries sum_{C containing j} G_C / v_C to each neuron.
+// The forward pass is the search's level-0 sweep without checkpoints (Z per source).
+// The backward sweep walks the sources' lists coherently (as the search does); per
+// node, the contributions of all lanes of the wave are summed across the wave first
+// and added to the node's gradient G with one float64 atomic per component. A
+// neuron's leaf is a node like any other (its centroid is the neuron's position), so
+// leaves need no separate path. The waves of each die add into that die's own copy
+// of G, so the atomics of concurrent waves on the nodes they all share (the upper
+// tree) are spread over eight addresses instead of queueing on one; a reduction
+// sums the copies. A top-down pass then carries sum_{C containing j} G_C / v_C to
+// each neuron.
 #pragma once
 
 #include "batch.hpp"
 
 namespace msp {
 
+constexpr int kGradCopies = 8;  // one per die (XCC)
+
 struct AttractArgs {
-  const float* gZ;              // [n] upstream gradient (backward), by neuron id
-  float* Z;                     // [n] output (forward), by neuron id
-  double* G;                    // [2][N][3] per-node centroid gradients (backward)
-  double* dpos;                 // [n][3] float64 accumulator (backward)
-  double* dsigma;               // scalar accumulator (backward)
+  const float* gZ;              // [n] upstream gradient, by neuron id
+  double* G;                    // [kGradCopies][2][N][3] per-node centroid gradients
+  double* dpos;                 // [n][3] float64 accumulator
+  double* dsigma;               // scalar accumulator
   double two_over_s2;           // 2 / sigma^2
   double two_over_s3;           // 2 / sigma^3
   int64_t N;
   const int32_t* tile_count;
 };
+
+// The die (XCC) this wave runs on: bits 3:0 of hardware register XCC_ID (20). It only
+// selects a copy of G; any value in 0..7 gives the same sums.
+__device__ __forceinline__ int xcc_id() {
+  return (int)(__builtin_amdgcn_s_getreg(20 | (0 << 6) | ((4 - 1) << 11)) & (kGradCopies - 1));
+}
+
+
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -37,7 +52,8 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Add the wave's contributions (fx, fy, fz) to dst[3] (skipped if all are zero).
+// Add the wave's contributions (fx, fy, fz) to dst[3] of this die's copy (skipped if
+// all are zero).
 __device__ __forceinline__ void wave_add3(double fx, double fy, double fz, double* dst, int lane) {
   if (!__any(fx != 0.0 || fy != 0.0 || fz != 0.0)) return;
   fx = wave_sum(fx);
@@ -50,7 +66,6 @@ __device__ __forceinline__ void wave_add3(double fx, double fy, double fz, doubl
   }
 }
 
-template <bool BWD>
 __device__ void attract_tile(const SearchArgs& A, const AttractArgs& O, int tile, int lane) {
   const int64_t slot = (int64_t)tile * kWave + lane;
   const int32_t i = A.work[slot];
@@ -65,12 +80,12 @@ __device__ void attract_tile(const SearchArgs& A, const AttractArgs& O, int tile
     xi = A.pos[3 * (int64_t)i];
     yi = A.pos[3 * (int64_t)i + 1];
     zi = A.pos[3 * (int64_t)i + 2];
-    if (BWD) g = (double)O.gZ[i];
+    g = (double)O.gZ[i];
   }
-  double Z = 0.0, dxi = 0.0, dyi = 0.0, dzi = 0.0, ds = 0.0;
-  double* G = BWD ? O.G + (int64_t)t * O.N * 3 : nullptr;
-  // one accepted entry of this lane: weight, and in the backward pass the gradient
-  // factor f = g * w * 2 / sigma^2 applied to the offset (x_i - c)
+  double dxi = 0.0, dyi = 0.0, dzi = 0.0, ds = 0.0;
+  double* G = O.G + ((int64_t)xcc_id() * 2 + t) * O.N * 3;
+  // one accepted entry of this lane: the gradient factor f = g * w * 2 / sigma^2
+  // applied to the offset (x_i - c)
   auto take = [&](bool on, int32_t v, double cx, double cy, double cz, double& fx, double& fy,
                   double& fz) {
     fx = fy = fz = 0.0;
@@ -78,10 +93,6 @@ __device__ void attract_tile(const SearchArgs& A, const AttractArgs& O, int tile
     const double dx = xi - cx, dy = yi - cy, dz = zi - cz;
     const double d2 = dx * dx + dy * dy + dz * dz;
     const double w = kernel_weight(v, d2, A.k2);
-    if (!BWD) {
-      Z = Z + w;
-      return;
-    }
     const double f = g * w * O.two_over_s2;
     fx = f * dx;
     fy = f * dy;
@@ -103,11 +114,13 @@ __device__ void attract_tile(const SearchArgs& A, const AttractArgs& O, int tile
       if (meta & kLeafBit) {
         if (cur.v != 0) {
           if (!(meta & kBucketBit)) {
+            // a neuron's leaf: its gradient reaches the neuron through the push-down
             const int32_t id = (int32_t)(meta & kIdMask);
             double fx, fy, fz;
             take(active && id != i, cur.v, cur.x, cur.y, cur.z, fx, fy, fz);
-            if (BWD) wave_add3(fx, fy, fz, O.dpos + 3 * (int64_t)id, lane);
+            wave_add3(fx, fy, fz, G + 3 * (int64_t)x, lane);
           } else {
+            // members of a bucket are entries at their own positions
             const cptr<int32_t> vs = as_const(A.vs[t]);
             const cptr<int32_t> order = as_const(A.order);
             const cptr<double> pos = as_const(A.pos);
@@ -118,7 +131,16 @@ __device__ void attract_tile(const SearchArgs& A, const AttractArgs& O, int tile
               double fx, fy, fz;
               take(active && id != i && v != 0, v, pos[3 * (int64_t)id], pos[3 * (int64_t)id + 1],
                    pos[3 * (int64_t)id + 2], fx, fy, fz);
-              if (BWD) wave_add3(fx, fy, fz, O.dpos + 3 * (int64_t)id, lane);
+              if (__any(fx != 0.0 || fy != 0.0 || fz != 0.0)) {
+                fx = wave_sum(fx);
+                fy = wave_sum(fy);
+                fz = wave_sum(fz);
+                if (lane == 0) {
+                  atomicAdd(O.dpos + 3 * (int64_t)id + 0, fx);
+                  atomicAdd(O.dpos + 3 * (int64_t)id + 1, fy);
+                  atomicAdd(O.dpos + 3 * (int64_t)id + 2, fz);
+                }
+              }
             }
           }
         }
@@ -138,32 +160,45 @@ __device__ void attract_tile(const SearchArgs& A, const AttractArgs& O, int tile
       const bool accept = active && !contains && acc_ok;
       double fx, fy, fz;
       take(accept, cur.v, cur.x, cur.y, cur.z, fx, fy, fz);
-      if (BWD) wave_add3(fx, fy, fz, G + 3 * (int64_t)x, lane);
+      wave_add3(fx, fy, fz, G + 3 * (int64_t)x, lane);
       if (accept) me = sk;
       x = __any(open) ? x + 1 : sk;
     }
   }
-  if (!BWD) {
-    if (valid) O.Z[i] = (float)Z;
-  } else {
-    if (valid) {
-      atomicAdd(O.dpos + 3 * (int64_t)i + 0, dxi);
-      atomicAdd(O.dpos + 3 * (int64_t)i + 1, dyi);
-      atomicAdd(O.dpos + 3 * (int64_t)i + 2, dzi);
-    }
-    ds = wave_sum(ds);
-    if (lane == 0 && ds != 0.0) atomicAdd(O.dsigma, ds);
+  if (valid) {
+    atomicAdd(O.dpos + 3 * (int64_t)i + 0, dxi);
+    atomicAdd(O.dpos + 3 * (int64_t)i + 1, dyi);
+    atomicAdd(O.dpos + 3 * (int64_t)i + 2, dzi);
   }
+  ds = wave_sum(ds);
+  if (lane == 0 && ds != 0.0) atomicAdd(O.dsigma, ds);
 }
 
 // One wave per tile (the batch path's worklist of sources with a_i > 0).
-template <bool BWD>
-__global__ void __launch_bounds__(256) attract_k(BatchDev B, AttractArgs O) {
+__global__ void __launch_bounds__(256) attract_bwd_k(BatchDev B, AttractArgs O) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   if (tile >= *O.tile_count) return;
   const SearchArgs A = args_of(B.sims, 0, B.work);
-  attract_tile<BWD>(A, O, (int)tile, lane);
+  attract_tile(A, O, (int)tile, lane);
+}
+
+// Z of every source from the sweep's per-slot sums (float32); other neurons keep 0.
+__global__ void z_scatter_k(const int32_t* __restrict__ work, const double* __restrict__ Zs,
+                            const int32_t* tile_count, float* __restrict__ Z) {
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= (int64_t)*tile_count * kWave) return;
+  const int32_t i = work[slot];
+  if (i >= 0) Z[i] = (float)Zs[slot];
+}
+
+// G = sum of the per-die copies, in die order.
+__global__ void grad_sum_k(double* __restrict__ G, int64_t count) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  double s = G[k];
+  for (int c = 1; c < kGradCopies; ++c) s += G[(int64_t)c * count + k];
+  G[k] = s;
 }
 
 __global__ void fill_f64_k(double* p, int64_t n, double v) {

@@ -119,9 +119,11 @@ __global__ void __launch_bounds__(kWaveBlock) search_sweep_k(BatchDev B, SweepOu
         find_sim(as_const(B.tile_base), B.nsims, (int64_t)tile));
     const SearchArgs A = args_of(B.sims, sim, B.work);
     const int steps = sweep_tile<DIAG, SLOTS>(A, W, tile, lane, step0);
-    // next interval: about SLOTS checkpoints over a sweep as long as this one
-    step0 = kCkptStepMin;
-    while (step0 * SLOTS < steps) step0 <<= 1;
+    if constexpr (SLOTS > 0) {
+      // next interval: about SLOTS checkpoints over a sweep as long as this one
+      step0 = kCkptStepMin;
+      while (step0 * SLOTS < steps) step0 <<= 1;
+    }
   }
 }
 

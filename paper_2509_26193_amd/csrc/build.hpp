@@ -131,45 +131,59 @@ __device__ __forceinline__ uint64_t same_depth_lanes(int d) {
   return peers;
 }
 
+// Nodes per block of the per-depth passes: enough that the per-block global atomics
+// (one per depth) do not queue up on the few hot depth counters.
+constexpr int kLevelItems = 16;
+
 // Nodes per depth: one LDS atomic per distinct depth and wave, one global atomic per
-// depth and block.
+// depth and block of kBuildBlock * kLevelItems nodes.
 __global__ void __launch_bounds__(kBuildBlock) level_count_k(const uint8_t* __restrict__ depth,
                                                             int64_t N, int32_t* level_cnt) {
   __shared__ int32_t c[kMaxDepth + 1];
   if (threadIdx.x <= kMaxDepth) c[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int d = x < N ? (int)depth[x] : -1;
-  const uint64_t peers = same_depth_lanes(d);
   const int lane = (int)(threadIdx.x & (kWave - 1));
-  if (d >= 0 && lane == __ffsll((unsigned long long)peers) - 1) atomicAdd(&c[d], __popcll(peers));
+  const int64_t base = (int64_t)blockIdx.x * kBuildBlock * kLevelItems + threadIdx.x;
+  for (int k = 0; k < kLevelItems; ++k) {
+    const int64_t x = base + (int64_t)k * kBuildBlock;
+    const int d = x < N ? (int)depth[x] : -1;
+    const uint64_t peers = same_depth_lanes(d);
+    if (d >= 0 && lane == __ffsll((unsigned long long)peers) - 1) atomicAdd(&c[d], __popcll(peers));
+  }
   __syncthreads();
   if (threadIdx.x <= kMaxDepth && c[threadIdx.x]) atomicAdd(&level_cnt[threadIdx.x], c[threadIdx.x]);
 }
 
 // Group node ids by depth (order within a depth is arbitrary: the refresh of one
-// depth treats its nodes independently).
+// depth treats its nodes independently). Same blocking as level_count_k.
 __global__ void __launch_bounds__(kBuildBlock) level_scatter_k(const uint8_t* __restrict__ depth,
                                                               int64_t N, int32_t* cursor,
                                                               int32_t* level_nodes) {
   __shared__ int32_t c[kMaxDepth + 1];
-  __shared__ int32_t base[kMaxDepth + 1];
+  __shared__ int32_t base_d[kMaxDepth + 1];
   if (threadIdx.x <= kMaxDepth) c[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int d = x < N ? (int)depth[x] : -1;
-  const uint64_t peers = same_depth_lanes(d);
   const int lane = (int)(threadIdx.x & (kWave - 1));
-  const int leader = __ffsll((unsigned long long)peers) - 1;
-  int r0 = 0;
-  if (d >= 0 && lane == leader) r0 = atomicAdd(&c[d], __popcll(peers));
-  const int r = __shfl(r0, leader < 0 ? 0 : leader, kWave) +
-                __popcll(peers & ((1ull << lane) - 1ull));
+  const int64_t base = (int64_t)blockIdx.x * kBuildBlock * kLevelItems + threadIdx.x;
+  int d[kLevelItems];
+  int r[kLevelItems];
+#pragma unroll
+  for (int k = 0; k < kLevelItems; ++k) {
+    const int64_t x = base + (int64_t)k * kBuildBlock;
+    d[k] = x < N ? (int)depth[x] : -1;
+    const uint64_t peers = same_depth_lanes(d[k]);
+    const int leader = __ffsll((unsigned long long)peers) - 1;
+    int r0 = 0;
+    if (d[k] >= 0 && lane == leader) r0 = atomicAdd(&c[d[k]], __popcll(peers));
+    r[k] = __shfl(r0, leader < 0 ? 0 : leader, kWave) + __popcll(peers & ((1ull << lane) - 1ull));
+  }
   __syncthreads();
   if (threadIdx.x <= kMaxDepth && c[threadIdx.x])
-    base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], c[threadIdx.x]);
+    base_d[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], c[threadIdx.x]);
   __syncthreads();
-  if (d >= 0) level_nodes[base[d] + r] = (int32_t)x;
+#pragma unroll
+  for (int k = 0; k < kLevelItems; ++k)
+    if (d[k] >= 0) level_nodes[base_d[d[k]] + r[k]] = (int32_t)(base + (int64_t)k * kBuildBlock);
 }
 
 // Per-type records start with count 0 and the node's meta word: an inner node keeps

@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdio>
+#include <cstring>
 #include <mutex>
 
 #include "msp.h"
@@ -69,6 +70,8 @@ struct msp_octree_s {
   int32_t* vs[2];        // [n] per type: counts in sorted order (bucket members)
   int32_t* err;          // [1] sticky device error flags
   bool refreshed;
+  void* slab_n;          // one allocation holding the neuron arrays ...
+  void* slab_N;          // ... and one holding the node arrays
 };
 
 #define MSP_HIP_TRY(expr)                                   \
@@ -84,15 +87,69 @@ namespace msp {
 
 inline bool handle_ok(const msp_octree_s* t) { return t != nullptr && t->magic == kMagic; }
 
+// The library's own stream-ordered memory pool on `device`: memory freed to it stays
+// mapped for the next allocation (release threshold = unlimited), so the per-call
+// temporaries of large updates do not pay for page mapping on every call. Other users
+// of the device's default pool are not affected.
+inline hipError_t lib_pool(int device, hipMemPool_t* out) {
+  static std::mutex m;
+  static hipMemPool_t pools[64] = {};
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(m);
+  if (!pools[device]) {
+    hipMemPoolProps props;
+    std::memset(&props, 0, sizeof(props));
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = device;
+    hipMemPool_t pool = nullptr;
+    hipError_t e = hipMemPoolCreate(&pool, &props);
+    if (e != hipSuccess) return e;
+    uint64_t keep = ~(uint64_t)0;
+    e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    if (e != hipSuccess) {
+      (void)hipMemPoolDestroy(pool);
+      return e;
+    }
+    pools[device] = pool;
+  }
+  *out = pools[device];
+  return hipSuccess;
+}
+
+// A non-blocking stream of the library's own on `device` (default priority), on which
+// memory whose users have all finished is returned to the pool.
+inline hipError_t lib_stream(int device, hipStream_t* out) {
+  static std::mutex m;
+  static hipStream_t streams[64] = {};
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(m);
+  if (!streams[device]) {
+    hipError_t e = hipStreamCreateWithFlags(&streams[device], hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+  }
+  *out = streams[device];
+  return hipSuccess;
+}
+
+// `bytes` of device memory from the library pool, ordered on stream `s` (current device).
+inline hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s) {
+  *p = nullptr;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  hipMemPool_t pool;
+  if ((e = lib_pool(dev, &pool)) != hipSuccess) return e;
+  return hipMallocFromPoolAsync(p, bytes == 0 ? 256 : bytes, pool, s);
+}
+
 // Stream-ordered temporary device memory; released on the same stream.
 struct Temp {
   hipStream_t s;
   void* p = nullptr;
   explicit Temp(hipStream_t st) : s(st) {}
-  hipError_t alloc(size_t bytes) {
-    if (bytes == 0) bytes = 256;
-    return hipMallocAsync(&p, bytes, s);
-  }
+  hipError_t alloc(size_t bytes) { return pool_alloc(&p, bytes, s); }
   ~Temp() {
     if (p) (void)hipFreeAsync(p, s);
   }

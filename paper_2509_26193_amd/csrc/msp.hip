@@ -19,21 +19,51 @@ using namespace msp;
 
 namespace {
 
-template <class T>
-hipError_t dalloc(T** p, int64_t count) {
-  *p = nullptr;
-  if (count <= 0) count = 1;
-  return hipMalloc((void**)p, sizeof(T) * (size_t)count);
+// Carves 256-byte aligned arrays out of one allocation (base null: only sizes it).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(int64_t count) {
+    T* q = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += (sizeof(T) * (size_t)(count > 0 ? count : 1) + 255) & ~(size_t)255;
+    return q;
+  }
+};
+
+void carve_neurons(msp_octree_s* t, char* base, size_t* bytes) {
+  Carver c{base};
+  const int64_t n = t->n;
+  t->pos = c.take<double>(3 * n);
+  t->keys = c.take<uint64_t>(n);
+  t->order = c.take<int32_t>(n);
+  t->leaf_of = c.take<int32_t>(n);
+  t->vs[0] = c.take<int32_t>(n);
+  t->vs[1] = c.take<int32_t>(n);
+  t->err = c.take<int32_t>(1);
+  *bytes = c.off;
+}
+
+void carve_nodes(msp_octree_s* t, char* base, size_t* bytes) {
+  Carver c{base};
+  const int64_t N = t->N;
+  t->rec[0] = c.take<NodeRec>(N + 1);        // + a sentinel record at index N
+  t->rec[1] = c.take<NodeRec>(N + 1);
+  t->skip = c.take<int32_t>(N);
+  t->nbeg = c.take<int32_t>(N);
+  t->nend = c.take<int32_t>(N);
+  t->level_nodes = c.take<int32_t>(N);
+  t->depth = c.take<uint8_t>(N);
+  *bytes = c.off;
 }
 
 void release(msp_octree_s* t) {
   if (!t) return;
-  void* ptrs[] = {t->pos, t->keys, t->order, t->leaf_of, t->skip, t->depth, t->nbeg, t->nend,
-                  t->level_nodes, t->rec[0], t->rec[1], t->err};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
-  if (t->vs[0]) (void)hipFree(t->vs[0]);
-  if (t->vs[1]) (void)hipFree(t->vs[1]);
+  // the callers have waited for every use: the memory returns to the library pool
+  hipStream_t fs = nullptr;
+  if (lib_stream(t->device, &fs) != hipSuccess) fs = nullptr;
+  if (t->slab_n) (void)hipFreeAsync(t->slab_n, fs);
+  if (t->slab_N) (void)hipFreeAsync(t->slab_N, fs);
   t->magic = kDead;
   delete t;
 }
@@ -221,13 +251,10 @@ msp_status msp_build_octree(const double* pos, int64_t n, const double box_min[3
     }                                                           \
   } while (0)
 
-  TRY(dalloc(&t->pos, 3 * n));
-  TRY(dalloc(&t->keys, n));
-  TRY(dalloc(&t->order, n));
-  TRY(dalloc(&t->leaf_of, n));
-  TRY(dalloc(&t->err, 1));
-  TRY(dalloc(&t->vs[0], n));
-  TRY(dalloc(&t->vs[1], n));
+  size_t bytes = 0;
+  carve_neurons(t, nullptr, &bytes);
+  TRY(pool_alloc(&t->slab_n, bytes, s));
+  carve_neurons(t, static_cast<char*>(t->slab_n), &bytes);
   TRY(hipMemsetAsync(t->err, 0, sizeof(int32_t), s));
   {
     Temp k1(s), v1(s), cnt(s), base(s), lvl(s);
@@ -253,13 +280,9 @@ msp_status msp_build_octree(const double* pos, int64_t n, const double box_min[3
     }
     const int64_t N = N32;
     t->N = N;
-    TRY(dalloc(&t->skip, N));
-    TRY(dalloc(&t->depth, N));
-    TRY(dalloc(&t->nbeg, N));
-    TRY(dalloc(&t->nend, N));
-    TRY(dalloc(&t->level_nodes, N));
-    TRY(dalloc(&t->rec[0], N + 1));           // + a sentinel record at index N
-    TRY(dalloc(&t->rec[1], N + 1));
+    carve_nodes(t, nullptr, &bytes);
+    TRY(pool_alloc(&t->slab_N, bytes, s));
+    carve_nodes(t, static_cast<char*>(t->slab_N), &bytes);
     TRY(hipMemsetAsync(t->rec[0] + N, 0, sizeof(NodeRec), s));
     TRY(hipMemsetAsync(t->rec[1] + N, 0, sizeof(NodeRec), s));
     TRY(lvl.alloc(sizeof(int32_t) * 2 * (kMaxDepth + 1)));
@@ -269,7 +292,7 @@ msp_status msp_build_octree(const double* pos, int64_t n, const double box_min[3
                                                              base.as<int32_t>(), t->skip, t->depth,
                                                              t->nbeg, t->nend, t->leaf_of);
     TRY(hipGetLastError());
-    level_count_k<<<grid_for(N, kBuildBlock), kBuildBlock, 0, s>>>(t->depth, N, lcnt);
+    level_count_k<<<grid_for(N, kBuildBlock * kLevelItems), kBuildBlock, 0, s>>>(t->depth, N, lcnt);
     TRY(hipGetLastError());
     int32_t hc[kMaxDepth + 1];
     TRY(hipMemcpyAsync(hc, lcnt, sizeof(hc), hipMemcpyDeviceToHost, s));
@@ -286,8 +309,8 @@ msp_status msp_build_octree(const double* pos, int64_t n, const double box_min[3
     }
     int32_t* cursor = lcnt + (kMaxDepth + 1);
     TRY(hipMemcpyAsync(cursor, hoff, sizeof(hoff), hipMemcpyHostToDevice, s));
-    level_scatter_k<<<grid_for(N, kBuildBlock), kBuildBlock, 0, s>>>(t->depth, N, cursor,
-                                                                     t->level_nodes);
+    level_scatter_k<<<grid_for(N, kBuildBlock * kLevelItems), kBuildBlock, 0, s>>>(
+        t->depth, N, cursor, t->level_nodes);
     TRY(hipGetLastError());
     init_meta_k<<<grid_for(N, kBuildBlock), kBuildBlock, 0, s>>>(t->skip, t->depth, t->nbeg,
                                                                  t->nend, t->order, N, t->rec[0],
@@ -801,29 +824,33 @@ msp_status attraction(msp_octree t, const uint8_t* neuron_type, const int32_t* v
   MSP_HIP_TRY(hipStreamSynchronize(s));
   if (status & kSimInvalid) return MSP_ERR_INVALID;
 
+  if (!bwd) {
+    // Z_i is the level-0 sum of the search: the sweep without checkpoints
+    unsigned blocks = 0;
+    MSP_HIP_TRY(sweep_blocks_for(t->device, false, max_tiles_for(n, 1), 1.0, &blocks));
+    fill_i32_k<<<grid_for(n, 256), 256, 0, s>>>(reinterpret_cast<int32_t*>(Z_out), n, 0);
+    search_sweep_k<false, 0><<<blocks, kWaveBlock, 0, s>>>(S.B, S.W);
+    z_scatter_k<<<grid_for(S.B.max_slots, 256), 256, 0, s>>>(S.B.work, S.W.Z, S.counters, Z_out);
+    MSP_HIP_TRY(hipGetLastError());
+    return MSP_OK;
+  }
   AttractArgs O{};
   O.gZ = gZ;
-  O.Z = Z_out;
   O.two_over_s2 = 2.0 / (sigma_um * sigma_um);
   O.two_over_s3 = 2.0 / (sigma_um * sigma_um * sigma_um);
   O.N = N;
   O.tile_count = S.counters;
-  const unsigned grid = grid_for(S.B.max_slots, 256);
-  if (!bwd) {
-    fill_i32_k<<<grid_for(n, 256), 256, 0, s>>>(reinterpret_cast<int32_t*>(Z_out), n, 0);
-    attract_k<false><<<grid, 256, 0, s>>>(S.B, O);
-    MSP_HIP_TRY(hipGetLastError());
-    return MSP_OK;
-  }
   const int64_t ng = 2 * N * 3, nh = 2 * N * 3, np = 3 * n;
-  MSP_HIP_TRY(grads.alloc(sizeof(double) * (size_t)(ng + nh + np)));
+  MSP_HIP_TRY(grads.alloc(sizeof(double) * (size_t)(kGradCopies * ng + nh + np)));
   O.G = grads.as<double>();
-  double* H = O.G + ng;
+  double* H = O.G + kGradCopies * ng;
   O.dpos = H + nh;
   O.dsigma = dsigma;
-  fill_f64_k<<<grid_for(ng + nh + np, 256), 256, 0, s>>>(O.G, ng + nh + np, 0.0);
+  fill_f64_k<<<grid_for(kGradCopies * ng + nh + np, 256), 256, 0, s>>>(
+      O.G, kGradCopies * ng + nh + np, 0.0);
   fill_f64_k<<<1, 64, 0, s>>>(dsigma, 1, 0.0);
-  attract_k<true><<<grid, 256, 0, s>>>(S.B, O);
+  attract_bwd_k<<<grid_for(S.B.max_slots, 256), 256, 0, s>>>(S.B, O);
+  grad_sum_k<<<grid_for(ng, 256), 256, 0, s>>>(O.G, ng);
   for (int k = 0; k <= kMaxDepth; ++k) {
     const int64_t cnt = t->level_off[k + 1] - t->level_off[k];
     if (cnt == 0) continue;

@@ -126,25 +126,28 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
     int imask = __builtin_amdgcn_readfirstlane(step0 - 1);   // interval - 1 (power of 2)
     NodeRec cur = load_rec_u(R, 1);
     while (x < end) {
-      // checkpoints at multiples of the interval; a full buffer keeps every other one
-      // and doubles the interval
-      if (nck == SLOTS) {
+      int chunk = 0x7FFFFFFF;                 // without checkpoints: one chunk to the end
+      if constexpr (SLOTS > 0) {
+        // checkpoints at multiples of the interval; a full buffer keeps every other
+        // one and doubles the interval
+        if (nck == SLOTS) {
 #pragma unroll 1
-        for (int k = 1; k < SLOTS / 2; ++k) {
-          ckP[k * kWave] = ckP[2 * k * kWave];
-          ckme[k * kWave] = ckme[2 * k * kWave];
-          if (lane == 0) ckx[k] = ckx[2 * k];
+          for (int k = 1; k < SLOTS / 2; ++k) {
+            ckP[k * kWave] = ckP[2 * k * kWave];
+            ckme[k * kWave] = ckme[2 * k * kWave];
+            if (lane == 0) ckx[k] = ckx[2 * k];
+          }
+          nck = SLOTS / 2;
+          imask = __builtin_amdgcn_readfirstlane(2 * imask + 1);
         }
-        nck = SLOTS / 2;
-        imask = __builtin_amdgcn_readfirstlane(2 * imask + 1);
+        if ((steps & imask) == 0) {
+          ckP[nck * kWave] = sum.Z;
+          ckme[nck * kWave] = me;
+          if (lane == 0) ckx[nck] = x;
+          nck = __builtin_amdgcn_readfirstlane(nck + 1);
+        }
+        chunk = (imask + 1) - (steps & imask);   // steps to the next multiple
       }
-      if ((steps & imask) == 0) {
-        ckP[nck * kWave] = sum.Z;
-        ckme[nck * kWave] = me;
-        if (lane == 0) ckx[nck] = x;
-        nck = __builtin_amdgcn_readfirstlane(nck + 1);
-      }
-      const int chunk = (imask + 1) - (steps & imask);   // steps to the next multiple
       int left = chunk;
       do {
         // one node: uniform branches on its kind, per-lane decisions as lane masks, the
