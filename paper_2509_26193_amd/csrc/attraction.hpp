@@ -46,10 +46,31 @@ __device__ __forceinline__ int xcc_id() {
 
 
 
+// v moved across lanes by a DPP pattern (both 32-bit halves); lanes of rows outside
+// row_mask get 0.0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROW_MASK, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over the 64 lanes of the wave (every lane active), returned to every lane. DPP
+// steps: pairs, quads (quad_perm), halves of a row (row_half_mirror), rows of 16
+// (row_mirror); then rows 0+1 and 2+3 (row_bcast:15), all four (row_bcast:31), which
+// leaves the total in lane 63.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  v += dpp_f64<0xB1, 0xF>(v);        // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E, 0xF>(v);        // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141, 0xF>(v);       // row_half_mirror
+  v += dpp_f64<0x140, 0xF>(v);       // row_mirror
+  v += dpp_f64<0x142, 0xA>(v);       // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xC>(v);       // row_bcast:31 into rows 2 and 3
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 // Add the wave's contributions (fx, fy, fz) to dst[3] of this die's copy (skipped if
