@@ -22,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
+EXP2_PEAK = 256 * 64 * 2.4e9 / 4   # float32 exp2 per second, quarter-rate transcendental
 REC_BYTES = 16             # one per-type node record {x, y, z, count} at 4 bytes each
 OPEN_BYTES = 8             # child link + mask + depth of an opened node
 SRC_BYTES = 16             # source record
@@ -68,6 +69,25 @@ def sweep_bytes(cnt, off):
     o0 = cnt["opens0"].astype(np.int64)
     first = off[:-1][np.diff(off) > 0]
     return int((REC_BYTES * v0[first] + OPEN_BYTES * o0[first] + SRC_BYTES).sum())
+
+
+def oracle_threads():
+    """Host threads the oracle runs on: every core, at most 64."""
+    return min(os.cpu_count() or 1, 64)
+
+
+def counted(msp, tree, ty, va, sigma, theta, seed, step):
+    """Per-search visit/open counters of one counting launch, on the host."""
+    _, off, _, _, cnt = msp.find_targets(tree, ty, va, sigma, theta, seed, step, diag=True,
+                                         counters=True)
+    h = {k: v.cpu().numpy() for k, v in cnt.items() if k != "wave_steps"}
+    return h, off.cpu().numpy()
+
+
+def hbm_roofline(bytes_, seconds, what):
+    return dict(bound="hbm", unit="GB/s", achieved=bytes_ / seconds / 1e9,
+                peak=HBM_PEAK / 1e9, frac=bytes_ / seconds / HBM_PEAK, bytes=int(bytes_),
+                basis=what)
 
 
 def kernel_sources_hash():
@@ -170,8 +190,30 @@ def bench_plain_update(msp, torch, w, steps, warmup):
         step()
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / steps
+    tree = msp.build_octree(pos, w.box_min, w.box_edge)
+    msp.update_vacant_counts(tree, ve0, vi0)
+    cnt, off = counted(msp, tree, ty, va0, w.sigma, w.theta, w.seed, w.step)
+    tree.free()
+    B, _ = algorithmic_bytes(cnt, off)
+    ks = float(np.mean(kern)) / 1e3
+    # the oracle on 20000 sampled searches of the same update
+    from oracle import oracle as orc
+    t = orc.OracleTree(w.pos, w.box_min, w.box_edge)
+    t.update_counts(w.vac_exc, w.vac_inh)
+    _, src, elem = orc.search_list(w.vac_axon)
+    q = np.sort(np.random.default_rng(99).choice(src.size, size=min(20000, src.size),
+                                                 replace=False))
+    t0 = time.perf_counter()
+    t.find_targets(w.neuron_type, w.sigma, w.theta, w.seed, w.step, src[q], elem[q],
+                   nthreads=oracle_threads())
+    t_or = time.perf_counter() - t0
     return dict(workload=w.name, neurons=w.n, searches=S, theta=w.theta, ms_per_update=sec * 1e3,
-                searches_per_s=S / sec, search_kernels_ms=float(np.mean(kern)))
+                searches_per_s=S / sec, search_kernels_ms=ks * 1e3,
+                roofline=hbm_roofline(B, ks, "algorithmic bytes of the search kernels (sweep "
+                                      "+ draw) / their HIP-event time"),
+                oracle=dict(value=q.size / t_or, unit="searches/s", cores=oracle_threads(),
+                            kind="oracle", sample=f"{q.size} sampled searches of the same "
+                            "update, tree build and refresh not included"))
 
 
 def bench_batched(msp, torch, reps=5):
@@ -212,13 +254,38 @@ def bench_batched(msp, torch, reps=5):
     tp = (time.perf_counter() - t0) / reps
     same = all(np.array_equal(o.cpu().numpy(), x) for o, x in zip(outs, bt))
     b.free()
+    B = 0
+    for k, d in enumerate(sims):
+        cnt, off = counted(msp, d["tree"], d["neuron_type"], d["vac_axon"], d["sigma"], 0.3,
+                           d["seed"], reps - 1)
+        B += algorithmic_bytes(cnt, off)[0]
     for d in sims:
         d["tree"].free()
+    # the oracle on the simulations of up to 2^14 neurons, all of their searches
+    from oracle import oracle as orc
+    small = [(k, w) for k, w in enumerate(ws) if w.n <= (1 << 14)]
+    t0 = time.perf_counter()
+    S_small = 0
+    for k, w in small:
+        t = orc.OracleTree(w.pos, w.box_min, w.box_edge)
+        t.update_counts(w.vac_exc, w.vac_inh)
+        _, src, elem = orc.search_list(w.vac_axon)
+        t.find_targets(w.neuron_type, w.sigma, 0.3, w.seed + k, 0, src, elem,
+                       nthreads=oracle_threads())
+        S_small += src.size
+    t_or = time.perf_counter() - t0
     return dict(workload=f"batched_{len(ws)}_simulations", simulations=len(ws),
                 neurons=int(sum(w.n for w in ws)), searches=int(S),
                 batched_ms=tb * 1e3, batched_searches_per_s=S / tb,
                 per_simulation_ms=tp * 1e3, per_simulation_searches_per_s=S / tp,
-                speedup=tp / tb, identical_targets=bool(same))
+                speedup=tp / tb, identical_targets=bool(same),
+                roofline=hbm_roofline(B, tb, "algorithmic bytes of all 64 searches / the "
+                                      "batched launch's wall time"),
+                oracle=dict(value=S_small / t_or, unit="searches/s",
+                            cores=oracle_threads(), kind="oracle",
+                            sample=f"all {S_small} searches of the {len(small)} simulations "
+                                   f"with at most 16384 neurons, tree build and refresh "
+                                   f"included"))
 
 
 def bench_plasticity(msp, torch, updates=3):
@@ -330,11 +397,34 @@ def bench_attraction(msp, torch, reps=5):
         msp.attraction_bwd(tree, ty, va, w.sigma, w.theta, gZ)
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / reps
+    cnt, off = counted(msp, tree, ty, va, w.sigma, w.theta, w.seed, 0)
     tree.free()
     ns = int(src.sum().item())
+    Bf = sweep_bytes(cnt, off)
+    first = off[:-1][np.diff(off) > 0]
+    accepted = int((cnt["visits0"][first].astype(np.int64) - cnt["opens0"][first]).sum())
+    Bb = Bf + 24 * accepted              # plus one gradient (3 x float64) per accepted entry
+    # the oracle (fp64, forward and analytic gradient) on a 32768-neuron cube at the
+    # same density
+    from oracle import oracle as orc
+    from synth_inputs import uniform_cube
+    wo = uniform_cube(32768, 5000.0 * (32768 / w.n) ** (1.0 / 3.0), seed=42)
+    t0 = time.perf_counter()
+    to = orc.OracleTree(wo.pos, wo.box_min, wo.box_edge)
+    to.update_counts(wo.vac_exc, wo.vac_inh)
+    to.attraction(wo.neuron_type, wo.vac_axon, wo.sigma, wo.theta, nthreads=oracle_threads())
+    t_or = time.perf_counter() - t0
     return dict(workload=w.name, neurons=w.n, sources=ns, forward_ms=tf * 1e3,
                 backward_ms=tb * 1e3, sources_per_s_forward=ns / tf,
-                sources_per_s_backward=ns / tb)
+                sources_per_s_backward=ns / tb,
+                roofline_forward=hbm_roofline(Bf, tf, "level-0 algorithmic bytes / forward "
+                                              "wall time"),
+                roofline_backward=hbm_roofline(Bb, tb, "level-0 algorithmic bytes + 24 B per "
+                                               "accepted entry / backward wall time"),
+                oracle=dict(value=int((wo.vac_axon > 0).sum()) / t_or, unit="sources/s",
+                            cores=oracle_threads(), kind="oracle",
+                            sample="forward and gradient of all sources of a 32768-neuron "
+                                   "uniform cube at the same density (tree build included)"))
 
 
 def main():
@@ -442,6 +532,8 @@ def main():
     lane_steps = int((cnt_h["visits0"][first].astype(np.int64) - 1).sum())
     wave_steps = int(cnt_h["wave_steps"][0])
     union_eff = lane_steps / max(1, 64 * wave_steps)
+    evals = int((cnt_h["visits0"][first].astype(np.int64)
+                 - cnt_h["opens0"][first].astype(np.int64)).sum())
     Bs = sweep_bytes(cnt_h, off_h)
     sweep_s = float(np.mean(times["sweep"])) / 1e3
     draw_s = float(np.mean(times["draw"])) / 1e3
@@ -457,7 +549,12 @@ def main():
                                   achieved=B / (sweep_s + draw_s) / 1e9,
                                   frac=B / (sweep_s + draw_s) / HBM_PEAK),
                 sweep_wave_steps=wave_steps, sweep_lane_visits=lane_steps,
-                sweep_lane_utilisation=union_eff)
+                sweep_lane_utilisation=union_eff,
+                # kernel evaluations the method needs at level 0 (accepted entries: visits
+                # that are not opened), per second of the sweep, against the float32 exp2
+                # rate (quarter rate: 256 CU x 64 lanes x 2.4 GHz / 4)
+                kernel_evals_per_s=evals / sweep_s, exp2_peak_per_s=EXP2_PEAK,
+                exp2_frac=evals / sweep_s / EXP2_PEAK)
     log(f"step {sec * 1e3:.1f} ms; sweep {sweep_s * 1e3:.2f} ms ({achieved / 1e9:.0f} GB/s "
         f"algorithmic, {roof['frac']:.3f} of HBM peak); draw {draw_s * 1e3:.2f} ms; "
         f"{wave_steps} wave steps, lane utilisation {union_eff:.3f}")
@@ -473,7 +570,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64/f32",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "neurons": w.n, "searches_per_step": S,
                    "sigma_um": w.sigma, "theta": w.theta,
@@ -499,7 +596,7 @@ def main():
             also["plasticity"] = bench_plasticity(msp, torch, args.updates)
         out["also"] = also
     if not args.no_cpu:
-        threads = args.cpu_threads or min(os.cpu_count() or 1, 64)
+        threads = args.cpu_threads or oracle_threads()
         out["cpu_baseline"] = cpu_baseline(w, gpu_target, args.cpu_sample, threads)
     print(json.dumps(out), flush=True)
 
