@@ -633,4 +633,129 @@ double oracle_attraction_frozen(const OracleTree* t, const uint8_t* neuron_type,
                         nthreads);
 }
 
+// ---------------------------------------------------------------------------
+// The change of the network between two connectivity updates (Sec. III-A, "Update of
+// synaptic elements" and the first sub-phase of "Update of synapses"), as the
+// multi-update workload reads it:
+//   * calcium per neuron j and element kind k (0 axon, 1 excitatory dendrite,
+//     2 inhibitory dendrite) is drawn from N(mean, sd): Box-Muller on Philox words
+//     0 and 1 with key (seed, 2) and counter (j, k, step, 0);
+//   * growth over the update: dz = steps * nu * (2 exp(-((Ca - xi) / zeta)^2) - 1),
+//     xi = (eta + eps) / 2, zeta = (eps - eta) / (2 sqrt(ln 2)), so dz = 0 at
+//     Ca = eta and at Ca = eps and dz = steps * nu at Ca = xi; z = max(z + dz, 0);
+//   * round(frac * m) synapses are deleted uniformly at random: those of smallest
+//     (Philox word 0, key (seed, 3), counter (s, step, 0, 0); then s), s being the
+//     synapse's place in the list at the start of the step;
+//   * then for k = 0, 1, 2 in turn: where floor(z) fell below the bound elements of
+//     kind k, that many of the neuron's synapses of that kind break, those of smallest
+//     (top 32 bits of Philox word 0, key (seed, 4), counter (s, step, k, 0); then s).
+//     A synapse (i, g, type) binds one axonal element of i and one dendritic element
+//     of kind 1 + type of g; breaking it frees both.
+//   * the list keeps its order; vacant elements are floor(z) - bound.
+// ---------------------------------------------------------------------------
+double oracle_growth_delta(double ca, double nu, double eps, double eta, int32_t steps) {
+  const double xi = 0.5 * (eta + eps);
+  const double zeta = (eps - eta) / (2.0 * std::sqrt(std::log(2.0)));
+  const double r = (ca - xi) / zeta;
+  const double e = std::exp(-(r * r));
+  return (double)steps * nu * (2.0 * e - 1.0);
+}
+
+double oracle_calcium(uint64_t seed, uint64_t j, uint64_t k, uint64_t step, double mean,
+                      double sd) {
+  P4 ctr = {{j, k, step, 0}};
+  P4 w = philox4x64_10(ctr, seed, 2);
+  const double u1 = (double)((w.v[0] >> 11) + 1) * 0x1p-53;     // (0, 1]
+  const double u2 = (double)(w.v[1] >> 11) * 0x1p-53;           // [0, 1)
+  const double two_pi = 6.283185307179586476925286766559;
+  const double g = std::sqrt(-2.0 * std::log(u1)) * std::cos(two_pi * u2);
+  return mean + sd * g;
+}
+
+// Appends m_new synapses at [m, m + m_new) and binds their elements.
+void oracle_plasticity_record(int64_t n, int64_t m, int64_t m_new, const int32_t* nsrc,
+                              const int32_t* ntgt, const uint8_t* ntype, int32_t* src,
+                              int32_t* tgt, uint8_t* type, int32_t* bound) {
+  for (int64_t q = 0; q < m_new; ++q) {
+    src[m + q] = nsrc[q];
+    tgt[m + q] = ntgt[q];
+    type[m + q] = ntype[q];
+    bound[nsrc[q]] += 1;
+    bound[(1 + (int64_t)ntype[q]) * n + ntgt[q]] += 1;
+  }
+}
+
+// One step; z [3][n], bound [3][n] and the list (m entries) are updated in place,
+// vac [3][n] receives the vacant elements. Returns the new list length.
+int64_t oracle_plasticity_step(int64_t n, int64_t m, double nu, double eps, double eta,
+                               int32_t steps, double ca_mean, double ca_sd, double delete_frac,
+                               uint64_t seed, uint64_t step, double* z, int32_t* bound,
+                               int32_t* src, int32_t* tgt, uint8_t* type, int32_t* vac) {
+  for (int64_t k = 0; k < 3; ++k)
+    for (int64_t j = 0; j < n; ++j) {
+      const double ca = oracle_calcium(seed, (uint64_t)j, (uint64_t)k, step, ca_mean, ca_sd);
+      const double zz = z[k * n + j] + oracle_growth_delta(ca, nu, eps, eta, steps);
+      z[k * n + j] = zz > 0.0 ? zz : 0.0;
+    }
+  std::vector<char> dead(m, 0);
+  auto unbind = [&](int64_t s) {
+    dead[s] = 1;
+    bound[src[s]] -= 1;
+    bound[(1 + (int64_t)type[s]) * n + tgt[s]] -= 1;
+  };
+  // deletion
+  const int64_t n_del = (int64_t)std::floor(delete_frac * (double)m + 0.5);
+  {
+    std::vector<std::pair<uint64_t, int64_t>> pr(m);
+    for (int64_t s = 0; s < m; ++s) {
+      P4 ctr = {{(uint64_t)s, step, 0, 0}};
+      pr[s] = {philox4x64_10(ctr, seed, 3).v[0], s};
+    }
+    std::sort(pr.begin(), pr.end());
+    for (int64_t q = 0; q < n_del && q < m; ++q) unbind(pr[q].second);
+  }
+  // retraction, kind by kind
+  for (int k = 0; k < 3; ++k) {
+    std::vector<int64_t> excess(n);
+    for (int64_t j = 0; j < n; ++j)
+      excess[j] = (int64_t)bound[k * n + j] - (int64_t)std::floor(z[k * n + j]);
+    struct C { int64_t owner; uint32_t q; int64_t s; };
+    std::vector<C> cand;
+    for (int64_t s = 0; s < m; ++s) {
+      if (dead[s]) continue;
+      int64_t owner;
+      if (k == 0) owner = src[s];
+      else if ((int)type[s] == k - 1) owner = tgt[s];
+      else continue;
+      if (excess[owner] <= 0) continue;
+      P4 ctr = {{(uint64_t)s, step, (uint64_t)k, 0}};
+      cand.push_back({owner, (uint32_t)(philox4x64_10(ctr, seed, 4).v[0] >> 32), s});
+    }
+    std::sort(cand.begin(), cand.end(), [](const C& a, const C& b) {
+      if (a.owner != b.owner) return a.owner < b.owner;
+      if (a.q != b.q) return a.q < b.q;
+      return a.s < b.s;
+    });
+    for (size_t p = 0; p < cand.size();) {
+      size_t e = p;
+      while (e < cand.size() && cand[e].owner == cand[p].owner) ++e;
+      const int64_t drop = std::min<int64_t>(excess[cand[p].owner], (int64_t)(e - p));
+      for (int64_t q = 0; q < drop; ++q) unbind(cand[p + q].s);
+      p = e;
+    }
+  }
+  int64_t w = 0;
+  for (int64_t s = 0; s < m; ++s) {
+    if (dead[s]) continue;
+    src[w] = src[s];
+    tgt[w] = tgt[s];
+    type[w] = type[s];
+    ++w;
+  }
+  for (int64_t k = 0; k < 3; ++k)
+    for (int64_t j = 0; j < n; ++j)
+      vac[k * n + j] = (int32_t)((int64_t)std::floor(z[k * n + j]) - bound[k * n + j]);
+  return w;
+}
+
 }  // extern "C"

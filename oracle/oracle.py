@@ -6,8 +6,9 @@ module. It shares no code with the HIP library and never imports it.
 The oracle follows the MSP connectivity update of arXiv 2509.26193: the octree and
 its vacancy aggregates (Sec. III-B, "Spatial octree" and "Division of work"), the
 Barnes-Hut target search with restarts (Sec. III-B, "Division of work"; Sec. II for
-theta = 0), the random acceptance of requests (Sec. III-A, "Update of synapses")
-and the expected-attraction adjoint used by the differentiated form.
+theta = 0), the random acceptance of requests (Sec. III-A, "Update of synapses"), the
+expected-attraction adjoint used by the differentiated form, and the growth and
+deletion of synaptic elements between updates (Sec. III-A).
 """
 from __future__ import annotations
 
@@ -68,6 +69,16 @@ def lib():
         L.oracle_attraction_frozen.restype = _dbl
         L.oracle_attraction_frozen.argtypes = [_ptr, _ptr, _ptr, _dbl, _dbl, _ptr, _ptr,
                                                ctypes.c_int]
+        L.oracle_growth_delta.restype = _dbl
+        L.oracle_growth_delta.argtypes = [_dbl, _dbl, _dbl, _dbl, ctypes.c_int32]
+        L.oracle_calcium.restype = _dbl
+        L.oracle_calcium.argtypes = [_u64, _u64, _u64, _u64, _dbl, _dbl]
+        L.oracle_plasticity_record.argtypes = [_i64, _i64, _i64, _ptr, _ptr, _ptr, _ptr, _ptr,
+                                               _ptr, _ptr]
+        L.oracle_plasticity_step.restype = _i64
+        L.oracle_plasticity_step.argtypes = [_i64, _i64, _dbl, _dbl, _dbl, ctypes.c_int32, _dbl,
+                                             _dbl, _dbl, _u64, _u64, _ptr, _ptr, _ptr, _ptr,
+                                             _ptr, _ptr]
         _lib = L
     return _lib
 
@@ -225,3 +236,55 @@ def commit(elem_offset, target, neuron_type, vac_axon, vac_exc, vac_inh, seed, s
                                 int(step), _p(ss), _p(st), _p(sy), _p(acc)))
     return dict(syn_src=ss[:m].copy(), syn_tgt=st[:m].copy(), syn_type=sy[:m].copy(),
                 vac_axon=a, vac_exc=e, vac_inh=i, n_formed=m, accepted=acc[:S].copy())
+
+
+# --------------------------------------------------------------------------- plasticity
+PLASTICITY = dict(nu=0.001, eps=0.7, eta=0.4, steps=100, ca_mean=0.7, ca_sd=0.1,
+                  delete_frac=0.1)
+
+
+def growth_delta(ca: float, nu=0.001, eps=0.7, eta=0.4, steps=100) -> float:
+    return float(lib().oracle_growth_delta(float(ca), nu, eps, eta, int(steps)))
+
+
+def calcium(seed: int, j: int, k: int, step: int, mean=0.7, sd=0.1) -> float:
+    return float(lib().oracle_calcium(int(seed), int(j), int(k), int(step), mean, sd))
+
+
+class Network:
+    """Element counts z [3, n] (float64: axon, excitatory and inhibitory dendrite),
+    bound elements [3, n] (int32) and the synapse list, with the oracle's record and
+    step."""
+
+    def __init__(self, vac_axon, vac_exc, vac_inh, capacity: int):
+        self.n = int(np.asarray(vac_axon).size)
+        self.z = np.ascontiguousarray(np.stack([vac_axon, vac_exc, vac_inh]).astype(np.float64))
+        self.bound = np.zeros((3, self.n), np.int32)
+        self.src = np.zeros(max(capacity, 1), np.int32)
+        self.tgt = np.zeros(max(capacity, 1), np.int32)
+        self.type = np.zeros(max(capacity, 1), np.uint8)
+        self.m = 0
+
+    def record(self, syn_src, syn_tgt, syn_type) -> None:
+        ns = np.ascontiguousarray(syn_src, dtype=np.int32)
+        nt = np.ascontiguousarray(syn_tgt, dtype=np.int32)
+        ny = np.ascontiguousarray(syn_type, dtype=np.uint8)
+        if self.m + ns.size > self.src.size:
+            raise ValueError("synapse capacity exceeded")
+        lib().oracle_plasticity_record(self.n, self.m, ns.size, _p(ns), _p(nt), _p(ny),
+                                       _p(self.src), _p(self.tgt), _p(self.type),
+                                       _p(self.bound))
+        self.m += ns.size
+
+    def step(self, seed: int, step: int, params=None):
+        """Returns the vacant elements (axon, exc, inh) for the next update."""
+        p = dict(PLASTICITY, **(params or {}))
+        vac = np.zeros((3, self.n), np.int32)
+        self.m = int(lib().oracle_plasticity_step(
+            self.n, self.m, p["nu"], p["eps"], p["eta"], int(p["steps"]), p["ca_mean"],
+            p["ca_sd"], p["delete_frac"], int(seed), int(step), _p(self.z), _p(self.bound),
+            _p(self.src), _p(self.tgt), _p(self.type), _p(vac)))
+        return vac[0].copy(), vac[1].copy(), vac[2].copy()
+
+    def synapses(self):
+        return self.src[:self.m].copy(), self.tgt[:self.m].copy(), self.type[:self.m].copy()
