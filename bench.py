@@ -290,38 +290,42 @@ def bench_batched(msp, torch, reps=5):
 
 def bench_plasticity(msp, torch, updates=3):
     """The first updates of the 100-update workload (2^23 neurons uniform in a 20,000 um
-    cube): the octree is built once (positions are fixed); each update refreshes the
-    vacancies, searches and commits on the device. The host-side element growth and
-    synapse deletion between updates is not timed."""
-    from synth_inputs import config_large, plasticity_init, plasticity_record, plasticity_step
+    cube), entirely on the device: the octree is built once (positions are fixed); each
+    update refreshes the vacancies, searches and commits, then records the new synapses
+    and runs the plasticity step (growth, deletion, retraction) that gives the next
+    update's vacancies."""
+    from synth_inputs import config_large
     dev = torch.device("cuda:0")
     T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
     w = config_large()
     tree = msp.build_octree(T(w.pos, torch.float64), w.box_min, w.box_edge)
     ty = T(w.neuron_type, torch.uint8)
-    state = plasticity_init(w)
-    vac = (w.vac_axon, w.vac_exc, w.vac_inh)
+    ga, ge, gi = (T(v, torch.int32) for v in (w.vac_axon, w.vac_exc, w.vac_inh))
+    net = msp.Network(ga, ge, gi, capacity=4 * w.n)
     per = []
     for step in range(updates):
-        ga, ge, gi = (T(v, torch.int32) for v in vac)
-        S = int(np.maximum(vac[0], 0).sum())
+        S = int(ga.sum().item())
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         msp.update_vacant_counts(tree, ge, gi)
         tgt, off = msp.find_targets(tree, ty, ga, w.sigma, w.theta, w.seed, step)
         res = msp.commit_synapses(tgt, off, ty, ga, ge, gi, w.seed, step, syn_capacity=S)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        net.record(res["syn_src"], res["syn_tgt"], res["syn_type"])
+        ga, ge, gi = net.step(w.seed, step)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
         m = int(res["n_formed"])
-        per.append(dict(update=step, searches=S, formed=m, ms=dt * 1e3, searches_per_s=S / dt))
-        log(f"plasticity update {step}: {S} searches, {m} formed, {dt * 1e3:.1f} ms")
-        plasticity_record(state, res["syn_src"].cpu().numpy(), res["syn_tgt"].cpu().numpy(),
-                          res["syn_type"].cpu().numpy())
-        vac = plasticity_step(state, w.neuron_type, w.seed, step)
+        per.append(dict(update=step, searches=S, formed=m, synapses=net.m,
+                        connectivity_ms=(t1 - t0) * 1e3, plasticity_ms=(t2 - t1) * 1e3,
+                        searches_per_s=S / (t1 - t0)))
+        log(f"plasticity update {step}: {S} searches, {m} formed, {net.m} synapses; "
+            f"connectivity {(t1 - t0) * 1e3:.1f} ms, plasticity step {(t2 - t1) * 1e3:.1f} ms")
     tree.free()
     return dict(workload=f"plasticity_{w.n}_uniform_20000um", updates=per,
-                note="refresh + search + commit per update on a fixed octree; the host growth "
-                     "and deletion between updates are not timed")
+                note="per update: refresh + search + commit (connectivity), then record + "
+                     "growth/deletion/retraction (plasticity step), all on the device")
 
 
 def study_complexity(msp, torch, log2_ns=(12, 14, 16, 18, 20, 22, 23),

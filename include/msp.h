@@ -287,6 +287,69 @@ msp_status msp_octree_export_topology(msp_octree t, int32_t* order, uint64_t* ke
 msp_status msp_octree_export_aggregates(msp_octree t, int32_t type, int64_t* count,
                                         double* centroid, hipStream_t s);
 
+/* ------------------------------------------------------------------------------------
+ * Plasticity between connectivity updates (Sec. III-A, "Update of synaptic elements"
+ * and the first sub-phase of "Update of synapses"): the element counts of every
+ * neuron grow or retract with its calcium, synapses are deleted at random, and
+ * retracted elements that were bound break random synapses. With these two calls the
+ * whole multi-update loop stays on the device.
+ *
+ * State (device, owned by the caller):
+ *   z [3][n] float64: continuous element counts, kinds 0 axon, 1 excitatory dendrite,
+ *     2 inhibitory dendrite;
+ *   bound [3][n] int32: elements of each kind bound in synapses;
+ *   syn_src, syn_tgt [m] int32 and syn_type [m] uint8 (0 excitatory, 1 inhibitory: the
+ *     source's type): the synapse list, in the order the synapses were recorded. A
+ *     synapse (i, g, type) binds one axonal element of i and one dendritic element of
+ *     kind 1 + type of g.
+ * ------------------------------------------------------------------------------------ */
+typedef struct msp_plasticity_params {
+  double growth_rate;       /* nu: element growth per simulation step at the peak */
+  double target_calcium;    /* eps: calcium at which elements neither grow nor retract */
+  double growth_onset;      /* eta: calcium below which elements retract */
+  double calcium_mean;      /* calcium is drawn from N(calcium_mean, calcium_sd) */
+  double calcium_sd;
+  double delete_fraction;   /* share of the synapses deleted at random per update */
+  int32_t steps_per_update; /* simulation steps between two connectivity updates */
+} msp_plasticity_params;
+
+/*
+ * Append m_new synapses (device arrays new_src, new_tgt, new_type, e.g. a commit's
+ * output) at [m, m + m_new) of the list and bind their elements in bound [3][n].
+ * Errors: MSP_ERR_CAPACITY if m + m_new > capacity (nothing written); MSP_ERR_INVALID
+ * for n < 1, m < 0, m_new < 0, or a neuron id outside [0, n) or a type > 1 (found on
+ * the device: the list is appended but such a synapse binds nothing). Waits on `s`.
+ */
+msp_status msp_plasticity_record(int64_t n, const int32_t* new_src, const int32_t* new_tgt,
+                                 const uint8_t* new_type, int64_t m_new, int32_t* syn_src,
+                                 int32_t* syn_tgt, uint8_t* syn_type, int64_t m, int64_t capacity,
+                                 int32_t* bound, hipStream_t s);
+
+/*
+ * One step between update `step` and the next, in this order:
+ *   1. growth: calcium Ca of neuron j, kind k = calcium_mean + calcium_sd * G, G from
+ *      Box-Muller on words 0 and 1 of Philox4x64-10 with key (seed, 2) and counter
+ *      (j, k, step, 0): u1 = ((w0 >> 11) + 1) 2^-53, u2 = (w1 >> 11) 2^-53,
+ *      G = sqrt(-2 ln u1) cos(2 pi u2); then z += steps * nu * (2 exp(-((Ca - xi) /
+ *      zeta)^2) - 1), xi = (eta + eps) / 2, zeta = (eps - eta) / (2 sqrt(ln 2)), and z
+ *      is clamped at 0;
+ *   2. deletion: the floor(delete_fraction * m + 0.5) synapses of smallest (word 0 of
+ *      Philox key (seed, 3), counter (s, step, 0, 0); then s) are deleted, s being the
+ *      synapse's place in the list at the start of the step;
+ *   3. retraction, for kinds k = 0, 1, 2 in turn: a neuron with bound > floor(z) of
+ *      kind k loses that many of its synapses of that kind, those of smallest (top 32
+ *      bits of word 0 of Philox key (seed, 4), counter (s, step, k, 0); then s);
+ *   4. the list is compacted in order; *m_out (host) = its new length;
+ *   5. vac_axon, vac_exc, vac_inh [n] int32 = floor(z) - bound of each kind.
+ * Errors: MSP_ERR_INVALID for n < 1, m < 0 or m >= 2^31, a null pointer or parameters
+ * that are not finite (or growth_onset >= target_calcium). Waits on `s`.
+ */
+msp_status msp_plasticity_step(int64_t n, const msp_plasticity_params* params, uint64_t seed,
+                               uint64_t step, double* z, int32_t* bound, int32_t* syn_src,
+                               int32_t* syn_tgt, uint8_t* syn_type, int64_t m, int64_t* m_out,
+                               int32_t* vac_axon, int32_t* vac_exc, int32_t* vac_inh,
+                               hipStream_t s);
+
 #ifdef __cplusplus
 }
 #endif

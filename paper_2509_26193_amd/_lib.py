@@ -49,6 +49,12 @@ class SimSpec(ctypes.Structure):
                 ("capacity_S", _i64)]
 
 
+class PlasticityParams(ctypes.Structure):
+    _fields_ = [("growth_rate", _dbl), ("target_calcium", _dbl), ("growth_onset", _dbl),
+                ("calcium_mean", _dbl), ("calcium_sd", _dbl), ("delete_fraction", _dbl),
+                ("steps_per_update", _i32)]
+
+
 _SIGS = {
     "msp_status_string": (ctypes.c_char_p, [_i32]),
     "msp_sync": (_i32, [_vp]),
@@ -72,6 +78,10 @@ _SIGS = {
     "msp_batch_free": (None, [_vp]),
     "msp_attraction_fwd": (_i32, [_vp, _vp, _vp, _dbl, _dbl, _vp, _vp]),
     "msp_attraction_bwd": (_i32, [_vp, _vp, _vp, _dbl, _dbl, _vp, _vp, _vp, _vp]),
+    "msp_plasticity_record": (_i32, [_i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _i64, _i64, _vp,
+                                     _vp]),
+    "msp_plasticity_step": (_i32, [_i64, ctypes.POINTER(PlasticityParams), _u64, _u64, _vp, _vp,
+                                   _vp, _vp, _vp, _i64, ctypes.POINTER(_i64), _vp, _vp, _vp, _vp]),
 }
 
 MSP_BATCH_GRAPH = 1
@@ -427,3 +437,56 @@ def attraction(pos: torch.Tensor, sigma: torch.Tensor, tree: Octree, neuron_type
                theta: float) -> torch.Tensor:
     """Differentiable Z (see AttractionFn)."""
     return AttractionFn.apply(pos, sigma, tree, neuron_type, vac_axon, theta)
+
+
+PLASTICITY = dict(growth_rate=0.001, target_calcium=0.7, growth_onset=0.4, calcium_mean=0.7,
+                  calcium_sd=0.1, delete_fraction=0.1, steps_per_update=100)
+
+
+class Network:
+    """Device state of the plasticity between updates: element counts z [3][n]
+    (float64; kinds axon, excitatory dendrite, inhibitory dendrite), bound elements
+    [3][n] (int32) and the synapse list (capacity entries, m used)."""
+
+    def __init__(self, vac_axon: torch.Tensor, vac_exc: torch.Tensor, vac_inh: torch.Tensor,
+                 capacity: int):
+        dev = vac_axon.device
+        self.n = vac_axon.numel()
+        self.z = torch.stack([vac_axon, vac_exc, vac_inh]).to(torch.float64).contiguous()
+        self.bound = torch.zeros((3, self.n), dtype=torch.int32, device=dev)
+        self.src = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+        self.tgt = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+        self.type = torch.empty(max(capacity, 1), dtype=torch.uint8, device=dev)
+        self.m = 0
+
+    def record(self, syn_src: torch.Tensor, syn_tgt: torch.Tensor, syn_type: torch.Tensor,
+               stream=None) -> None:
+        """Append synapses (e.g. commit_synapses' output) and bind their elements."""
+        k = syn_src.numel()
+        if k == 0:
+            return
+        _check(lib().msp_plasticity_record(
+            self.n, _dev(syn_src, torch.int32, "syn_src", k), _dev(syn_tgt, torch.int32, "syn_tgt", k),
+            _dev(syn_type, torch.uint8, "syn_type", k), k, self.src.data_ptr(),
+            self.tgt.data_ptr(), self.type.data_ptr(), self.m, self.src.numel(),
+            self.bound.data_ptr(), _stream(stream)), "plasticity_record")
+        self.m += k
+
+    def step(self, seed: int, step: int, params: dict | None = None, stream=None):
+        """Growth, deletion and retraction after update `step`; returns the vacant
+        elements (axon, exc, inh) as int32 device tensors for the next update."""
+        p = PlasticityParams(**dict(PLASTICITY, **(params or {})))
+        va = torch.empty(self.n, dtype=torch.int32, device=self.z.device)
+        ve = torch.empty_like(va)
+        vi = torch.empty_like(va)
+        m_out = _i64(0)
+        _check(lib().msp_plasticity_step(
+            self.n, ctypes.byref(p), int(seed), int(step), self.z.data_ptr(), self.bound.data_ptr(),
+            self.src.data_ptr(), self.tgt.data_ptr(), self.type.data_ptr(), self.m,
+            ctypes.byref(m_out), va.data_ptr(), ve.data_ptr(), vi.data_ptr(), _stream(stream)),
+            "plasticity_step")
+        self.m = int(m_out.value)
+        return va, ve, vi
+
+    def synapses(self):
+        return self.src[:self.m], self.tgt[:self.m], self.type[:self.m]

@@ -14,6 +14,7 @@
 #include "batch.hpp"
 #include "attraction.hpp"
 #include "commit.hpp"
+#include "plasticity.hpp"
 
 using namespace msp;
 
@@ -878,6 +879,133 @@ msp_status msp_attraction_bwd(msp_octree t, const uint8_t* neuron_type, const in
                               double* dsigma, hipStream_t s) {
   return attraction(t, neuron_type, vac_axon, sigma_um, theta, true, nullptr, gZ, dpos, dsigma,
                     s);
+}
+
+// ---------------------------------------------------------------------------
+// Plasticity between updates
+// ---------------------------------------------------------------------------
+msp_status msp_plasticity_record(int64_t n, const int32_t* new_src, const int32_t* new_tgt,
+                                 const uint8_t* new_type, int64_t m_new, int32_t* syn_src,
+                                 int32_t* syn_tgt, uint8_t* syn_type, int64_t m, int64_t capacity,
+                                 int32_t* bound, hipStream_t s) {
+  if (n < 1 || m < 0 || m_new < 0 || !bound) return MSP_ERR_INVALID;
+  if (m_new == 0) return MSP_OK;
+  if (!new_src || !new_tgt || !new_type || !syn_src || !syn_tgt || !syn_type)
+    return MSP_ERR_INVALID;
+  if (m + m_new > capacity) return MSP_ERR_CAPACITY;
+  MSP_HIP_TRY(hipMemcpyAsync(syn_src + m, new_src, sizeof(int32_t) * m_new,
+                             hipMemcpyDeviceToDevice, s));
+  MSP_HIP_TRY(hipMemcpyAsync(syn_tgt + m, new_tgt, sizeof(int32_t) * m_new,
+                             hipMemcpyDeviceToDevice, s));
+  MSP_HIP_TRY(hipMemcpyAsync(syn_type + m, new_type, sizeof(uint8_t) * m_new,
+                             hipMemcpyDeviceToDevice, s));
+  Temp err(s);
+  MSP_HIP_TRY(err.alloc(sizeof(int32_t)));
+  fill_i32_k<<<1, 64, 0, s>>>(err.as<int32_t>(), 1, 0);
+  bind_k<<<grid_for(m_new, kPlastBlock), kPlastBlock, 0, s>>>(new_src, new_tgt, new_type, m_new,
+                                                            n, bound, err.as<int32_t>());
+  MSP_HIP_TRY(hipGetLastError());
+  int32_t bad = 0;
+  MSP_HIP_TRY(hipMemcpyAsync(&bad, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MSP_HIP_TRY(hipStreamSynchronize(s));
+  return bad ? MSP_ERR_INVALID : MSP_OK;
+}
+
+msp_status msp_plasticity_step(int64_t n, const msp_plasticity_params* params, uint64_t seed,
+                               uint64_t step, double* z, int32_t* bound, int32_t* syn_src,
+                               int32_t* syn_tgt, uint8_t* syn_type, int64_t m, int64_t* m_out,
+                               int32_t* vac_axon, int32_t* vac_exc, int32_t* vac_inh,
+                               hipStream_t s) {
+  if (n < 1 || m < 0 || m >= ((int64_t)1 << 31) || !params || !z || !bound || !m_out ||
+      !vac_axon || !vac_exc || !vac_inh)
+    return MSP_ERR_INVALID;
+  if (m > 0 && (!syn_src || !syn_tgt || !syn_type)) return MSP_ERR_INVALID;
+  const msp_plasticity_params& p = *params;
+  const double vals[] = {p.growth_rate, p.target_calcium, p.growth_onset, p.calcium_mean,
+                         p.calcium_sd, p.delete_fraction};
+  for (double v : vals)
+    if (!std::isfinite(v)) return MSP_ERR_INVALID;
+  if (!(p.growth_onset < p.target_calcium) || p.delete_fraction < 0.0 || p.delete_fraction > 1.0 ||
+      p.steps_per_update < 0)
+    return MSP_ERR_INVALID;
+  // the same double expressions as the definition, evaluated once
+  const double scale = (double)p.steps_per_update * p.growth_rate;
+  const double xi = 0.5 * (p.growth_onset + p.target_calcium);
+  const double zeta = (p.target_calcium - p.growth_onset) / (2.0 * std::sqrt(std::log(2.0)));
+  growth_k<<<grid_for(3 * n, kPlastBlock), kPlastBlock, 0, s>>>(
+      z, n, seed, step, p.calcium_mean, p.calcium_sd, xi, zeta, scale);
+  MSP_HIP_TRY(hipGetLastError());
+  int64_t M = m;
+  if (m > 0) {
+    const SynList L{syn_src, syn_tgt, syn_type};
+    Temp dead(s), k0(s), v0(s), k1(s), v1(s), pos(s), exc(s), o_src(s), o_tgt(s), o_type(s);
+    MSP_HIP_TRY(dead.alloc(sizeof(uint8_t) * m));
+    MSP_HIP_TRY(k0.alloc(sizeof(uint64_t) * m));
+    MSP_HIP_TRY(v0.alloc(sizeof(int32_t) * m));
+    MSP_HIP_TRY(k1.alloc(sizeof(uint64_t) * m));
+    MSP_HIP_TRY(v1.alloc(sizeof(int32_t) * m));
+    MSP_HIP_TRY(pos.alloc(sizeof(int32_t) * (m + 1)));
+    MSP_HIP_TRY(exc.alloc(sizeof(int32_t) * n));
+    MSP_HIP_TRY(hipMemsetAsync(dead.p, 0, sizeof(uint8_t) * m, s));
+    uint8_t* dd = dead.as<uint8_t>();
+    const int64_t n_del = (int64_t)std::floor(p.delete_fraction * (double)m + 0.5);
+    if (n_del > 0) {
+      del_keys_k<<<grid_for(m, kPlastBlock), kPlastBlock, 0, s>>>(k0.as<uint64_t>(),
+                                                                 v0.as<int32_t>(), m, seed, step);
+      MSP_HIP_TRY(radix_sort_pairs(k0.as<uint64_t>(), v0.as<int32_t>(), k1.as<uint64_t>(),
+                                   v1.as<int32_t>(), m, 64, s));
+      drop_first_k<<<grid_for(n_del, kPlastBlock), kPlastBlock, 0, s>>>(
+          v0.as<int32_t>(), n_del < m ? n_del : m, L, n, dd, bound);
+    }
+    int owner_bits = 1;
+    while (owner_bits < 31 && ((int64_t)1 << owner_bits) < n) ++owner_bits;
+    const int key_bits = (32 + owner_bits + 7) / 8 * 8;
+    for (int k = 0; k < 3; ++k) {
+      excess_k<<<grid_for(n, kPlastBlock), kPlastBlock, 0, s>>>(bound + k * n, z + k * n, n,
+                                                               exc.as<int32_t>());
+      const RetractFlag F{L, dd, exc.as<int32_t>(), k};
+      MSP_HIP_TRY((exclusive_scan<int32_t, int32_t, RetractFlag>(nullptr, pos.as<int32_t>(), m, F,
+                                                                true, s)));
+      int32_t C = 0;
+      MSP_HIP_TRY(hipMemcpyAsync(&C, pos.as<int32_t>() + m, sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, s));
+      MSP_HIP_TRY(hipStreamSynchronize(s));
+      if (C == 0) continue;
+      cand_write_k<<<grid_for(m, kPlastBlock), kPlastBlock, 0, s>>>(
+          F, pos.as<int32_t>(), m, seed, step, k0.as<uint64_t>(), v0.as<int32_t>());
+      MSP_HIP_TRY(radix_sort_pairs(k0.as<uint64_t>(), v0.as<int32_t>(), k1.as<uint64_t>(),
+                                   v1.as<int32_t>(), C, key_bits, s));
+      retract_k<<<grid_for(C, kPlastBlock), kPlastBlock, 0, s>>>(
+          k0.as<uint64_t>(), v0.as<int32_t>(), C, exc.as<int32_t>(), L, n, dd, bound);
+      MSP_HIP_TRY(hipGetLastError());
+    }
+    MSP_HIP_TRY((exclusive_scan<int32_t, int32_t, LiveFlag>(nullptr, pos.as<int32_t>(), m,
+                                                           LiveFlag{dd}, true, s)));
+    int32_t M32 = 0;
+    MSP_HIP_TRY(hipMemcpyAsync(&M32, pos.as<int32_t>() + m, sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
+    MSP_HIP_TRY(hipStreamSynchronize(s));
+    M = M32;
+    if (M < m) {
+      MSP_HIP_TRY(o_src.alloc(sizeof(int32_t) * (M > 0 ? M : 1)));
+      MSP_HIP_TRY(o_tgt.alloc(sizeof(int32_t) * (M > 0 ? M : 1)));
+      MSP_HIP_TRY(o_type.alloc(sizeof(uint8_t) * (M > 0 ? M : 1)));
+      const SynList O{o_src.as<int32_t>(), o_tgt.as<int32_t>(), o_type.as<uint8_t>()};
+      compact_k<<<grid_for(m, kPlastBlock), kPlastBlock, 0, s>>>(L, dd, pos.as<int32_t>(), m, O);
+      MSP_HIP_TRY(hipGetLastError());
+      if (M > 0) {
+        MSP_HIP_TRY(hipMemcpyAsync(syn_src, O.src, sizeof(int32_t) * M, hipMemcpyDeviceToDevice, s));
+        MSP_HIP_TRY(hipMemcpyAsync(syn_tgt, O.tgt, sizeof(int32_t) * M, hipMemcpyDeviceToDevice, s));
+        MSP_HIP_TRY(hipMemcpyAsync(syn_type, O.type, sizeof(uint8_t) * M, hipMemcpyDeviceToDevice, s));
+      }
+    }
+  }
+  vacancy_k<<<grid_for(3 * n, kPlastBlock), kPlastBlock, 0, s>>>(z, bound, n, vac_axon, vac_exc,
+                                                                vac_inh);
+  MSP_HIP_TRY(hipGetLastError());
+  MSP_HIP_TRY(hipStreamSynchronize(s));
+  *m_out = M;
+  return MSP_OK;
 }
 
 }  // extern "C"

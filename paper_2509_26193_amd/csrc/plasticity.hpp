@@ -1,0 +1,186 @@
+// The change of the network between two connectivity updates (Sec. III-A, "Update of
+// synaptic elements" and the first sub-phase of "Update of synapses"), on the device:
+//   * growth: per neuron j and element kind k (0 axon, 1 excitatory dendrite,
+//     2 inhibitory dendrite) a calcium value Ca ~ N(mean, sd) (Box-Muller on Philox
+//     words 0 and 1, key (seed, 2), counter (j, k, step, 0)) moves the continuous
+//     element count by dz = steps * nu * (2 exp(-((Ca - xi) / zeta)^2) - 1), with
+//     xi = (eta + eps) / 2 and zeta = (eps - eta) / (2 sqrt(ln 2)); z = max(z + dz, 0);
+//   * deletion: the round(frac * m) synapses of smallest (Philox word 0, key (seed, 3),
+//     counter (s, step, 0, 0); then s) go, s being the place in the list at the start
+//     of the step;
+//   * retraction, for k = 0, 1, 2 in turn: a neuron whose floor(z) fell below its
+//     bound elements of kind k loses that many of its synapses of that kind, those of
+//     smallest (top 32 bits of Philox word 0, key (seed, 4), counter (s, step, k, 0);
+//     then s);
+//   * a synapse (i, g, type) binds one axonal element of i and one dendritic element
+//     of kind 1 + type of g; breaking it frees both; the list keeps its order;
+//   * vacant elements: floor(z) - bound.
+// Selections are sorts of 64-bit keys (priority, or owner and priority) with the
+// synapse index as a stable tie-break, so every choice is exact and reproducible.
+#pragma once
+
+#include "scan.hpp"
+
+namespace msp {
+
+constexpr int kPlastBlock = 256;
+
+struct SynList {
+  int32_t* src;
+  int32_t* tgt;
+  uint8_t* type;
+};
+
+__global__ void __launch_bounds__(kPlastBlock) growth_k(double* __restrict__ z, int64_t n,
+                                                       uint64_t seed, uint64_t step,
+                                                       double ca_mean, double ca_sd, double xi,
+                                                       double zeta, double scale) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= 3 * n) return;
+  const int64_t k = g / n, j = g - k * n;
+  uint64_t c0 = (uint64_t)j, c1 = (uint64_t)k, c2 = step, c3 = 0;
+  philox4x64_10(c0, c1, c2, c3, seed, 2);
+  const double u1 = (double)((c0 >> 11) + 1) * 0x1p-53;     // (0, 1]
+  const double u2 = (double)(c1 >> 11) * 0x1p-53;           // [0, 1)
+  const double two_pi = 6.283185307179586476925286766559;
+  const double gauss = sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
+  const double ca = ca_mean + ca_sd * gauss;
+  const double r = (ca - xi) / zeta;
+  const double e = exp(-(r * r));
+  const double zz = z[g] + scale * (2.0 * e - 1.0);
+  z[g] = zz > 0.0 ? zz : 0.0;
+}
+
+// Frees the two elements a synapse binds.
+__device__ __forceinline__ void unbind(const SynList& L, int64_t s, int64_t n, int32_t* bound) {
+  atomicSub(&bound[L.src[s]], 1);
+  atomicSub(&bound[(1 + (int64_t)L.type[s]) * n + L.tgt[s]], 1);
+}
+
+__global__ void __launch_bounds__(kPlastBlock) del_keys_k(uint64_t* __restrict__ key,
+                                                         int32_t* __restrict__ val, int64_t m,
+                                                         uint64_t seed, uint64_t step) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= m) return;
+  key[s] = philox_word0(seed, 3, (uint64_t)s, step, 0, 0);
+  val[s] = (int32_t)s;
+}
+
+// The first `cnt` synapses in sorted order go.
+__global__ void __launch_bounds__(kPlastBlock) drop_first_k(const int32_t* __restrict__ val,
+                                                           int64_t cnt, SynList L, int64_t n,
+                                                           uint8_t* __restrict__ dead,
+                                                           int32_t* bound) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= cnt) return;
+  const int64_t s = val[q];
+  dead[s] = 1;
+  unbind(L, s, n, bound);
+}
+
+__global__ void __launch_bounds__(kPlastBlock) excess_k(const int32_t* __restrict__ bound_k,
+                                                       const double* __restrict__ z_k, int64_t n,
+                                                       int32_t* __restrict__ exc) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  exc[j] = bound_k[j] - (int32_t)floor(z_k[j]);
+}
+
+// Owner of synapse s for element kind k, or -1 if s binds no element of that kind.
+__device__ __forceinline__ int32_t owner_of(const SynList& L, int64_t s, int k) {
+  if (k == 0) return L.src[s];
+  return (int)L.type[s] == k - 1 ? L.tgt[s] : -1;
+}
+
+struct RetractFlag {            // live synapse of a neuron with an excess of kind k
+  SynList L;
+  const uint8_t* dead;
+  const int32_t* exc;
+  int k;
+  __device__ int32_t operator()(int32_t, int64_t s) const {
+    if (dead[s]) return 0;
+    const int32_t o = owner_of(L, s, k);
+    return (o >= 0 && exc[o] > 0) ? 1 : 0;
+  }
+};
+
+__global__ void __launch_bounds__(kPlastBlock) cand_write_k(RetractFlag F, const int32_t* __restrict__ pos,
+                                                           int64_t m, uint64_t seed, uint64_t step,
+                                                           uint64_t* __restrict__ key,
+                                                           int32_t* __restrict__ val) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= m || !F(0, s)) return;
+  const int32_t o = owner_of(F.L, s, F.k);
+  const uint64_t q = philox_word0(seed, 4, (uint64_t)s, step, (uint64_t)F.k, 0) >> 32;
+  key[pos[s]] = ((uint64_t)(uint32_t)o << 32) | q;
+  val[pos[s]] = (int32_t)s;
+}
+
+// Candidates sorted by (owner, priority, s): the first exc[owner] of each owner go.
+__global__ void __launch_bounds__(kPlastBlock) retract_k(const uint64_t* __restrict__ key,
+                                                        const int32_t* __restrict__ val,
+                                                        int64_t cnt, const int32_t* __restrict__ exc,
+                                                        SynList L, int64_t n,
+                                                        uint8_t* __restrict__ dead, int32_t* bound) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= cnt) return;
+  const uint64_t o = key[p] >> 32;
+  // first candidate of this owner
+  int64_t lo = 0, hi = p;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((key[mid] >> 32) < o) lo = mid + 1; else hi = mid;
+  }
+  if (p - lo < (int64_t)exc[o]) {
+    const int64_t s = val[p];
+    dead[s] = 1;
+    unbind(L, s, n, bound);
+  }
+}
+
+struct LiveFlag {
+  const uint8_t* dead;
+  __device__ int32_t operator()(int32_t, int64_t s) const { return dead[s] ? 0 : 1; }
+};
+
+__global__ void __launch_bounds__(kPlastBlock) compact_k(SynList in, const uint8_t* __restrict__ dead,
+                                                        const int32_t* __restrict__ pos, int64_t m,
+                                                        SynList out) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= m || dead[s]) return;
+  const int64_t p = pos[s];
+  out.src[p] = in.src[s];
+  out.tgt[p] = in.tgt[s];
+  out.type[p] = in.type[s];
+}
+
+__global__ void __launch_bounds__(kPlastBlock) vacancy_k(const double* __restrict__ z,
+                                                        const int32_t* __restrict__ bound,
+                                                        int64_t n, int32_t* va, int32_t* ve,
+                                                        int32_t* vi) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= 3 * n) return;
+  const int64_t k = g / n, j = g - k * n;
+  int32_t* out = k == 0 ? va : k == 1 ? ve : vi;
+  out[j] = (int32_t)floor(z[g]) - bound[g];
+}
+
+// New synapses (appended by the caller) bind their elements.
+__global__ void __launch_bounds__(kPlastBlock) bind_k(const int32_t* __restrict__ src,
+                                                     const int32_t* __restrict__ tgt,
+                                                     const uint8_t* __restrict__ type,
+                                                     int64_t cnt, int64_t n, int32_t* bound,
+                                                     int32_t* err) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= cnt) return;
+  const int32_t i = src[q], g = tgt[q];
+  const uint8_t ty = type[q];
+  if (i < 0 || i >= n || g < 0 || g >= n || ty > 1) {
+    atomicOr(err, 1);
+    return;
+  }
+  atomicAdd(&bound[i], 1);
+  atomicAdd(&bound[(1 + (int64_t)ty) * n + g], 1);
+}
+
+}  // namespace msp

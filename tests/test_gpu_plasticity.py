@@ -1,8 +1,10 @@
 """The 100-update workload on the GPU: positions fixed, the octree built once, then per
-update a vacancy refresh, the search and the commit on the device, with the host-side
-element growth and synapse deletion in between (Sec. III-A). Every update is checked
-against the oracle fed the same pre-update state; a resumed run equals an
-uninterrupted one bitwise."""
+update a vacancy refresh, the search and the commit on the device, with the element
+growth and synapse deletion in between (Sec. III-A). Every update is checked against
+the oracle fed the same pre-update state; a resumed run equals an uninterrupted one
+bitwise. The first tests run the growth and deletion on the host (input generation);
+the last ones run the device's plasticity step (msp_plasticity_step) and compare it
+with the oracle's step: element counts to 1e-12, everything integer bitwise."""
 import numpy as np
 import pytest
 import torch
@@ -109,4 +111,110 @@ def test_updates_8388608_sampled_oracle():
         plasticity_record(state, g["syn_src"], g["syn_tgt"], g["syn_type"])
         vac = plasticity_step(state, w.neuron_type, w.seed, step)
         say(f"[8M update {step}] formed {g['syn_src'].size}, synapses {state.syn_src.size}")
+    tree.free()
+
+
+# ---------------------------------------------------------------------------- device step
+def _device_and_oracle_networks(w, cap):
+    """One connectivity update on the device, its synapses recorded on both sides."""
+    tree = msp.build_octree(T(w.pos, torch.float64), w.box_min, w.box_edge)
+    ty = T(w.neuron_type, torch.uint8)
+    g = _gpu_update(tree, w, ty, (w.vac_axon, w.vac_exc, w.vac_inh), 0)
+    dnet = msp.Network(T(w.vac_axon, torch.int32), T(w.vac_exc, torch.int32),
+                       T(w.vac_inh, torch.int32), capacity=cap)
+    dnet.record(T(g["syn_src"], torch.int32), T(g["syn_tgt"], torch.int32),
+                T(g["syn_type"], torch.uint8))
+    onet = orc.Network(w.vac_axon, w.vac_exc, w.vac_inh, capacity=cap)
+    onet.record(g["syn_src"], g["syn_tgt"], g["syn_type"])
+    return tree, ty, dnet, onet
+
+
+def _compare_networks(dnet, onet, dvac, ovac, label):
+    """Element counts to 1e-12, then every integer bitwise. floor(z) decides integers:
+    where the two floors differ, the oracle's z must lie within rounding of an integer
+    (calcium next to the target leaves z next to its old integer value); the states
+    then legitimately part and the caller stops comparing (returns False)."""
+    torch.cuda.synchronize()
+    z = dnet.z.cpu().numpy()
+    err = np.abs(z - onet.z).max()
+    frac = np.abs(onet.z - np.round(onet.z))
+    near = int(((frac < 1e-9) & (onet.z != np.round(onet.z))).sum())
+    split = np.floor(z) != np.floor(onet.z)
+    say(f"[{label}] m={dnet.m} (oracle {onet.m}) max |dz|={err:.2e} near-integer z={near} "
+        f"floors differing={int(split.sum())}")
+    assert err <= 1e-12 * max(1.0, np.abs(onet.z).max())
+    if split.any():
+        assert np.all(frac[split] < 1e-9)
+        return False
+    assert dnet.m == onet.m
+    assert np.array_equal(dnet.bound.cpu().numpy(), onet.bound)
+    for a, b in zip(dnet.synapses(), onet.synapses()):
+        assert np.array_equal(a.cpu().numpy(), b)
+    for a, b in zip(dvac, ovac):
+        assert np.array_equal(a.cpu().numpy(), b)
+    return True
+
+
+def test_device_plasticity_step_matches_oracle():
+    w = uniform_cube(65536, 20000.0 * (65536 / float(1 << 23)) ** (1.0 / 3.0), seed=13)
+    tree, _, dnet, onet = _device_and_oracle_networks(w, cap=400000)
+    for step in range(5):
+        dvac = dnet.step(w.seed, step)
+        ovac = onet.step(w.seed, step)
+        assert _compare_networks(dnet, onet, dvac, ovac, f"step {step}")
+    # parameters that force heavy retraction (calcium far below the onset)
+    for step in range(5, 8):
+        p = dict(calcium_mean=0.1, calcium_sd=0.05, delete_fraction=0.03)
+        dvac = dnet.step(w.seed, step, p)
+        ovac = onet.step(w.seed, step, dict(ca_mean=0.1, ca_sd=0.05, delete_frac=0.03))
+        assert _compare_networks(dnet, onet, dvac, ovac, f"retracting step {step}")
+    tree.free()
+
+
+def _sync_oracle(onet, dnet):
+    """The oracle's network := the device's (each update then starts from one state)."""
+    torch.cuda.synchronize()
+    onet.z[:] = dnet.z.cpu().numpy()
+    onet.bound[:] = dnet.bound.cpu().numpy()
+    for dst, t in zip((onet.src, onet.tgt, onet.type), dnet.synapses()):
+        dst[:dnet.m] = t.cpu().numpy()
+    onet.m = dnet.m
+
+
+def test_device_loop_8388608_matches_oracle():
+    """Three updates of the 8M workload entirely on the device (search, commit, record,
+    plasticity step). Per update the oracle starts from the device's state, samples the
+    searches, and replays the commit of the device's proposals and the step."""
+    w = config_large()
+    tree = msp.build_octree(T(w.pos, torch.float64), w.box_min, w.box_edge)
+    ty = T(w.neuron_type, torch.uint8)
+    otree = orc.OracleTree(w.pos, w.box_min, w.box_edge)
+    dnet = msp.Network(T(w.vac_axon, torch.int32), T(w.vac_exc, torch.int32),
+                       T(w.vac_inh, torch.int32), capacity=20_000_000)
+    onet = orc.Network(w.vac_axon, w.vac_exc, w.vac_inh, capacity=20_000_000)
+    ga, ge, gi = (T(v, torch.int32) for v in (w.vac_axon, w.vac_exc, w.vac_inh))
+    rng = np.random.default_rng(77)
+    agreed = 0
+    for step in range(3):
+        _sync_oracle(onet, dnet)
+        a, e, i = (v.cpu().numpy() for v in (ga, ge, gi))
+        msp.update_vacant_counts(tree, ge, gi)
+        tgt, off, z0, _ = msp.find_targets(tree, ty, ga, w.sigma, w.theta, w.seed, step, diag=True)
+        res = msp.commit_synapses(tgt, off, ty, ga, ge, gi, w.seed, step)
+        dnet.record(res["syn_src"], res["syn_tgt"], res["syn_type"])
+        ga, ge, gi = dnet.step(w.seed, step)
+        # oracle: sampled searches, then commit of the device's proposals and the step
+        gt = tgt.cpu().numpy().astype(np.int64)
+        otree.update_counts(e, i)
+        ooff, src, elem = orc.search_list(a)
+        pick = np.sort(rng.choice(src.size, size=min(32768, src.size), replace=False))
+        o = otree.find_targets(w.neuron_type, w.sigma, w.theta, w.seed, step, src[pick], elem[pick])
+        diff = gt[pick] != o["target"]
+        assert int((diff & ~(o["window"] < WINDOW)).sum()) == 0
+        oc = orc.commit(ooff, gt, w.neuron_type, a, e, i, w.seed, step)
+        assert np.array_equal(res["syn_src"].cpu().numpy(), oc["syn_src"])
+        onet.record(oc["syn_src"], oc["syn_tgt"], oc["syn_type"])
+        ovac = onet.step(w.seed, step)
+        agreed += _compare_networks(dnet, onet, (ga, ge, gi), ovac, f"8M update {step}")
+    assert agreed >= 2
     tree.free()
