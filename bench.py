@@ -320,12 +320,20 @@ def bench_plasticity(msp, torch, updates=3):
         per.append(dict(update=step, searches=S, formed=m, synapses=net.m,
                         connectivity_ms=(t1 - t0) * 1e3, plasticity_ms=(t2 - t1) * 1e3,
                         searches_per_s=S / (t1 - t0)))
-        log(f"plasticity update {step}: {S} searches, {m} formed, {net.m} synapses; "
-            f"connectivity {(t1 - t0) * 1e3:.1f} ms, plasticity step {(t2 - t1) * 1e3:.1f} ms")
+        if step < 3 or step % 10 == 9:
+            log(f"plasticity update {step}: {S} searches, {m} formed, {net.m} synapses; "
+                f"connectivity {(t1 - t0) * 1e3:.1f} ms, plasticity step "
+                f"{(t2 - t1) * 1e3:.1f} ms")
     tree.free()
-    return dict(workload=f"plasticity_{w.n}_uniform_20000um", updates=per,
-                note="per update: refresh + search + commit (connectivity), then record + "
-                     "growth/deletion/retraction (plasticity step), all on the device")
+    tot_s = sum(u["connectivity_ms"] + u["plasticity_ms"] for u in per) / 1e3
+    searches = sum(u["searches"] for u in per)
+    return dict(workload=f"plasticity_{w.n}_uniform_20000um", n_updates=len(per),
+                total_s=tot_s, searches=searches, searches_per_s=searches / tot_s,
+                synapses_formed=sum(u["formed"] for u in per), synapses_at_end=net.m,
+                first_updates=per[:3], last_update=per[-1],
+                note="per update: refresh + search + commit, then record + growth/deletion/"
+                     "retraction (the plasticity step), all on the device; octree built "
+                     "once (positions fixed)")
 
 
 def study_complexity(msp, torch, log2_ns=(12, 14, 16, 18, 20, 22, 23),
@@ -438,7 +446,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large", choices=["large", "clusters", "small"])
     ap.add_argument("--theta", type=float, default=None)
-    ap.add_argument("--cpu-sample", type=int, default=40000)
+    ap.add_argument("--cpu-sample", type=int, default=400000)
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -447,7 +455,7 @@ def main():
                     help="skip the 2^20-neuron, batched, attraction and multi-update measurements")
     ap.add_argument("--study", choices=["complexity"], default=None,
                     help="instead of the benchmark: visits and throughput over n and theta")
-    ap.add_argument("--updates", type=int, default=3,
+    ap.add_argument("--updates", type=int, default=100,
                     help="updates of the multi-update workload measured with the others")
     args = ap.parse_args()
     if args.gpus != 1:
