@@ -96,7 +96,7 @@ def kernel_sources_hash():
     import hashlib
     import re
     h = hashlib.sha256()
-    for f in ("search.hpp", "search_wave.hpp", "common.hpp"):
+    for f in ("search.hpp", "search_wave.hpp", "batch.hpp", "common.hpp"):
         with open(os.path.join(ROOT, "paper_2509_26193_amd", "csrc", f)) as fh:
             src = fh.read()
         src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)

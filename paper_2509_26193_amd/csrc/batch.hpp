@@ -24,6 +24,7 @@ struct SimDesc {
   const int32_t* vs[2];
   const double* pos;
   const int32_t* order;
+  const uint64_t* keys;         // [n] sorted Morton keys (position g: neuron order[g])
   const int32_t* nbeg;
   const int32_t* nend;
   const int32_t* leaf_of;
@@ -229,24 +230,94 @@ __global__ void b_tiles_k(BatchDev B, int32_t* tile_count) {
   *tile_count = t;
 }
 
-__global__ void b_work_k(BatchDev B, int64_t total) {
+// Hilbert index of a cell of the 2^21 grid (J. Skilling, "Programming the Hilbert
+// curve", AIP Conf. Proc. 707, 2004: axes to transposed index, then bit interleave).
+// Only the order it induces matters here: sources consecutive along the curve are
+// close in space, with none of the long jumps the Morton order makes between octants.
+__device__ __forceinline__ uint64_t hilbert3(uint32_t x0, uint32_t x1, uint32_t x2) {
+  uint32_t X[3] = {x0, x1, x2};
+  for (uint32_t Q = 1u << 20; Q > 1; Q >>= 1) {
+    const uint32_t P = Q - 1;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      if (X[i] & Q) {
+        X[0] ^= P;                                  // invert
+      } else {
+        const uint32_t t = (X[0] ^ X[i]) & P;       // exchange
+        X[0] ^= t;
+        X[i] ^= t;
+      }
+    }
+  }
+  X[1] ^= X[0];
+  X[2] ^= X[1];
+  uint32_t t = 0;
+  for (uint32_t Q = 1u << 20; Q > 1; Q >>= 1)
+    if (X[2] & Q) t ^= Q - 1;
+  X[0] ^= t;
+  X[1] ^= t;
+  X[2] ^= t;
+  uint64_t h = 0;
+  for (int b = 20; b >= 0; --b)
+    h = (h << 3) | ((uint64_t)((X[0] >> b) & 1u) << 2) | ((uint64_t)((X[1] >> b) & 1u) << 1) |
+        (uint64_t)((X[2] >> b) & 1u);
+  return h;
+}
+
+// The three 21-bit cell coordinates of a Morton key (digit 4x + 2y + z per level).
+__device__ __forceinline__ void morton_decode(uint64_t k, uint32_t& x, uint32_t& y, uint32_t& z) {
+  x = y = z = 0;
+  for (int b = 20; b >= 0; --b) {
+    const uint32_t d = (uint32_t)(k >> (3 * b)) & 7u;
+    x = (x << 1) | (d >> 2);
+    y = (y << 1) | ((d >> 1) & 1u);
+    z = (z << 1) | (d & 1u);
+  }
+}
+
+__global__ void fill_u64_k(uint64_t* p, int64_t n, uint64_t v) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+
+// Sort keys of the sources: (simulation, type) group in the top `gb` of 48 bits, then
+// the leading 48 - gb bits of the Hilbert index; value = flat Morton position. Sources
+// are packed in Morton order (position p0 + p1); the rest of the array keeps the
+// padding key written before (all 48 bits set), which sorts last.
+__global__ void b_hkeys_k(BatchDev B, int64_t total, int gb, uint64_t* key, int32_t* val) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const int s = find_sim(B.nbase, B.nsims, g);
   if (B.status[s] != 0) return;
+  const SimDesc& d = B.sims[s];
+  const int64_t m = g - B.nbase[s];
+  const int32_t id = d.order[m];
+  if (d.vac_axon[id] <= 0) return;
+  const int t = d.type[id] ? 1 : 0;
+  uint32_t x, y, z;
+  morton_decode(d.keys[m], x, y, z);
+  const int hb = 48 - gb;
+  const uint64_t h = hilbert3(x, y, z) >> (63 - hb);
+  const int64_t idx = (int64_t)B.p0[g] + B.p1[g];
+  key[idx] = ((uint64_t)(2 * s + t) << hb) | h;
+  val[idx] = (int32_t)g;
+}
+
+// Worklist from the sorted sources: the rank within a (simulation, type) group is the
+// sorted position minus the group's start.
+__global__ void b_work_sorted_k(BatchDev B, int64_t total, const int32_t* __restrict__ val) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (int64_t)B.p0[total] + B.p1[total]) return;
+  const int64_t g = val[p];
+  const int s = find_sim(B.nbase, B.nsims, g);
   const int64_t b = B.nbase[s], e = B.nbase[s + 1];
   const SimDesc& d = B.sims[s];
   const int32_t id = d.order[g - b];
-  if (d.vac_axon[id] <= 0) return;
-  const int64_t base = (int64_t)B.tile_base[s] * kWave;
-  int64_t slot;
-  if (d.type[id]) {
-    const int32_t c0 = B.p0[e] - B.p0[b];
-    slot = base + (int64_t)((c0 + kWave - 1) / kWave) * kWave + (B.p1[g] - B.p1[b]);
-  } else {
-    slot = base + (B.p0[g] - B.p0[b]);
-  }
-  B.work[slot] = id;
+  const int32_t c0 = B.p0[e] - B.p0[b];
+  const int64_t start = (int64_t)B.p0[b] + B.p1[b] + (d.type[id] ? c0 : 0);
+  const int64_t base = (int64_t)B.tile_base[s] * kWave +
+                       (d.type[id] ? (int64_t)((c0 + kWave - 1) / kWave) * kWave : 0);
+  B.work[base + (p - start)] = id;
 }
 
 // ---------------------------------------------------------------------------
@@ -257,6 +328,9 @@ struct SearchScratch {
   SweepOut W;
   int32_t* counters;            // [0] tile count, [1..8] die queues
   void* scan_tmp;
+  uint64_t* hkey[2];            // [total_n] sort keys of the Hilbert-ordered worklist
+  int32_t* hval[2];             // [total_n] their flat positions
+  void* hsort;                  // radix sort workspace
 };
 
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -264,7 +338,8 @@ inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 inline int64_t max_tiles_for(int64_t total_n, int nsims) { return total_n / kWave + 2 * nsims + 1; }
 
 struct ScratchSizes {
-  size_t ea, p, tile_base, status, work, Z, v, nck, ckx, ckP, ckme, counters, scan, total;
+  size_t ea, p, tile_base, status, work, Z, v, nck, ckx, ckP, ckme, counters, scan, hkey, hval,
+      hsort, total;
 };
 
 // Checkpoint bytes per slot of a tile: the wave position and, per lane, the running
@@ -289,8 +364,11 @@ inline ScratchSizes scratch_sizes(int64_t total_n, int nsims, int slots) {
   z.ckme = align_up(sizeof(int32_t) * mt * slots * kWave);
   z.counters = align_up(sizeof(int32_t) * (1 + kXcd));
   z.scan = align_up(std::max(scan_tmp_bytes<int64_t>(total_n), scan_tmp_bytes<int32_t>(total_n)));
+  z.hkey = align_up(sizeof(uint64_t) * total_n);
+  z.hval = align_up(sizeof(int32_t) * total_n);
+  z.hsort = align_up(radix_sort_ws_bytes(total_n));
   z.total = z.ea + 2 * z.p + z.tile_base + z.status + z.work + z.Z + 2 * z.v + z.nck + z.ckx +
-            z.ckP + z.ckme + z.counters + z.scan;
+            z.ckP + z.ckme + z.counters + z.scan + 2 * z.hkey + 2 * z.hval + z.hsort;
   return z;
 }
 
@@ -327,6 +405,11 @@ inline SearchScratch carve(void* base, int64_t total_n, int nsims, int slots,
   S.W.queue = S.counters + 1;
   S.W.wave_steps = nullptr;
   S.scan_tmp = take(z.scan);
+  S.hkey[0] = reinterpret_cast<uint64_t*>(take(z.hkey));
+  S.hkey[1] = reinterpret_cast<uint64_t*>(take(z.hkey));
+  S.hval[0] = reinterpret_cast<int32_t*>(take(z.hval));
+  S.hval[1] = reinterpret_cast<int32_t*>(take(z.hval));
+  S.hsort = take(z.hsort);
   return S;
 }
 
@@ -349,7 +432,14 @@ inline hipError_t enqueue_prep(SearchScratch& S, int64_t total_n, hipStream_t s)
                                                    S.scan_tmp);
   if (e != hipSuccess) return e;
   b_tiles_k<<<1, 64, 0, s>>>(B, S.counters);
-  b_work_k<<<g, 256, 0, s>>>(B, total_n);
+  // 64-source tiles in Hilbert order within each (simulation, type) group
+  int gb = 1;
+  while ((1ll << gb) < 2ll * B.nsims) ++gb;
+  fill_u64_k<<<g, 256, 0, s>>>(S.hkey[0], total_n, (1ull << 48) - 1);
+  b_hkeys_k<<<g, 256, 0, s>>>(B, total_n, gb, S.hkey[0], S.hval[0]);
+  e = radix_sort_pairs_ws(S.hkey[0], S.hval[0], S.hkey[1], S.hval[1], total_n, 48, s, S.hsort);
+  if (e != hipSuccess) return e;
+  b_work_sorted_k<<<g, 256, 0, s>>>(B, total_n, S.hval[0]);
   return hipGetLastError();
 }
 

@@ -84,6 +84,7 @@ SimDesc make_desc(const msp_octree_s* t, const uint8_t* neuron_type, const int32
   d.vs[1] = t->vs[1];
   d.pos = t->pos;
   d.order = t->order;
+  d.keys = t->keys;
   d.nbeg = t->nbeg;
   d.nend = t->nend;
   d.leaf_of = t->leaf_of;

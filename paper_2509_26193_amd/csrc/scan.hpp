@@ -201,27 +201,34 @@ __global__ void __launch_bounds__(kSortBlock) rs_scatter_k(const uint64_t* kin, 
   }
 }
 
-// Sort (keys, vals) of length n ascending by key; `bits` = number of key bits to sort.
-// Buffers k0/v0 hold the input and receive the output; k1/v1 are scratch of size n.
-inline hipError_t radix_sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int64_t n,
-                                   int bits, hipStream_t s) {
+// Scratch bytes of radix_sort_pairs_ws for n items: the digit histograms, then the
+// block sums of their scan.
+inline size_t radix_sort_ws_bytes(int64_t n) {
+  const int64_t nb = (n + kSortTile - 1) / kSortTile;
+  const size_t hist = ((sizeof(uint32_t) * 256 * (size_t)(nb > 0 ? nb : 1)) + 255) & ~(size_t)255;
+  return hist + scan_tmp_bytes<uint32_t>(256 * (nb > 0 ? nb : 1));
+}
+
+// Sort (keys, vals) of length n ascending by the low `bits` key bits (a multiple of 8).
+// Buffers k0/v0 hold the input and receive the output; k1/v1 are scratch of size n;
+// `ws` holds radix_sort_ws_bytes(n) bytes. Allocates nothing, so it can be captured.
+inline hipError_t radix_sort_pairs_ws(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1,
+                                      int64_t n, int bits, hipStream_t s, void* ws) {
   if (n <= 1) return hipSuccess;
   const int64_t nb = (n + kSortTile - 1) / kSortTile;
-  Temp hist(s);
-  hipError_t e = hist.alloc(sizeof(uint32_t) * 256 * (size_t)nb);
-  if (e != hipSuccess) return e;
+  uint32_t* hist = static_cast<uint32_t*>(ws);
+  void* scan_ws = static_cast<char*>(ws) + (((sizeof(uint32_t) * 256 * (size_t)nb) + 255) & ~(size_t)255);
   uint64_t* ka = k0;
   int32_t* va = v0;
   uint64_t* kb = k1;
   int32_t* vb = v1;
-  int passes = 0;
-  for (int shift = 0; shift < bits; shift += 8, ++passes) {
-    rs_hist_k<<<(unsigned)nb, kSortBlock, 0, s>>>(ka, n, shift, hist.as<uint32_t>(), (int)nb);
-    e = exclusive_scan<uint32_t, uint32_t, Ident<uint32_t>>(hist.as<uint32_t>(), hist.as<uint32_t>(),
-                                                            256 * nb, Ident<uint32_t>(), false, s);
+  hipError_t e = hipSuccess;
+  for (int shift = 0; shift < bits; shift += 8) {
+    rs_hist_k<<<(unsigned)nb, kSortBlock, 0, s>>>(ka, n, shift, hist, (int)nb);
+    e = exclusive_scan<uint32_t, uint32_t, Ident<uint32_t>>(hist, hist, 256 * nb, Ident<uint32_t>(),
+                                                            false, s, scan_ws);
     if (e != hipSuccess) return e;
-    rs_scatter_k<<<(unsigned)nb, kSortBlock, 0, s>>>(ka, va, kb, vb, n, shift, hist.as<uint32_t>(),
-                                                     (int)nb);
+    rs_scatter_k<<<(unsigned)nb, kSortBlock, 0, s>>>(ka, va, kb, vb, n, shift, hist, (int)nb);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     uint64_t* tk = ka; ka = kb; kb = tk;
@@ -233,6 +240,17 @@ inline hipError_t radix_sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int3
     e = hipMemcpyAsync(v0, va, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s);
   }
   return e;
+}
+
+// Sort (keys, vals) of length n ascending by key; `bits` = number of key bits to sort.
+// Buffers k0/v0 hold the input and receive the output; k1/v1 are scratch of size n.
+inline hipError_t radix_sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int64_t n,
+                                   int bits, hipStream_t s) {
+  if (n <= 1) return hipSuccess;
+  Temp ws(s);
+  hipError_t e = ws.alloc(radix_sort_ws_bytes(n));
+  if (e != hipSuccess) return e;
+  return radix_sort_pairs_ws(k0, v0, k1, v1, n, bits, s, ws.p);
 }
 
 }  // namespace msp
