@@ -51,6 +51,7 @@ struct BatchDev {
   int64_t* ea;                  // [total + 1] flat exclusive scan of vac_axon
   int32_t* p0;                  // [total + 1] flat scan: excitatory sources, Morton order
   int32_t* p1;                  // [total + 1] flat scan: inhibitory sources, Morton order
+  uint8_t* src_type;            // [total] type of the source at flat position g, 2: none
   int32_t* tile_base;           // [nsims + 1]
   int32_t* status;              // [nsims]
   int32_t* work;                // [max_slots] source id per slot, -1 = padding
@@ -203,16 +204,26 @@ __global__ void b_offsets_k(BatchDev B, int64_t total) {
   }
 }
 
-struct FlatSource {             // flat Morton position g is a type-`want` source
-  BatchDev B;
-  uint8_t want;
-  __device__ int32_t operator()(int32_t, int64_t g) const {
-    const int s = find_sim(B.nbase, B.nsims, g);
-    if (B.status[s] != 0) return 0;
+// src_type[g]: the type (0, 1) of the neuron at flat Morton position g if it is a
+// source of a simulation without errors, else 2. One gather per neuron; the scans and
+// the worklist then read it in order.
+__global__ void b_src_type_k(BatchDev B, int64_t total) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int s = find_sim(B.nbase, B.nsims, g);
+  uint8_t st = 2;
+  if (B.status[s] == 0) {
     const SimDesc& d = B.sims[s];
     const int32_t id = d.order[g - B.nbase[s]];
-    return (d.vac_axon[id] > 0 && (d.type[id] ? 1 : 0) == want) ? 1 : 0;
+    if (d.vac_axon[id] > 0) st = d.type[id] ? 1 : 0;
   }
+  B.src_type[g] = st;
+}
+
+struct FlatSource {             // flat Morton position g is a type-`want` source
+  const uint8_t* src_type;
+  uint8_t want;
+  __device__ int32_t operator()(int32_t, int64_t g) const { return src_type[g] == want ? 1 : 0; }
 };
 
 // Tiles per simulation: excitatory sources padded to a multiple of 64, then
@@ -280,23 +291,21 @@ __global__ void fill_u64_k(uint64_t* p, int64_t n, uint64_t v) {
   if (k < n) p[k] = v;
 }
 
-// Sort keys of the sources: (simulation, type) group in the top `gb` of 48 bits, then
-// the leading 48 - gb bits of the Hilbert index; value = flat Morton position. Sources
+// Sort keys of the sources: (simulation, type) group in the top `gb` of `kb` bits, then
+// the leading kb - gb bits of the Hilbert index; value = flat Morton position. Sources
 // are packed in Morton order (position p0 + p1); the rest of the array keeps the
-// padding key written before (all 48 bits set), which sorts last.
-__global__ void b_hkeys_k(BatchDev B, int64_t total, int gb, uint64_t* key, int32_t* val) {
+// padding key written before (all kb bits set), which sorts last.
+__global__ void b_hkeys_k(BatchDev B, int64_t total, int gb, int kb, uint64_t* key,
+                          int32_t* val) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
+  const int t = B.src_type[g];
+  if (t > 1) return;
   const int s = find_sim(B.nbase, B.nsims, g);
-  if (B.status[s] != 0) return;
   const SimDesc& d = B.sims[s];
-  const int64_t m = g - B.nbase[s];
-  const int32_t id = d.order[m];
-  if (d.vac_axon[id] <= 0) return;
-  const int t = d.type[id] ? 1 : 0;
   uint32_t x, y, z;
-  morton_decode(d.keys[m], x, y, z);
-  const int hb = 48 - gb;
+  morton_decode(d.keys[g - B.nbase[s]], x, y, z);
+  const int hb = kb - gb;
   const uint64_t h = hilbert3(x, y, z) >> (63 - hb);
   const int64_t idx = (int64_t)B.p0[g] + B.p1[g];
   key[idx] = ((uint64_t)(2 * s + t) << hb) | h;
@@ -313,10 +322,11 @@ __global__ void b_work_sorted_k(BatchDev B, int64_t total, const int32_t* __rest
   const int64_t b = B.nbase[s], e = B.nbase[s + 1];
   const SimDesc& d = B.sims[s];
   const int32_t id = d.order[g - b];
+  const int t = B.src_type[g];
   const int32_t c0 = B.p0[e] - B.p0[b];
-  const int64_t start = (int64_t)B.p0[b] + B.p1[b] + (d.type[id] ? c0 : 0);
+  const int64_t start = (int64_t)B.p0[b] + B.p1[b] + (t ? c0 : 0);
   const int64_t base = (int64_t)B.tile_base[s] * kWave +
-                       (d.type[id] ? (int64_t)((c0 + kWave - 1) / kWave) * kWave : 0);
+                       (t ? (int64_t)((c0 + kWave - 1) / kWave) * kWave : 0);
   B.work[base + (p - start)] = id;
 }
 
@@ -338,8 +348,8 @@ inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 inline int64_t max_tiles_for(int64_t total_n, int nsims) { return total_n / kWave + 2 * nsims + 1; }
 
 struct ScratchSizes {
-  size_t ea, p, tile_base, status, work, Z, v, nck, ckx, ckP, ckme, counters, scan, hkey, hval,
-      hsort, total;
+  size_t ea, p, tile_base, status, work, Z, v, nck, ckx, ckP, ckme, counters, scan, srct, hkey,
+      hval, hsort, total;
 };
 
 // Checkpoint bytes per slot of a tile: the wave position and, per lane, the running
@@ -364,11 +374,12 @@ inline ScratchSizes scratch_sizes(int64_t total_n, int nsims, int slots) {
   z.ckme = align_up(sizeof(int32_t) * mt * slots * kWave);
   z.counters = align_up(sizeof(int32_t) * (1 + kXcd));
   z.scan = align_up(std::max(scan_tmp_bytes<int64_t>(total_n), scan_tmp_bytes<int32_t>(total_n)));
+  z.srct = align_up(sizeof(uint8_t) * total_n);
   z.hkey = align_up(sizeof(uint64_t) * total_n);
   z.hval = align_up(sizeof(int32_t) * total_n);
   z.hsort = align_up(radix_sort_ws_bytes(total_n));
   z.total = z.ea + 2 * z.p + z.tile_base + z.status + z.work + z.Z + 2 * z.v + z.nck + z.ckx +
-            z.ckP + z.ckme + z.counters + z.scan + 2 * z.hkey + 2 * z.hval + z.hsort;
+            z.ckP + z.ckme + z.counters + z.scan + z.srct + 2 * z.hkey + 2 * z.hval + z.hsort;
   return z;
 }
 
@@ -405,6 +416,7 @@ inline SearchScratch carve(void* base, int64_t total_n, int nsims, int slots,
   S.W.queue = S.counters + 1;
   S.W.wave_steps = nullptr;
   S.scan_tmp = take(z.scan);
+  S.B.src_type = reinterpret_cast<uint8_t*>(take(z.srct));
   S.hkey[0] = reinterpret_cast<uint64_t*>(take(z.hkey));
   S.hkey[1] = reinterpret_cast<uint64_t*>(take(z.hkey));
   S.hval[0] = reinterpret_cast<int32_t*>(take(z.hval));
@@ -425,19 +437,23 @@ inline hipError_t enqueue_prep(SearchScratch& S, int64_t total_n, hipStream_t s)
                                                              true, s, S.scan_tmp);
   if (e != hipSuccess) return e;
   b_offsets_k<<<g, 256, 0, s>>>(B, total_n);
-  e = exclusive_scan<int32_t, int32_t, FlatSource>(nullptr, B.p0, total_n, FlatSource{B, 0}, true, s,
-                                                   S.scan_tmp);
+  b_src_type_k<<<g, 256, 0, s>>>(B, total_n);
+  e = exclusive_scan<int32_t, int32_t, FlatSource>(nullptr, B.p0, total_n,
+                                                   FlatSource{B.src_type, 0}, true, s, S.scan_tmp);
   if (e != hipSuccess) return e;
-  e = exclusive_scan<int32_t, int32_t, FlatSource>(nullptr, B.p1, total_n, FlatSource{B, 1}, true, s,
-                                                   S.scan_tmp);
+  e = exclusive_scan<int32_t, int32_t, FlatSource>(nullptr, B.p1, total_n,
+                                                   FlatSource{B.src_type, 1}, true, s, S.scan_tmp);
   if (e != hipSuccess) return e;
   b_tiles_k<<<1, 64, 0, s>>>(B, S.counters);
   // 64-source tiles in Hilbert order within each (simulation, type) group
+  // (32-bit keys keep 20 or more Hilbert bits, cells of about a hundredth of the box
+  // edge or finer, for up to 2048 simulations)
   int gb = 1;
   while ((1ll << gb) < 2ll * B.nsims) ++gb;
-  fill_u64_k<<<g, 256, 0, s>>>(S.hkey[0], total_n, (1ull << 48) - 1);
-  b_hkeys_k<<<g, 256, 0, s>>>(B, total_n, gb, S.hkey[0], S.hval[0]);
-  e = radix_sort_pairs_ws(S.hkey[0], S.hval[0], S.hkey[1], S.hval[1], total_n, 48, s, S.hsort);
+  const int kb = gb <= 12 ? 32 : 48;
+  fill_u64_k<<<g, 256, 0, s>>>(S.hkey[0], total_n, (1ull << kb) - 1);
+  b_hkeys_k<<<g, 256, 0, s>>>(B, total_n, gb, kb, S.hkey[0], S.hval[0]);
+  e = radix_sort_pairs_ws(S.hkey[0], S.hval[0], S.hkey[1], S.hval[1], total_n, kb, s, S.hsort);
   if (e != hipSuccess) return e;
   b_work_sorted_k<<<g, 256, 0, s>>>(B, total_n, S.hval[0]);
   return hipGetLastError();
