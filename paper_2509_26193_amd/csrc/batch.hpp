@@ -98,7 +98,7 @@ __device__ __forceinline__ SearchArgs args_of(const SimDesc* sims, int s, const 
 // Persistent waves pull 64-source tiles: first from the Morton range of their own
 // die (neighbouring sources share upper-tree nodes in that die's L2), then from the
 // other dies' ranges. A tile's simulation is found from the tile bases.
-template <bool DIAG, int SLOTS>
+template <bool DIAG, int SLOTS, bool OWN>
 __global__ void __launch_bounds__(kWaveBlock) search_sweep_k(BatchDev B, SweepOut W) {
   const int lane = threadIdx.x & (kWave - 1);
   const int home = blockIdx.x % kXcd;
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(kWaveBlock) search_sweep_k(BatchDev B, SweepOu
     const int sim = __builtin_amdgcn_readfirstlane(
         find_sim(as_const(B.tile_base), B.nsims, (int64_t)tile));
     const SearchArgs A = args_of(B.sims, sim, B.work);
-    const int steps = sweep_tile<DIAG, SLOTS>(A, W, tile, lane, step0);
+    const int steps = sweep_tile<DIAG, SLOTS, OWN>(A, W, tile, lane, step0);
     if constexpr (SLOTS > 0) {
       // next interval: about SLOTS checkpoints over a sweep as long as this one
       step0 = kCkptStepMin;
@@ -341,6 +341,7 @@ struct SearchScratch {
   uint64_t* hkey[2];            // [total_n] sort keys of the Hilbert-ordered worklist
   int32_t* hval[2];             // [total_n] their flat positions
   void* hsort;                  // radix sort workspace
+  bool own_cell;                // the sweep tests for the source's own cell (see sweep_tile)
 };
 
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -415,6 +416,7 @@ inline SearchScratch carve(void* base, int64_t total_n, int nsims, int slots,
   S.W.tile_count = S.counters;
   S.W.queue = S.counters + 1;
   S.W.wave_steps = nullptr;
+  S.own_cell = true;
   S.scan_tmp = take(z.scan);
   S.B.src_type = reinterpret_cast<uint8_t*>(take(z.srct));
   S.hkey[0] = reinterpret_cast<uint64_t*>(take(z.hkey));
@@ -461,18 +463,26 @@ inline hipError_t enqueue_prep(SearchScratch& S, int64_t total_n, hipStream_t s)
 
 // The sweep and draw launches. `sweep_blocks` persistent blocks; the draw covers
 // every possible slot (threads past the tile count return at once).
+template <bool DIAG, int SLOTS>
+inline void launch_sweep(const SearchScratch& S, unsigned blocks, hipStream_t s) {
+  if (S.own_cell)
+    search_sweep_k<DIAG, SLOTS, true><<<blocks, kWaveBlock, 0, s>>>(S.B, S.W);
+  else
+    search_sweep_k<DIAG, SLOTS, false><<<blocks, kWaveBlock, 0, s>>>(S.B, S.W);
+}
+
 inline hipError_t enqueue_search(SearchScratch& S, bool diag, unsigned sweep_blocks,
                                  int draw_block, hipStream_t s, hipEvent_t mid = nullptr) {
   const unsigned draw_grid = grid_for(S.B.max_slots, draw_block);
   const bool big = S.W.ck_slots == kCkptMax;
   if (diag && big)
-    search_sweep_k<true, kCkptMax><<<sweep_blocks, kWaveBlock, 0, s>>>(S.B, S.W);
+    launch_sweep<true, kCkptMax>(S, sweep_blocks, s);
   else if (diag)
-    search_sweep_k<true, kCkptMin><<<sweep_blocks, kWaveBlock, 0, s>>>(S.B, S.W);
+    launch_sweep<true, kCkptMin>(S, sweep_blocks, s);
   else if (big)
-    search_sweep_k<false, kCkptMax><<<sweep_blocks, kWaveBlock, 0, s>>>(S.B, S.W);
+    launch_sweep<false, kCkptMax>(S, sweep_blocks, s);
   else
-    search_sweep_k<false, kCkptMin><<<sweep_blocks, kWaveBlock, 0, s>>>(S.B, S.W);
+    launch_sweep<false, kCkptMin>(S, sweep_blocks, s);
   if (mid) {
     hipError_t e = hipEventRecord(mid, s);
     if (e != hipSuccess) return e;

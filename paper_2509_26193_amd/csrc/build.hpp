@@ -31,11 +31,19 @@ __device__ __forceinline__ uint64_t quantise(double x, double lo, double edge) {
 __global__ void __launch_bounds__(kBuildBlock) keys_k(const double* __restrict__ pos_in, int64_t n,
                                                      double x0, double y0, double z0, double edge,
                                                      double* __restrict__ pos, uint64_t* keys,
-                                                     int32_t* ids, int32_t* err) {
+                                                     int32_t* ids, int32_t* err,
+                                                     int32_t* outside) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double x = pos_in[3 * i + 0], y = pos_in[3 * i + 1], z = pos_in[3 * i + 2];
   if (!isfinite(x) || !isfinite(y) || !isfinite(z)) atomicOr(err, kErrNonFinite);
+  // a position outside the closed cube (it is clamped into an edge cell); one atomic
+  // per wave at most
+  const bool out = !(x >= x0 && x <= x0 + edge && y >= y0 && y <= y0 + edge && z >= z0 &&
+                     z <= z0 + edge);
+  const uint64_t outs = __ballot(out);
+  if (outs && (threadIdx.x & 63) == (unsigned)(__ffsll((unsigned long long)outs) - 1))
+    atomicOr(outside, 1);
   pos[3 * i + 0] = x;
   pos[3 * i + 1] = y;
   pos[3 * i + 2] = z;

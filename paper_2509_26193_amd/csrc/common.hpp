@@ -70,6 +70,8 @@ struct msp_octree_s {
   int32_t* vs[2];        // [n] per type: counts in sorted order (bucket members)
   int32_t* err;          // [1] sticky device error flags
   bool refreshed;
+  bool inside;           // every position lies in the closed cube, and the cube lies
+                         // within 2^18 edges of the origin
   void* slab_n;          // one allocation holding the neuron arrays ...
   void* slab_N;          // ... and one holding the node arrays
 };

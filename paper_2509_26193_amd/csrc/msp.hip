@@ -1,4 +1,5 @@
 // libmsp: C ABI entry points (declared in include/msp.h). One translation unit.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <cstdlib>
@@ -103,6 +104,12 @@ SimDesc make_desc(const msp_octree_s* t, const uint8_t* neuron_type, const int32
   return d;
 }
 
+// Whether the sweep must test for the source's own cell: always, unless theta <= 1/2
+// and every position of the tree lies inside its cube (then that test never fires).
+bool own_cell_needed(const msp_octree_s* t, double theta) {
+  return !(t->inside && theta * theta <= 0.25);
+}
+
 // Persistent sweep blocks: occupancy x CUs (times `frac` in [0, 1]), at most one
 // wave per tile.
 hipError_t sweep_blocks_for(int device, bool diag, int64_t max_tiles, double frac,
@@ -112,7 +119,8 @@ hipError_t sweep_blocks_for(int device, bool diag, int64_t max_tiles, double fra
   if (e != hipSuccess) return e;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
       &per_cu,
-      diag ? (const void*)search_sweep_k<true, kCkptMax> : (const void*)search_sweep_k<false, kCkptMax>,
+      diag ? (const void*)search_sweep_k<true, kCkptMax, true>
+           : (const void*)search_sweep_k<false, kCkptMax, true>,
       kWaveBlock, 0);
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
@@ -259,12 +267,15 @@ msp_status msp_build_octree(const double* pos, int64_t n, const double box_min[3
   carve_neurons(t, static_cast<char*>(t->slab_n), &bytes);
   TRY(hipMemsetAsync(t->err, 0, sizeof(int32_t), s));
   {
-    Temp k1(s), v1(s), cnt(s), base(s), lvl(s);
+    Temp k1(s), v1(s), cnt(s), base(s), lvl(s), outside(s);
     TRY(k1.alloc(sizeof(uint64_t) * n));
     TRY(v1.alloc(sizeof(int32_t) * n));
+    TRY(outside.alloc(sizeof(int32_t)));
+    TRY(hipMemsetAsync(outside.p, 0, sizeof(int32_t), s));
     keys_k<<<grid_for(n, kBuildBlock), kBuildBlock, 0, s>>>(pos, n, box_min[0], box_min[1],
                                                             box_min[2], box_edge, t->pos, t->keys,
-                                                            t->order, t->err);
+                                                            t->order, t->err,
+                                                            outside.as<int32_t>());
     TRY(hipGetLastError());
     TRY(radix_sort_pairs(t->keys, t->order, k1.as<uint64_t>(), v1.as<int32_t>(), n, 63, s));
     TRY(cnt.alloc(sizeof(int32_t) * n));
@@ -273,9 +284,14 @@ msp_status msp_build_octree(const double* pos, int64_t n, const double box_min[3
     TRY(hipGetLastError());
     TRY((exclusive_scan<int32_t, int32_t, Ident<int32_t>>(cnt.as<int32_t>(), base.as<int32_t>(), n,
                                                           Ident<int32_t>(), true, s)));
-    int32_t N32 = 0;
+    int32_t N32 = 0, h_outside = 1;
     TRY(hipMemcpyAsync(&N32, base.as<int32_t>() + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    TRY(hipMemcpyAsync(&h_outside, outside.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     TRY(hipStreamSynchronize(s));
+    double far = 0.0;
+    for (int a = 0; a < 3; ++a)
+      far = std::max(far, std::max(std::fabs(box_min[a]), std::fabs(box_min[a] + box_edge)));
+    t->inside = h_outside == 0 && far <= std::ldexp(box_edge, 18);
     if (N32 < 1 || N32 >= kMaxNodes) {
       release(t);
       return MSP_ERR_INVALID;
@@ -399,6 +415,7 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
   MSP_HIP_TRY(hipMemcpyAsync(dsim.p, &h, sizeof(SimDesc), hipMemcpyHostToDevice, s));
   MSP_HIP_TRY(hipMemcpyAsync(dbase.p, hbase, sizeof(hbase), hipMemcpyHostToDevice, s));
   SearchScratch S = carve(scratch, n, 1, slots, dsim.as<SimDesc>(), dbase.as<int64_t>());
+  S.own_cell = own_cell_needed(t, theta);
   if (any) S.W.wave_steps = reinterpret_cast<unsigned long long*>(diag->wave_steps);
   MSP_HIP_TRY(enqueue_prep(S, n, s));
   int32_t status = 0, ntiles = 0;
@@ -592,6 +609,7 @@ struct msp_batch_s {
   int draw_block;
   int ck_slots;             // checkpoint slots per tile
   bool tuned;
+  bool captured_own;        // own-cell test of the captured sweep
   hipGraphExec_t exec;
   bool captured;
   hipStream_t cap_stream;   // private stream for graph capture (the caller's may be the
@@ -699,6 +717,7 @@ msp_status msp_batch_create(const msp_sim* sims, int32_t n_sims, int32_t flags, 
   b->staged_pending = false;
   b->tuned = false;
   b->captured = false;
+  b->captured_own = true;
   b->cap_stream = nullptr;
   b->draw_block = 256;
   b->ck_slots = kCkptMin;
@@ -736,10 +755,18 @@ msp_status msp_find_targets_batched(msp_batch b, const msp_sim* sims, double the
   }
   // the staging buffer is reused: wait until the previous upload has been read
   if (b->staged_pending) MSP_HIP_TRY(hipEventSynchronize(b->staged));
+  bool own = false;
   for (int k = 0; k < b->nsims; ++k) {
     const msp_sim& m = b->sims[k];
     b->h_sims[k] = make_desc(m.tree, m.neuron_type, m.vac_axon, m.sigma_um, theta, m.seed, step,
                              m.target_out, m.elem_offset_out, m.capacity_S);
+    own = own || own_cell_needed(m.tree, theta);
+  }
+  b->S.own_cell = own;
+  if (b->captured && b->captured_own != own) {     // the captured sweep is the other variant
+    MSP_HIP_TRY(hipStreamSynchronize(s));
+    (void)hipGraphExecDestroy(b->exec);
+    b->captured = false;
   }
   MSP_HIP_TRY(hipMemcpyAsync(b->d_sims, b->h_sims, sizeof(SimDesc) * b->nsims,
                              hipMemcpyHostToDevice, s));
@@ -763,6 +790,7 @@ msp_status msp_find_targets_batched(msp_batch b, const msp_sim* sims, double the
       (void)hipGraphDestroy(g);
       if (e != hipSuccess) return MSP_ERR_HIP;
       b->captured = true;
+      b->captured_own = own;
     }
     MSP_HIP_TRY(hipGraphLaunch(b->exec, s));
     return MSP_OK;
@@ -831,7 +859,8 @@ msp_status attraction(msp_octree t, const uint8_t* neuron_type, const int32_t* v
     unsigned blocks = 0;
     MSP_HIP_TRY(sweep_blocks_for(t->device, false, max_tiles_for(n, 1), 1.0, &blocks));
     fill_i32_k<<<grid_for(n, 256), 256, 0, s>>>(reinterpret_cast<int32_t*>(Z_out), n, 0);
-    search_sweep_k<false, 0><<<blocks, kWaveBlock, 0, s>>>(S.B, S.W);
+    S.own_cell = own_cell_needed(t, theta);
+    launch_sweep<false, 0>(S, blocks, s);
     z_scatter_k<<<grid_for(S.B.max_slots, 256), 256, 0, s>>>(S.B.work, S.W.Z, S.counters, Z_out);
     MSP_HIP_TRY(hipGetLastError());
     return MSP_OK;

@@ -60,14 +60,21 @@ __device__ __forceinline__ bool bh_accept(double L2, double theta2, double d2, u
   return L2 < ldexp(theta2 * d2, (int)(meta_hi & 62u));
 }
 
-// Branch-free (the walks evaluate it for every lane and mask the result).
-__device__ __forceinline__ double kernel_weight(int32_t v, double d2, double k2) {
+// v * 2^-y with y = d2 * k2 (= v exp(-d2 / sigma^2)), or exactly 0 where `keep` is
+// false or exp(-d2 / sigma^2) underflows in float64. Branch-free: the walks evaluate
+// it on every lane. A dropped entry gets the exponent -2048, which takes any
+// v * mant < 2^31 to 0, so the mask costs one 32-bit select instead of a 64-bit one.
+__device__ __forceinline__ double kernel_weight_if(bool keep, int32_t v, double d2, double k2) {
   const double y = fmin(d2 * k2, 2048.0);         // keeps the integer part in range
   const double fr = __builtin_amdgcn_fract(y);
-  const int fl = (int)y;                          // truncation = floor for y >= 0
+  const int nfl = (int)(-y);                      // -floor(y): truncation, as y >= 0
+  const int e = (keep && y <= kMaxY) ? nfl : -2048;
   const double mant = (double)__builtin_amdgcn_exp2f(-(float)fr);
-  const double w = ldexp((double)v * mant, -fl);
-  return y <= kMaxY ? w : 0.0;
+  return ldexp((double)v * mant, e);
+}
+
+__device__ __forceinline__ double kernel_weight(int32_t v, double d2, double k2) {
+  return kernel_weight_if(true, v, d2, k2);
 }
 
 struct SumPass {

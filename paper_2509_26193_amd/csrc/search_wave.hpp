@@ -83,7 +83,12 @@ __device__ __forceinline__ NodeRec load_rec(cptr<NodeRec> R, int64_t x) {
 // `step0`: initial checkpoint interval (a power of two), chosen from the length of
 // the wave's previous sweep so that the buffer rarely has to be thinned out.
 // Returns the number of wave steps of this tile.
-template <bool DIAG, int SLOTS>
+// OWN: test whether an inner node holds the source's own leaf (such a node is always
+// opened). Launches drop the test only where it can never fire: with theta <= 1/2 and
+// every position inside the cube, the source and the node's centroid lie in (or,
+// through rounding, within a tiny fraction of an edge of) the node's cell of edge l,
+// so d^2 <= 3 l^2 (1 + 2^-4) and theta^2 d^2 < l^2: the acceptance test fails anyway.
+template <bool DIAG, int SLOTS, bool OWN>
 __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W, int tile,
                                           int lane, int step0) {
   const int64_t slot = (int64_t)tile * kWave + lane;
@@ -160,8 +165,8 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
           if (cur.v != 0) {
             if (!(meta & kBucketBit)) {
               const int32_t id = (int32_t)(meta & kIdMask);
-              const double w = kernel_weight(cur.v, dist2(xi, yi, zi, cur.x, cur.y, cur.z), A.k2);
-              sum.Z = sum.Z + ((active && id != i) ? w : 0.0);
+              sum.Z = sum.Z + kernel_weight_if(active && id != i, cur.v,
+                                               dist2(xi, yi, zi, cur.x, cur.y, cur.z), A.k2);
             } else {                            // several neurons at one finest cell
               const cptr<int32_t> vs = as_const(A.vs[t]);
               const cptr<int32_t> order = as_const(A.order);
@@ -171,11 +176,11 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
                 const int32_t id = order[p];
                 const int32_t v = vs[p];
                 if (v == 0) continue;
-                const double w = kernel_weight(
-                    v, dist2(xi, yi, zi, pos[3 * (int64_t)id], pos[3 * (int64_t)id + 1],
-                             pos[3 * (int64_t)id + 2]),
+                sum.Z = sum.Z + kernel_weight_if(
+                    active && id != i, v,
+                    dist2(xi, yi, zi, pos[3 * (int64_t)id], pos[3 * (int64_t)id + 1],
+                          pos[3 * (int64_t)id + 2]),
                     A.k2);
-                sum.Z = sum.Z + ((active && id != i) ? w : 0.0);
               }
             }
           }
@@ -186,15 +191,16 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
           if (cur.v != 0) {
             const double d2 = dist2(xi, yi, zi, cur.x, cur.y, cur.z);
             // li in [x, sk) (padding lanes have li = -1, far above sk - x unsigned)
-            const bool contains = (uint32_t)(li - x) < (uint32_t)(sk - x);
+            const bool contains = OWN && (uint32_t)(li - x) < (uint32_t)(sk - x);
             const bool far = !contains && bh_accept(A.L2, A.theta2, d2, meta >> (kSkipBits - 1));
             const bool take = active && far;
             const bool open = active && !far;
-            const double w = kernel_weight(cur.v, d2, A.k2);
-            sum.Z = sum.Z + (take ? w : 0.0);
+            sum.Z = sum.Z + kernel_weight_if(take, cur.v, d2, A.k2);
             me = take ? sk : me;
             if (DIAG && open) c0.opens += 1;
-            if (__any(open)) next = x + 1;
+            // a lane opened x iff it is still active at x (taking moves me past x;
+            // inactive and padding lanes have me > x): one compare feeds the ballot
+            if (__builtin_amdgcn_ballot_w64(me <= x)) next = x + 1;
           }
         }
         x = next < end ? next : end;
