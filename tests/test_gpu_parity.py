@@ -29,6 +29,9 @@ def _degenerate_positions():
     cases["all_coincident"] = np.full((12, 3), 500.0)
     c = rng.uniform(0, 1000, size=(3, 3))
     cases["chains"] = np.repeat(c, 40, axis=0) + rng.normal(0, 0.01, size=(120, 3))
+    # positions outside the cube fall in its edge cells, far from their cell: the
+    # search must keep testing for the source's own cell
+    cases["outside_cube"] = rng.uniform(-400, 1400, size=(300, 3))
     return cases
 
 
