@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
 EXP2_PEAK = 256 * 64 * 2.4e9 / 4   # float32 exp2 per second, quarter-rate transcendental
+FP64_VECTOR_PEAK = 78.6e12  # MI355X fp64 vector FLOP/s (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
 REC_BYTES = 16             # one per-type node record {x, y, z, count} at 4 bytes each
 OPEN_BYTES = 8             # child link + mask + depth of an opened node
 SRC_BYTES = 16             # source record
@@ -546,6 +547,7 @@ def main():
     union_eff = lane_steps / max(1, 64 * wave_steps)
     evals = int((cnt_h["visits0"][first].astype(np.int64)
                  - cnt_h["opens0"][first].astype(np.int64)).sum())
+    alu_flops = 12 * lane_steps + int(cnt_h["opens0"][first].astype(np.int64).sum())
     Bs = sweep_bytes(cnt_h, off_h)
     sweep_s = float(np.mean(times["sweep"])) / 1e3
     draw_s = float(np.mean(times["draw"])) / 1e3
@@ -566,7 +568,16 @@ def main():
                 # that are not opened), per second of the sweep, against the float32 exp2
                 # rate (quarter rate: 256 CU x 64 lanes x 2.4 GHz / 4)
                 kernel_evals_per_s=evals / sweep_s, exp2_peak_per_s=EXP2_PEAK,
-                exp2_frac=evals / sweep_s / EXP2_PEAK)
+                exp2_frac=evals / sweep_s / EXP2_PEAK,
+                # the vector-ALU view of the same launch: fp64 operations the method needs
+                # per source and visited record (squared distance 8; weight 4: d2 k2, the
+                # exponential, times v, the running sum) plus the acceptance product of
+                # every opened node, against the fp64 vector peak
+                alu=dict(bound="alu", achieved=alu_flops / sweep_s / 1e12,
+                         peak=FP64_VECTOR_PEAK / 1e12, unit="TFLOP/s",
+                         frac=alu_flops / sweep_s / FP64_VECTOR_PEAK, flops_per_launch=alu_flops,
+                         basis="12 fp64 operations per source and visited record + 1 per "
+                               "opened node; level-0 counts of the launch"))
     log(f"step {sec * 1e3:.1f} ms; sweep {sweep_s * 1e3:.2f} ms ({achieved / 1e9:.0f} GB/s "
         f"algorithmic, {roof['frac']:.3f} of HBM peak); draw {draw_s * 1e3:.2f} ms; "
         f"{wave_steps} wave steps, lane utilisation {union_eff:.3f}")
