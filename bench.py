@@ -217,6 +217,46 @@ def bench_plain_update(msp, torch, w, steps, warmup):
                             "update, tree build and refresh not included"))
 
 
+def bench_two_phase(msp, torch, w, alg_bytes, branch_level=6, reps=4):
+    """The two-phase (location-aware) search of Sec. IV-A on the headline workload:
+    restarts from cells at depth >= branch_level run as a second pass in cell order.
+    Times both forms on the same refreshed tree and checks that the targets agree."""
+    dev = torch.device("cuda:0")
+    T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    tree = msp.build_octree(T(w.pos, torch.float64), w.box_min, w.box_edge)
+    msp.update_vacant_counts(tree, T(w.vac_exc, torch.int32), T(w.vac_inh, torch.int32))
+    ty, va = T(w.neuron_type, torch.uint8), T(w.vac_axon, torch.int32)
+    res = {}
+    for b in (-1, branch_level):
+        ms, info = [], {}
+        for k in range(reps):
+            tm = {}
+            tgt, _ = msp.find_targets(tree, ty, va, w.sigma, w.theta, w.seed, w.step, timing=tm,
+                                      branch_level=b, phase2=info)
+            if k > 0:
+                ms.append((tm["sweep_ms"], tm["draw_ms"] - tm["phase2_ms"], tm["phase2_ms"]))
+        m = np.mean(np.array(ms), axis=0)
+        res[b] = dict(sweep_ms=float(m[0]), draw_ms=float(m[1]), phase2_ms=float(m[2]),
+                      requests=info["requests"], target=tgt.cpu().numpy())
+    tree.free()
+    one, two = res[-1], res[branch_level]
+    kern_s = (two["sweep_ms"] + two["draw_ms"] + two["phase2_ms"]) / 1e3
+    return dict(workload=w.name, searches=w.searches, branch_level=branch_level,
+                second_phase_requests=two["requests"],
+                request_bytes_paper_format=42 * two["requests"],
+                one_phase_ms=dict(sweep=one["sweep_ms"], draw=one["draw_ms"]),
+                two_phase_ms=dict(sweep=two["sweep_ms"], draw=two["draw_ms"],
+                                  phase2=two["phase2_ms"]),
+                identical_targets=bool(np.array_equal(one["target"], two["target"])),
+                searches_per_s=w.searches / kern_s,
+                roofline=hbm_roofline(alg_bytes, kern_s, "algorithmic bytes of the one-phase "
+                                      "search (the same lists are read) / the two-phase "
+                                      "kernels' HIP-event time"),
+                oracle="as cpu_baseline: the two-phase targets equal the one-phase ones",
+                note="on one GPU the second phase only regroups work; the paper's gain is the "
+                     "communication it removes between processes")
+
+
 def bench_batched(msp, torch, reps=5):
     """64 simulations of 2^12..2^18 neurons: one batched launch (HIP graph) against 64
     per-simulation find_targets calls, same stream, same results (checked)."""
@@ -610,6 +650,8 @@ def main():
         log(f"also: {wc.name}")
         also["plain_1M_clusters"] = bench_plain_update(msp, torch, wc, steps=5, warmup=1)
         del wc
+        log("also: two-phase search")
+        also["two_phase_8M"] = bench_two_phase(msp, torch, w, B)
         log("also: batched")
         also["batched"] = bench_batched(msp, torch)
         log("also: attraction")

@@ -124,13 +124,23 @@ msp_status msp_find_targets(msp_octree t, const uint8_t* neuron_type, const int3
  *           children over all levels (the start node included);
  *   visits0, opens0 [S] int32: the level-0 part of visits / opens (the level-0 list
  *           of a source is shared by all of its elements);
- *   kernel_ms (host) [2]: durations in ms, from HIP events recorded on `s` around each
- *           kernel: [0] the level-0 sweep, [1] the draws and restarts; when set, the
- *           call waits for the kernels to finish.
+ *   kernel_ms (host) [3]: durations in ms, from HIP events recorded on `s` around each
+ *           kernel: [0] the level-0 sweep, [1] the draws and restarts of the first
+ *           phase, [2] the second phase (0 with one phase); when set, the call waits
+ *           for the kernels to finish.
  *   wave_steps (device int64 scalar): incremented by the number of node steps of the
  *           shared level-0 walks (one per 64-source wavefront tile); with visits0 it
  *           gives the fraction of lanes doing useful work. Counted only when one of
  *           the per-search arrays above is also requested.
+ *   branch_level: the two-phase (location-aware) form of the search (Sec. IV-A).
+ *           Restarts from a drawn cell at depth >= branch_level (1..21) are not run
+ *           where they are drawn: they become requests (source, element, cell, level)
+ *           that a second pass runs in cell order, which groups them by branch cell
+ *           (depth-b subtree) as the paper groups them by owning process. Targets,
+ *           levels, visits and opens are bitwise those of the one-phase search.
+ *           0: the library's default (one phase); above 21 or negative: one phase.
+ *           The second phase needs about 40 B per search of working memory.
+ *   phase2_requests (device int64 scalar): set to the number of second-phase requests.
  */
 typedef struct msp_search_diag {
   double* z0;
@@ -141,6 +151,8 @@ typedef struct msp_search_diag {
   int32_t* opens0;
   float* kernel_ms;
   int64_t* wave_steps;
+  int32_t branch_level;
+  int64_t* phase2_requests;
 } msp_search_diag;
 
 /* msp_find_targets with diagnostics (diag may be null). */

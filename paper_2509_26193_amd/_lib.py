@@ -40,7 +40,8 @@ _dbl = ctypes.c_double
 class SearchDiag(ctypes.Structure):
     _fields_ = [("z0", _vp), ("levels", _vp), ("visits", _vp), ("opens", _vp),
                 ("visits0", _vp), ("opens0", _vp), ("kernel_ms", ctypes.POINTER(ctypes.c_float)),
-                ("wave_steps", _vp)]
+                ("wave_steps", _vp), ("branch_level", ctypes.c_int32),
+                ("phase2_requests", _vp)]
 
 
 class SimSpec(ctypes.Structure):
@@ -224,12 +225,17 @@ def update_vacant_counts(tree: Octree, vac_exc: torch.Tensor, vac_inh: torch.Ten
 def find_targets(tree: Octree, neuron_type: torch.Tensor, vac_axon: torch.Tensor, sigma: float,
                  theta: float, seed: int, step: int, target_out: torch.Tensor | None = None,
                  elem_offset_out: torch.Tensor | None = None, diag: bool = False,
-                 counters: bool = False, timing: dict | None = None, stream=None):
+                 counters: bool = False, timing: dict | None = None, stream=None,
+                 branch_level: int = 0, phase2: dict | None = None):
     """Returns (target[S], elem_offset[n+1]); with diag also (z0[S], levels[S]); with
     counters also a dict of visits/opens/visits0/opens0 [S]. target_out may be a
     preallocated int32 buffer of any capacity >= S. If `timing` is a dict, the kernel
     durations (HIP events on the launch stream) are stored under "sweep_ms" (level-0
-    sweep), "draw_ms" (draws and restarts) and "kernel_ms" (both)."""
+    sweep), "draw_ms" (draws and restarts, both phases), "phase2_ms" (the second phase)
+    and "kernel_ms" (all). branch_level selects the two-phase search (restarts from
+    cells at that depth or deeper run in a second pass, in cell order; 0: the library's
+    default); if `phase2` is a dict, phase2["requests"] is set to the number of
+    second-phase requests."""
     n = tree.n
     dev = tree.device
     ty = _dev(neuron_type, torch.uint8, "neuron_type", n)
@@ -238,7 +244,7 @@ def find_targets(tree: Octree, neuron_type: torch.Tensor, vac_axon: torch.Tensor
         elem_offset_out = torch.empty(n + 1, dtype=torch.int64, device=dev)
     off = _dev(elem_offset_out, torch.int64, "elem_offset_out", n + 1)
     st = _stream(stream)
-    ms = (ctypes.c_float * 2)(0.0, 0.0)
+    ms = (ctypes.c_float * 3)(0.0, 0.0, 0.0)
     extra = {}
     for attempt in range(2):
         cap = 0 if target_out is None else target_out.numel()
@@ -252,6 +258,10 @@ def find_targets(tree: Octree, neuron_type: torch.Tensor, vac_axon: torch.Tensor
             extra["wave_steps"] = torch.zeros(1, dtype=torch.int64, device=dev)
         for k, v in extra.items():
             setattr(d, k, v.data_ptr())
+        d.branch_level = int(branch_level)
+        if phase2 is not None:
+            nreq = torch.zeros(1, dtype=torch.int64, device=dev)
+            d.phase2_requests = nreq.data_ptr()
         if timing is not None:
             d.kernel_ms = ctypes.cast(ms, ctypes.POINTER(ctypes.c_float))
         tp = None if target_out is None else _dev(target_out, torch.int32, "target_out")
@@ -268,8 +278,11 @@ def find_targets(tree: Octree, neuron_type: torch.Tensor, vac_axon: torch.Tensor
         target_out = torch.empty(0, dtype=torch.int32, device=dev)
     if timing is not None:
         timing["sweep_ms"] = float(ms[0])
-        timing["draw_ms"] = float(ms[1])
-        timing["kernel_ms"] = float(ms[0]) + float(ms[1])
+        timing["draw_ms"] = float(ms[1]) + float(ms[2])
+        timing["phase2_ms"] = float(ms[2])
+        timing["kernel_ms"] = float(ms[0]) + float(ms[1]) + float(ms[2])
+    if phase2 is not None:
+        phase2["requests"] = int(nreq.item())
     out = [target_out[:S], elem_offset_out]
     if diag:
         out += [extra["z0"][:S], extra["levels"][:S]]

@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(kWaveBlock) search_sweep_k(BatchDev B, SweepOu
 
 // One thread per worklist slot (source): its elements' draws and restarts. The 64
 // slots of a wavefront form one tile, so the simulation is uniform across the wave.
-template <bool DIAG, int SLOTS>
+template <bool DIAG, int SLOTS, bool DEFER>
 __global__ void __launch_bounds__(256) search_draw_k(BatchDev B, SweepOut W) {
   const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t tile = slot / kWave;
@@ -148,7 +148,57 @@ __global__ void __launch_bounds__(256) search_draw_k(BatchDev B, SweepOut W) {
     D.visits0 = d->diag.visits0;
     D.opens0 = d->diag.opens0;
   }
-  draw_slot<DIAG, SLOTS>(A, D, W, slot);
+  draw_slot<DIAG, SLOTS, DEFER>(A, D, W, slot);
+}
+
+// Second phase of a two-phase search (one simulation): one thread per request in
+// cell order (keys sorted); each continues its search from the deferred cell with the
+// same draws as the one-phase search, so the target is the same.
+template <bool DIAG>
+__global__ void __launch_bounds__(256) search_phase2_k(BatchDev B, SweepOut W, int64_t nreq) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nreq) return;
+  const uint64_t key = W.defer.key[q];
+  if (key == W.defer.none) return;              // sorted last: no request from here on
+  const int64_t e = W.defer.val[q];
+  const SearchArgs A = args_of(B.sims, 0, B.work);
+  const int32_t i = W.defer.src[e];
+  const int32_t j = W.defer.elem[e];
+  const int t = A.type[i] ? 1 : 0;
+  const NodeRec* __restrict__ R = A.rec[t];
+  const int32_t li = A.leaf_of[i];
+  const double xi = A.pos[3 * (int64_t)i], yi = A.pos[3 * (int64_t)i + 1],
+               zi = A.pos[3 * (int64_t)i + 2];
+  int lev = W.defer.level[e];
+  Count c;
+  DiagOut D{};
+  if (DIAG) {
+    const cptr<SimDesc> d = as_const(B.sims);
+    D.levels = d->diag.levels;
+    D.visits = d->diag.visits;
+    D.opens = d->diag.opens;
+    if (D.visits) c.visits = D.visits[e];
+    if (D.opens) c.opens = D.opens[e];
+  }
+  int32_t none = -1;
+  const int32_t tgt = restart_search<DIAG, false>(A, R, A.vs[t], W.defer.cell[e], lev, kNoDefer,
+                                                  i, j, li, xi, yi, zi, &lev, c, &none);
+  A.target[e] = tgt;
+  if (DIAG) {
+    if (D.levels) D.levels[e] = lev;
+    if (D.visits) D.visits[e] = c.visits;
+    if (D.opens) D.opens[e] = c.opens;
+  }
+}
+
+// Number of requests: the first position whose sorted key is `none`.
+__global__ void phase2_count_k(SweepOut W, int64_t nreq, int64_t* out) {
+  int64_t lo = 0, hi = nreq;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (W.defer.key[mid] == W.defer.none) hi = mid; else lo = mid + 1;
+  }
+  *out = lo;
 }
 
 __global__ void fill_i32_k(int32_t* p, int64_t n, int32_t v) {
@@ -471,6 +521,14 @@ inline void launch_sweep(const SearchScratch& S, unsigned blocks, hipStream_t s)
     search_sweep_k<DIAG, SLOTS, false><<<blocks, kWaveBlock, 0, s>>>(S.B, S.W);
 }
 
+template <bool DIAG, int SLOTS>
+inline void launch_draw(const SearchScratch& S, unsigned grid, int block, hipStream_t s) {
+  if (S.W.defer.depth < kNoDefer)
+    search_draw_k<DIAG, SLOTS, true><<<grid, block, 0, s>>>(S.B, S.W);
+  else
+    search_draw_k<DIAG, SLOTS, false><<<grid, block, 0, s>>>(S.B, S.W);
+}
+
 inline hipError_t enqueue_search(SearchScratch& S, bool diag, unsigned sweep_blocks,
                                  int draw_block, hipStream_t s, hipEvent_t mid = nullptr) {
   const unsigned draw_grid = grid_for(S.B.max_slots, draw_block);
@@ -488,13 +546,13 @@ inline hipError_t enqueue_search(SearchScratch& S, bool diag, unsigned sweep_blo
     if (e != hipSuccess) return e;
   }
   if (diag && big)
-    search_draw_k<true, kCkptMax><<<draw_grid, draw_block, 0, s>>>(S.B, S.W);
+    launch_draw<true, kCkptMax>(S, draw_grid, draw_block, s);
   else if (diag)
-    search_draw_k<true, kCkptMin><<<draw_grid, draw_block, 0, s>>>(S.B, S.W);
+    launch_draw<true, kCkptMin>(S, draw_grid, draw_block, s);
   else if (big)
-    search_draw_k<false, kCkptMax><<<draw_grid, draw_block, 0, s>>>(S.B, S.W);
+    launch_draw<false, kCkptMax>(S, draw_grid, draw_block, s);
   else
-    search_draw_k<false, kCkptMin><<<draw_grid, draw_block, 0, s>>>(S.B, S.W);
+    launch_draw<false, kCkptMin>(S, draw_grid, draw_block, s);
   return hipGetLastError();
 }
 

@@ -104,6 +104,10 @@ SimDesc make_desc(const msp_octree_s* t, const uint8_t* neuron_type, const int32
   return d;
 }
 
+// Branch level of the two-phase search when the caller names none: restarts from
+// cells at this depth or deeper run in a second pass, in cell order.
+constexpr int kDefaultBranchLevel = kNoDefer;
+
 // Whether the sweep must test for the source's own cell: always, unless theta <= 1/2
 // and every position of the tree lies inside its cube (then that test never fires).
 bool own_cell_needed(const msp_octree_s* t, double theta) {
@@ -419,33 +423,85 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
   if (any) S.W.wave_steps = reinterpret_cast<unsigned long long*>(diag->wave_steps);
   MSP_HIP_TRY(enqueue_prep(S, n, s));
   int32_t status = 0, ntiles = 0;
+  int64_t total_S = 0;
   MSP_HIP_TRY(hipMemcpyAsync(&status, S.B.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   MSP_HIP_TRY(hipMemcpyAsync(&ntiles, S.counters, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MSP_HIP_TRY(hipMemcpyAsync(&total_S, elem_offset_out + n, sizeof(int64_t),
+                             hipMemcpyDeviceToHost, s));
   MSP_HIP_TRY(hipStreamSynchronize(s));
   if (status & kSimInvalid) return MSP_ERR_INVALID;
   if (status & kSimCapacity) return MSP_ERR_CAPACITY;
+  if (diag && diag->phase2_requests)
+    MSP_HIP_TRY(hipMemsetAsync(diag->phase2_requests, 0, sizeof(int64_t), s));
 
   const bool timed = diag && diag->kernel_ms;
   if (ntiles == 0) {
-    if (timed) diag->kernel_ms[0] = diag->kernel_ms[1] = 0.0f;
+    if (timed) diag->kernel_ms[0] = diag->kernel_ms[1] = diag->kernel_ms[2] = 0.0f;
     return MSP_OK;
+  }
+  // two phases: restarts from cells at depth >= the branch level wait for a second
+  // pass that takes them in cell order
+  int depth = kDefaultBranchLevel;
+  if (diag && diag->branch_level != 0) depth = diag->branch_level;
+  const bool two = depth >= 1 && depth <= kMaxDepth && total_S < INT32_MAX;
+  Temp req(s);
+  constexpr int key_bits = 16;        // two radix passes; keys < 2^15 < none
+  if (two) {
+    int node_bits = 1;
+    while ((1ll << node_bits) < t->N) ++node_bits;
+    const size_t ks = align_up(sizeof(uint64_t) * total_S);
+    const size_t vs = align_up(sizeof(int32_t) * total_S);
+    const size_t ls = align_up(sizeof(uint8_t) * total_S);
+    MSP_HIP_TRY(req.alloc(2 * ks + 5 * vs + ls + radix_sort_ws_bytes(total_S)));
+    char* p = static_cast<char*>(req.p);
+    DeferOut& D = S.W.defer;
+    D.depth = depth;
+    D.shift = std::max(0, node_bits - (key_bits - 1));
+    D.none = (1ull << key_bits) - 1;
+    D.key = reinterpret_cast<uint64_t*>(p);
+    D.val = reinterpret_cast<int32_t*>(p + 2 * ks);
+    D.src = reinterpret_cast<int32_t*>(p + 2 * ks + 2 * vs);
+    D.elem = reinterpret_cast<int32_t*>(p + 2 * ks + 3 * vs);
+    D.cell = reinterpret_cast<int32_t*>(p + 2 * ks + 4 * vs);
+    D.level = reinterpret_cast<uint8_t*>(p + 2 * ks + 5 * vs);
   }
   unsigned blocks = 0;
   MSP_HIP_TRY(sweep_blocks_for(t->device, any, ntiles, 1.0, &blocks));
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   if (timed) {
     for (auto& e : ev) MSP_HIP_TRY(hipEventCreate(&e));
     MSP_HIP_TRY(hipEventRecord(ev[0], s));
   }
   hipError_t le = enqueue_search(S, any, blocks, 256, s, timed ? ev[1] : nullptr);
+  if (timed && le == hipSuccess) le = hipEventRecord(ev[2], s);
+  if (two && le == hipSuccess) {
+    const size_t ks = align_up(sizeof(uint64_t) * total_S);
+    const size_t vs = align_up(sizeof(int32_t) * total_S);
+    const DeferOut& D = S.W.defer;
+    char* p = static_cast<char*>(req.p);
+    le = radix_sort_pairs_ws(D.key, D.val, reinterpret_cast<uint64_t*>(p + ks),
+                             reinterpret_cast<int32_t*>(p + 2 * ks + vs), total_S, key_bits, s,
+                             p + 2 * ks + 5 * vs + align_up(sizeof(uint8_t) * total_S));
+    if (le == hipSuccess) {
+      if (any)
+        search_phase2_k<true><<<grid_for(total_S, 256), 256, 0, s>>>(S.B, S.W, total_S);
+      else
+        search_phase2_k<false><<<grid_for(total_S, 256), 256, 0, s>>>(S.B, S.W, total_S);
+      if (diag && diag->phase2_requests)
+        phase2_count_k<<<1, 1, 0, s>>>(S.W, total_S, diag->phase2_requests);
+      le = hipGetLastError();
+    }
+  }
   if (timed) {
-    float a = 0.0f, b = 0.0f;
-    (void)hipEventRecord(ev[2], s);
-    (void)hipEventSynchronize(ev[2]);
+    float a = 0.0f, b = 0.0f, c = 0.0f;
+    (void)hipEventRecord(ev[3], s);
+    (void)hipEventSynchronize(ev[3]);
     (void)hipEventElapsedTime(&a, ev[0], ev[1]);
     (void)hipEventElapsedTime(&b, ev[1], ev[2]);
+    (void)hipEventElapsedTime(&c, ev[2], ev[3]);
     diag->kernel_ms[0] = a;
     diag->kernel_ms[1] = b;
+    diag->kernel_ms[2] = c;
     for (auto& e : ev) (void)hipEventDestroy(e);
   }
   MSP_HIP_TRY(le);

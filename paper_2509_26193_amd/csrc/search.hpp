@@ -201,13 +201,29 @@ __device__ __forceinline__ double draw_u(uint64_t seed, int32_t i, int32_t j, ui
   return (double)(r >> 40) * 0x1p-24;
 }
 
-// Levels >= 1 of a search: restart at the chosen cell S until a neuron is drawn.
-template <bool COUNT>
+constexpr int32_t kDeferred = -2;      // restart handed on to the second phase
+constexpr int kNoDefer = 1 << 20;      // a defer depth no cell reaches
+
+// Depth of an inner node (a drawn cell is always one: leaf entries are neurons).
+__device__ __forceinline__ int cell_depth(uint32_t meta) {
+  return (int)((meta >> kSkipBits) & 31u);
+}
+
+// Levels >= level0 of a search (level0 >= 1): restart at the chosen cell S until a
+// neuron is drawn. A cell at depth >= defer_depth is not expanded here: the call
+// returns kDeferred with *S_out = that cell and *levels_out = the levels drawn so far
+// (its expansion is level *levels_out), for the second phase to continue from.
+template <bool COUNT, bool DEFER>
 __device__ int32_t restart_search(const SearchArgs& A, const NodeRec* R, const int32_t* vs,
-                                  int32_t S, int32_t i, int32_t j, int32_t li, double xi,
-                                  double yi, double zi, int* levels_out, Count& cnt) {
+                                  int32_t S, int level0, int defer_depth, int32_t i, int32_t j,
+                                  int32_t li, double xi, double yi, double zi, int* levels_out,
+                                  Count& cnt, int32_t* S_out) {
   Count none;
-  for (int level = 1; level < kMaxLevels; ++level) {
+  for (int level = level0; level < kMaxLevels; ++level) {
+    if (DEFER && cell_depth(R[S].meta) >= defer_depth) {
+      *S_out = S;
+      return kDeferred;
+    }
     SumPass s{A.k2};
     expand<COUNT>(A, R, vs, S, i, li, xi, yi, zi, s, cnt);
     *levels_out = level + 1;

@@ -27,6 +27,23 @@ constexpr int kCkptStepMin = 16;   // smallest checkpoint interval, wave steps
 constexpr int kWaveBlock = 256;    // 4 independent waves per block
 constexpr int kXcd = 8;            // accelerator dies; workgroup b runs on die b % 8
 
+// Requests of the second phase of a two-phase search (one simulation): one entry per
+// element e; key[e] is the deferred cell's pre-order index >> shift, or `none` if the
+// element was finished in the first phase. Sorting by key groups the requests by
+// pre-order range, and the pre-order makes every subtree (a branch cell's in
+// particular) one contiguous range.
+struct DeferOut {
+  int depth = kNoDefer;            // cells at this depth or deeper are deferred
+  int shift = 0;
+  uint64_t none = ~0ull;
+  uint64_t* key = nullptr;         // [S]
+  int32_t* val = nullptr;          // [S] e
+  int32_t* cell = nullptr;         // [S] the deferred cell
+  int32_t* src = nullptr;          // [S] source neuron
+  int32_t* elem = nullptr;         // [S] element j of the source
+  uint8_t* level = nullptr;        // [S] level of the deferred expansion
+};
+
 struct SweepOut {
   double* Z;                       // [slots] level-0 sum
   int32_t* v0;                     // [slots] level-0 visits (counting launches only)
@@ -39,6 +56,7 @@ struct SweepOut {
   const int32_t* tile_count;       // device scalar
   int32_t* queue;                  // [kXcd] tile counters, zero at launch
   unsigned long long* wave_steps;  // counting launches: total wave steps (nullable)
+  DeferOut defer;                  // two-phase search (depth kNoDefer: one phase)
 };
 
 // Read-only data seen through the constant address space: wave-uniform loads from
@@ -223,8 +241,9 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
   return steps;
 }
 
-// The draws and restarts of the source in worklist slot `slot`.
-template <bool DIAG, int SLOTS>
+// The draws and restarts of the source in worklist slot `slot` (DEFER: restarts from
+// cells at depth >= W.defer.depth become second-phase requests).
+template <bool DIAG, int SLOTS, bool DEFER>
 __device__ __forceinline__ void draw_slot(const SearchArgs& A, const DiagOut& D, const SweepOut& W,
                                           int64_t slot) {
   const int32_t i = A.work[slot];
@@ -255,6 +274,7 @@ __device__ __forceinline__ void draw_slot(const SearchArgs& A, const DiagOut& D,
     int lev = 1;
     Count c = c0;
     int32_t tgt = -1;
+    int32_t deferred = -1;
     if (Z > 0.0) {
       const double T = draw_u(A.seed, i, j, A.step, 0) * Z;
       SelectPass p{A.k2, T};
@@ -275,7 +295,23 @@ __device__ __forceinline__ void draw_slot(const SearchArgs& A, const DiagOut& D,
       const int32_t id = p.chosen >= 0 ? p.chosen : p.last;
       const bool neuron = p.chosen >= 0 ? p.chosen_neuron : p.last_neuron;
       if (id >= 0)
-        tgt = neuron ? id : restart_search<DIAG>(A, R, vs, id, i, j, li, xi, yi, zi, &lev, c);
+        tgt = neuron ? id
+                     : restart_search<DIAG, DEFER>(A, R, vs, id, 1, W.defer.depth, i, j, li,
+                                                   xi, yi, zi, &lev, c, &deferred);
+    }
+    if (DEFER) {
+      const int64_t e = off + j;
+      if (tgt == kDeferred) {
+        W.defer.key[e] = (uint64_t)((uint32_t)deferred >> W.defer.shift);
+        W.defer.cell[e] = deferred;
+        W.defer.src[e] = i;
+        W.defer.elem[e] = j;
+        W.defer.level[e] = (uint8_t)lev;
+        tgt = -1;                               // the second phase overwrites it
+      } else {
+        W.defer.key[e] = W.defer.none;
+      }
+      W.defer.val[e] = (int32_t)e;
     }
     A.target[off + j] = tgt;
     if (DIAG) {
