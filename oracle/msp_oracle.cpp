@@ -22,6 +22,11 @@
 //   * commit: Sec. III-A "Update of synapses" (neurons accept as many requests as
 //     their vacant dendritic elements allow, chosen randomly, and decline the rest)
 //     and Sec. III-B (all requests are formed before the exchange).
+//   * electrical activity: Sec. II "Update of electrical activity" (exchange the
+//     previous step's spikes, new state from the inputs and background noise, record
+//     spikes, update calcium, a running average of the firing rate) with the neuron
+//     model the paper names (Izhikevich), and Sec. IV-B (between processes, a spike
+//     is drawn from the sender's frequency of the previous epoch).
 //   * Philox4x64-10: Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
 //     as 1, 2, 3", SC'11. The paper leaves the generator open.
 //
@@ -756,6 +761,96 @@ int64_t oracle_plasticity_step(int64_t n, int64_t m, double nu, double eps, doub
     for (int64_t j = 0; j < n; ++j)
       vac[k * n + j] = (int32_t)((int64_t)std::floor(z[k * n + j]) - bound[k * n + j]);
   return w;
+}
+
+
+// ---------------------------------------------------------------------------
+// Electrical activity between connectivity updates (Sec. II, "Update of electrical
+// activity") with the firing-rate approximation of Sec. IV-B. One step is 1 ms:
+//   1. exchange: the spikes a neuron recorded in the previous step reach its synapse
+//      partners. Under the approximation, a synapse whose two neurons lie in
+//      different processes (approx = 1; every synapse with approx = 2) carries a
+//      spike at step t iff u < f_i, f_i being the source's firing frequency over the
+//      previous epoch (spikes per step) and u = (Philox word 0 >> 11) * 2^-53 with
+//      key (seed, 5) and counter (synapse s, t, 0, 0). Per target g: e_g excitatory
+//      and h_g inhibitory spikes received (the synapse type is the source's type);
+//   2. neuron model (Izhikevich 2003; regular spiking for excitatory, fast spiking
+//      for inhibitory neurons): I = w_e e_g - w_i h_g + mu + width (u' - 1/2) with u'
+//      from key (seed, 6), counter (g, t, 0, 0); v += (0.04 v^2 + 5 v + 140 - u + I)/2
+//      twice (two half-millisecond steps), u += a (b v - u); v >= 30 is a spike:
+//      v = c, u += d, and the spike is recorded for the next step;
+//   3. calcium (a running average of the firing rate): Ca -= Ca / tau, then
+//      Ca += beta for a spike;
+//   4. every epoch (delta steps; the step t with (t + 1) % delta == 0 closes one) the
+//      frequency f = spikes in the epoch / delta replaces the previous one.
+// Every operation is a +, -, * or a comparison in fp64 (1/tau and 1/delta are
+// passed in), so the library's result is the same bit for bit.
+// last_input (nullable) [2][n] receives e and h of the last step.
+// ---------------------------------------------------------------------------
+int64_t oracle_activity_run(int64_t n, const uint8_t* ntype, const int32_t* rank,
+                            int64_t m, const int32_t* src, const int32_t* tgt,
+                            const uint8_t* stype, int32_t approx, const double* p,
+                            double inv_tau, double inv_delta, int32_t delta, uint64_t seed,
+                            uint64_t t0, int32_t steps, double* v, double* u, double* ca,
+                            uint8_t* spk, int32_t* count, double* freq, int32_t* last_input) {
+  // p: a_e b_e c_e d_e a_i b_i c_i d_i w_e w_i mu width beta
+  std::vector<int32_t> e(n), h(n);
+  std::vector<uint8_t> fired(n);
+  int64_t total = 0;
+  for (int32_t k = 0; k < steps; ++k) {
+    const uint64_t t = t0 + (uint64_t)k;
+    std::fill(e.begin(), e.end(), 0);
+    std::fill(h.begin(), h.end(), 0);
+    for (int64_t s = 0; s < m; ++s) {
+      const int32_t i = src[s], g = tgt[s];
+      const bool remote = approx == 2 || (approx == 1 && rank && rank[i] != rank[g]);
+      bool arrives;
+      if (remote) {
+        P4 ctr = {{(uint64_t)s, t, 0, 0}};
+        const double uu = (double)(philox4x64_10(ctr, seed, 5).v[0] >> 11) * 0x1p-53;
+        arrives = uu < freq[i];
+      } else {
+        arrives = spk[i] != 0;
+      }
+      if (arrives) {
+        if (stype[s] == 0) e[g] += 1; else h[g] += 1;
+      }
+    }
+    for (int64_t g = 0; g < n; ++g) {
+      const double* q = ntype[g] ? p + 4 : p;
+      P4 ctr = {{(uint64_t)g, t, 0, 0}};
+      const double uu = (double)(philox4x64_10(ctr, seed, 6).v[0] >> 11) * 0x1p-53;
+      const double I = p[8] * (double)e[g] - p[9] * (double)h[g] + (p[10] + p[11] * (uu - 0.5));
+      double vv = v[g], w = u[g];
+      vv = vv + 0.5 * (0.04 * vv * vv + 5.0 * vv + 140.0 - w + I);
+      vv = vv + 0.5 * (0.04 * vv * vv + 5.0 * vv + 140.0 - w + I);
+      w = w + q[0] * (q[1] * vv - w);
+      const bool f = vv >= 30.0;
+      if (f) {
+        vv = q[2];
+        w = w + q[3];
+      }
+      v[g] = vv;
+      u[g] = w;
+      double c = ca[g];
+      c = c - c * inv_tau;
+      if (f) c = c + p[12];
+      ca[g] = c;
+      fired[g] = f ? 1 : 0;
+      count[g] += f ? 1 : 0;
+      total += f ? 1 : 0;
+      if ((t + 1) % (uint64_t)delta == 0) {
+        freq[g] = (double)count[g] * inv_delta;
+        count[g] = 0;
+      }
+    }
+    std::memcpy(spk, fired.data(), (size_t)n);
+    if (last_input && k == steps - 1) {
+      std::memcpy(last_input, e.data(), sizeof(int32_t) * n);
+      std::memcpy(last_input + n, h.data(), sizeof(int32_t) * n);
+    }
+  }
+  return total;
 }
 
 }  // extern "C"

@@ -79,6 +79,11 @@ def lib():
         L.oracle_plasticity_step.argtypes = [_i64, _i64, _dbl, _dbl, _dbl, ctypes.c_int32, _dbl,
                                              _dbl, _dbl, _u64, _u64, _ptr, _ptr, _ptr, _ptr,
                                              _ptr, _ptr]
+        L.oracle_activity_run.restype = _i64
+        L.oracle_activity_run.argtypes = [_i64, _ptr, _ptr, _i64, _ptr, _ptr, _ptr,
+                                          ctypes.c_int32, _ptr, _dbl, _dbl, ctypes.c_int32,
+                                          _u64, _u64, ctypes.c_int32, _ptr, _ptr, _ptr, _ptr,
+                                          _ptr, _ptr, _ptr]
         _lib = L
     return _lib
 
@@ -288,3 +293,53 @@ class Network:
 
     def synapses(self):
         return self.src[:self.m].copy(), self.tgt[:self.m].copy(), self.type[:self.m].copy()
+
+
+# Electrical activity (Sec. II) with the firing-rate approximation (Sec. IV-B):
+# Izhikevich's regular-spiking (excitatory) and fast-spiking (inhibitory) neurons,
+# uniform background current, calcium as a running average of spikes, frequencies
+# exchanged every `delta` steps.
+ACTIVITY = dict(a_exc=0.02, b_exc=0.2, c_exc=-65.0, d_exc=8.0, a_inh=0.1, b_inh=0.2,
+                c_inh=-65.0, d_inh=2.0, w_exc=2.0, w_inh=4.0, bg_mean=4.5, bg_width=9.0,
+                ca_beta=0.001, ca_tau=10000.0, epoch=100)
+
+_ACT_KEYS = ("a_exc", "b_exc", "c_exc", "d_exc", "a_inh", "b_inh", "c_inh", "d_inh", "w_exc",
+             "w_inh", "bg_mean", "bg_width", "ca_beta")
+
+
+class Activity:
+    """Per-neuron state of the electrical activity: v, u, calcium (float64), the
+    spikes of the last step (uint8), the spike count of the running epoch (int32) and
+    the frequency of the previous epoch (float64)."""
+
+    def __init__(self, neuron_type, params=None):
+        self.type = np.ascontiguousarray(neuron_type, dtype=np.uint8)
+        self.n = self.type.size
+        self.p = dict(ACTIVITY, **(params or {}))
+        inh = self.type != 0
+        c = np.where(inh, self.p["c_inh"], self.p["c_exc"])
+        b = np.where(inh, self.p["b_inh"], self.p["b_exc"])
+        self.v = np.ascontiguousarray(c, dtype=np.float64)
+        self.u = np.ascontiguousarray(b * c, dtype=np.float64)
+        self.ca = np.zeros(self.n, np.float64)
+        self.spk = np.zeros(self.n, np.uint8)
+        self.count = np.zeros(self.n, np.int32)
+        self.freq = np.zeros(self.n, np.float64)
+
+    def run(self, syn_src, syn_tgt, syn_type, seed: int, t0: int, steps: int, approx: int = 0,
+            rank=None, last_input: bool = False):
+        """`steps` steps from global step t0. approx: 0 every spike is exchanged, 1 the
+        synapses between different ranks use the frequency, 2 every synapse does.
+        Returns the number of spikes (and the inputs [2, n] of the last step)."""
+        src = np.ascontiguousarray(syn_src, dtype=np.int32)
+        tgt = np.ascontiguousarray(syn_tgt, dtype=np.int32)
+        sty = np.ascontiguousarray(syn_type, dtype=np.uint8)
+        rk = None if rank is None else np.ascontiguousarray(rank, dtype=np.int32)
+        pv = np.array([self.p[k] for k in _ACT_KEYS], dtype=np.float64)
+        li = np.zeros((2, self.n), np.int32) if last_input else None
+        total = lib().oracle_activity_run(
+            self.n, _p(self.type), _p(rk), src.size, _p(src), _p(tgt), _p(sty), int(approx),
+            _p(pv), 1.0 / self.p["ca_tau"], 1.0 / self.p["epoch"], int(self.p["epoch"]),
+            int(seed), int(t0), int(steps), _p(self.v), _p(self.u), _p(self.ca), _p(self.spk),
+            _p(self.count), _p(self.freq), _p(li))
+        return (int(total), li) if last_input else int(total)
