@@ -257,6 +257,60 @@ def bench_two_phase(msp, torch, w, alg_bytes, branch_level=6, reps=4):
                      "communication it removes between processes")
 
 
+def bench_activity(msp, torch, w, steps=100):
+    """Electrical activity between two connectivity updates (one epoch of `steps` 1 ms
+    steps) on the synapses that one update of the headline workload forms, with every
+    spike exchanged and with the firing-rate approximation between 8 ranks that own
+    contiguous Morton ranges (the paper's domain division) or on every synapse."""
+    dev = torch.device("cuda:0")
+    T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    ty = T(w.neuron_type, torch.uint8)
+    va, ve, vi = (T(x, torch.int32) for x in (w.vac_axon, w.vac_exc, w.vac_inh))
+    tree = msp.build_octree(T(w.pos, torch.float64), w.box_min, w.box_edge)
+    msp.update_vacant_counts(tree, ve, vi)
+    tgt, off = msp.find_targets(tree, ty, va, w.sigma, w.theta, w.seed, w.step)
+    res = msp.commit_synapses(tgt, off, ty, va, ve, vi, w.seed, w.step, syn_capacity=w.searches)
+    order = tree.export_topology()["order"]
+    tree.free()
+    rank = torch.empty(w.n, dtype=torch.int32, device=dev)
+    rank[order.long()] = (torch.arange(w.n, device=dev) * 8 // w.n).to(torch.int32)
+    src, tgt_, sty = res["syn_src"], res["syn_tgt"], res["syn_type"]
+    m = src.numel()
+    remote = float((rank[src.long()] != rank[tgt_.long()]).float().mean())
+    out = dict(workload=f"activity_{w.n}_neurons_{m}_synapses", neurons=w.n, synapses=m,
+               steps=steps, remote_synapse_share=remote)
+    for approx, name in ((0, "exact"), (1, "approx_between_8_ranks"), (2, "approx_all")):
+        a = msp.Activity(ty)
+        a.run(src, tgt_, sty, seed=w.seed, t0=0, steps=steps, approx=approx, rank=rank)
+        sp = torch.zeros(1, dtype=torch.int64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a.run(src, tgt_, sty, seed=w.seed, t0=steps, steps=steps, approx=approx, rank=rank,
+              spikes=sp)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        # per step: the neuron state read and written (74 B) and per synapse its
+        # endpoints, type and the source's spike (10 B), the frequency instead of the
+        # spike where approximated (+7 B), and the rank-split flag (+1 B, approx 1)
+        n_apx = 0 if approx == 0 else (m * remote if approx == 1 else m)
+        B = int(74 * w.n + 10 * m + 7 * n_apx + (m if approx == 1 else 0))
+        out[name] = dict(ms_per_step=sec * 1e3, neuron_steps_per_s=w.n / sec,
+                         spikes=int(sp.item()), rate_hz=int(sp.item()) / w.n / (steps * 1e-3),
+                         roofline=hbm_roofline(B, sec, "74 B per neuron + 10 B per synapse "
+                                               "(+7 B approximated, +1 B rank flag) and "
+                                               "step / wall time per step"))
+    # the oracle: 3 steps of the same network, all 8M neurons, one host thread
+    from oracle import oracle as orc
+    o = orc.Activity(w.neuron_type)
+    hs, ht, hy = (x.cpu().numpy() for x in (src, tgt_, sty))
+    t0 = time.perf_counter()
+    o.run(hs, ht, hy, seed=w.seed, t0=0, steps=3)
+    t_or = (time.perf_counter() - t0) / 3
+    out["oracle"] = dict(value=w.n / t_or, unit="neuron steps/s", cores=1, kind="oracle",
+                         sample="3 steps of the same network (every spike exchanged)")
+    return out
+
+
 def bench_batched(msp, torch, reps=5):
     """64 simulations of 2^12..2^18 neurons: one batched launch (HIP graph) against 64
     per-simulation find_targets calls, same stream, same results (checked)."""
@@ -652,6 +706,8 @@ def main():
         del wc
         log("also: two-phase search")
         also["two_phase_8M"] = bench_two_phase(msp, torch, w, B)
+        log("also: electrical activity")
+        also["activity"] = bench_activity(msp, torch, w)
         log("also: batched")
         also["batched"] = bench_batched(msp, torch)
         log("also: attraction")

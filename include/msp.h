@@ -362,6 +362,57 @@ msp_status msp_plasticity_step(int64_t n, const msp_plasticity_params* params, u
                                int32_t* vac_axon, int32_t* vac_exc, int32_t* vac_inh,
                                hipStream_t s);
 
+/*
+ * Electrical activity between connectivity updates (Sec. II, "Update of electrical
+ * activity") with the firing-rate approximation of Sec. IV-B: neurons exchange
+ * spikes, integrate them and their background input, record new spikes and update
+ * their calcium; every epoch of `epoch` steps their firing frequency is refreshed.
+ * Parameters of the neuron model (Izhikevich 2003: a, b, c, d per type, regular
+ * spiking for excitatory and fast spiking for inhibitory neurons), the synaptic
+ * weights per received spike, the uniform background current (mean, width) and the
+ * calcium increment per spike and time constant (in steps):
+ */
+typedef struct msp_activity_params {
+  double a_exc, b_exc, c_exc, d_exc;
+  double a_inh, b_inh, c_inh, d_inh;
+  double w_exc, w_inh;
+  double bg_mean, bg_width;
+  double ca_beta, ca_tau;
+  int32_t epoch;
+} msp_activity_params;
+
+/*
+ * Runs steps t0 .. t0 + steps - 1 (1 ms each). Per step t:
+ *   1. exchange: synapse s (syn_src -> syn_tgt, syn_type = the source's type 0/1)
+ *      carries the spike its source recorded in step t - 1 (spiked). With approx = 1,
+ *      the synapses whose two neurons have different `rank` (the processes of a
+ *      distributed run) instead carry a spike iff u < freq[source], u = (word 0 >> 11)
+ *      2^-53 of Philox4x64-10 with key (seed, 5) and counter (s, t, 0, 0); approx = 2
+ *      does so for every synapse; approx = 0 exchanges every spike. Each target counts
+ *      the excitatory (e) and inhibitory (h) spikes it receives;
+ *   2. I = w_exc e - w_inh h + bg_mean + bg_width (u' - 1/2), u' as above with key
+ *      (seed, 6) and counter (neuron, t, 0, 0); v += (0.04 v^2 + 5 v + 140 - u + I) / 2
+ *      twice, then u += a (b v - u); v >= 30 is a spike: v = c, u += d, spiked = 1;
+ *   3. calcium -= calcium / ca_tau, then += ca_beta on a spike;
+ *   4. if (t + 1) % epoch == 0: freq = epoch_count / epoch (spikes per step), and
+ *      epoch_count restarts at 0.
+ * All state is device memory of the caller, updated in place: v, u, calcium, freq
+ * [n] float64; spiked [n] uint8; epoch_count [n] int32. rank [n] int32 is needed for
+ * approx = 1 only. last_input (nullable, [2][n] int32) receives e and h of the last
+ * step; spikes (nullable device int64 scalar) is incremented by the spikes of the run.
+ * Errors: MSP_ERR_INVALID for n < 1, m < 0, steps < 0, approx outside 0..2, a null
+ * pointer that is needed, epoch < 1 or ca_tau <= 0; a synapse with an endpoint
+ * outside [0, n) or a type > 1 is skipped and the call returns MSP_ERR_INVALID after
+ * the run. Waits on `s` once, at the end.
+ */
+msp_status msp_activity_run(int64_t n, const uint8_t* neuron_type, const int32_t* rank,
+                            int64_t m, const int32_t* syn_src, const int32_t* syn_tgt,
+                            const uint8_t* syn_type, int32_t approx,
+                            const msp_activity_params* params, uint64_t seed, uint64_t t0,
+                            int32_t steps, double* v, double* u, double* calcium,
+                            uint8_t* spiked, int32_t* epoch_count, double* freq,
+                            int32_t* last_input, int64_t* spikes, hipStream_t s);
+
 #ifdef __cplusplus
 }
 #endif

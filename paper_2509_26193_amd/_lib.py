@@ -56,6 +56,13 @@ class PlasticityParams(ctypes.Structure):
                 ("steps_per_update", _i32)]
 
 
+class ActivityParams(ctypes.Structure):
+    _fields_ = [("a_exc", _dbl), ("b_exc", _dbl), ("c_exc", _dbl), ("d_exc", _dbl),
+                ("a_inh", _dbl), ("b_inh", _dbl), ("c_inh", _dbl), ("d_inh", _dbl),
+                ("w_exc", _dbl), ("w_inh", _dbl), ("bg_mean", _dbl), ("bg_width", _dbl),
+                ("ca_beta", _dbl), ("ca_tau", _dbl), ("epoch", _i32)]
+
+
 _SIGS = {
     "msp_status_string": (ctypes.c_char_p, [_i32]),
     "msp_sync": (_i32, [_vp]),
@@ -83,6 +90,9 @@ _SIGS = {
                                      _vp]),
     "msp_plasticity_step": (_i32, [_i64, ctypes.POINTER(PlasticityParams), _u64, _u64, _vp, _vp,
                                    _vp, _vp, _vp, _i64, ctypes.POINTER(_i64), _vp, _vp, _vp, _vp]),
+    "msp_activity_run": (_i32, [_i64, _vp, _vp, _i64, _vp, _vp, _vp, _i32,
+                                ctypes.POINTER(ActivityParams), _u64, _u64, _i32, _vp, _vp, _vp,
+                                _vp, _vp, _vp, _vp, _vp, _vp]),
 }
 
 MSP_BATCH_GRAPH = 1
@@ -503,3 +513,56 @@ class Network:
 
     def synapses(self):
         return self.src[:self.m], self.tgt[:self.m], self.type[:self.m]
+
+
+ACTIVITY = dict(a_exc=0.02, b_exc=0.2, c_exc=-65.0, d_exc=8.0, a_inh=0.1, b_inh=0.2,
+                c_inh=-65.0, d_inh=2.0, w_exc=2.0, w_inh=4.0, bg_mean=4.5, bg_width=9.0,
+                ca_beta=0.001, ca_tau=10000.0, epoch=100)
+
+
+class Activity:
+    """Device state of the electrical activity (msp_activity_run): v, u, calcium and
+    the previous epoch's frequency (float64), the last step's spikes (uint8) and the
+    running epoch's spike count (int32), for neurons of the given types."""
+
+    def __init__(self, neuron_type: torch.Tensor, params: dict | None = None):
+        self.type = neuron_type
+        self.n = neuron_type.numel()
+        self.p = dict(ACTIVITY, **(params or {}))
+        dev = neuron_type.device
+        inh = neuron_type != 0
+        c = torch.where(inh, torch.tensor(self.p["c_inh"], dtype=torch.float64, device=dev),
+                        torch.tensor(self.p["c_exc"], dtype=torch.float64, device=dev))
+        b = torch.where(inh, torch.tensor(self.p["b_inh"], dtype=torch.float64, device=dev),
+                        torch.tensor(self.p["b_exc"], dtype=torch.float64, device=dev))
+        self.v = c.contiguous()
+        self.u = (b * c).contiguous()
+        self.calcium = torch.zeros(self.n, dtype=torch.float64, device=dev)
+        self.spiked = torch.zeros(self.n, dtype=torch.uint8, device=dev)
+        self.count = torch.zeros(self.n, dtype=torch.int32, device=dev)
+        self.freq = torch.zeros(self.n, dtype=torch.float64, device=dev)
+
+    def run(self, syn_src: torch.Tensor, syn_tgt: torch.Tensor, syn_type: torch.Tensor,
+            seed: int, t0: int, steps: int, approx: int = 0, rank: torch.Tensor | None = None,
+            last_input: bool = False, spikes: torch.Tensor | None = None, stream=None):
+        """Steps t0 .. t0 + steps - 1. approx: 0 exchange every spike, 1 use the
+        frequency on synapses between different ranks, 2 on every synapse. Returns the
+        inputs [2, n] of the last step when last_input is set. `spikes` (device int64
+        [1]) is incremented by the number of spikes."""
+        m = syn_src.numel()
+        li = torch.empty((2, self.n), dtype=torch.int32, device=self.type.device) \
+            if last_input else None
+        P = ActivityParams(*[self.p[f] for f, _ in ActivityParams._fields_])
+        _check(lib().msp_activity_run(
+            self.n, _dev(self.type, torch.uint8, "neuron_type", self.n),
+            None if rank is None else _dev(rank, torch.int32, "rank", self.n), m,
+            _dev(syn_src, torch.int32, "syn_src", m) if m else None,
+            _dev(syn_tgt, torch.int32, "syn_tgt", m) if m else None,
+            _dev(syn_type, torch.uint8, "syn_type", m) if m else None, int(approx),
+            ctypes.byref(P), int(seed), int(t0), int(steps), self.v.data_ptr(),
+            self.u.data_ptr(), self.calcium.data_ptr(), self.spiked.data_ptr(),
+            self.count.data_ptr(), self.freq.data_ptr(),
+            None if li is None else li.data_ptr(),
+            None if spikes is None else _dev(spikes, torch.int64, "spikes", 1),
+            _stream(stream)), "activity_run")
+        return li

@@ -1,0 +1,141 @@
+// Electrical activity between connectivity updates (Sec. II, "Update of electrical
+// activity"), with the firing-rate approximation of Sec. IV-B. One step is 1 ms:
+//   * exchange (act_input_k, one thread per synapse): the spike a source recorded in
+//     the previous step reaches the target. Approximated synapses (approx 1: those
+//     whose two neurons carry different ranks; approx 2: all) carry a spike at step
+//     t iff u < f_i, f_i being the source's frequency over the previous epoch (spikes
+//     per step) and u = (Philox word 0 >> 11) 2^-53, key (seed, 5), counter (s, t, 0,
+//     0). Targets count excitatory and inhibitory arrivals (exact integer atomics);
+//   * neuron model (act_neuron_k, one thread per neuron): Izhikevich 2003, regular
+//     spiking (excitatory) or fast spiking (inhibitory):
+//       I = w_e e - w_i h + mu + width (u' - 1/2), u' from key (seed, 6), counter (g, t, 0, 0);
+//       v += (0.04 v^2 + 5 v + 140 - u + I) / 2, twice (two half-millisecond steps);
+//       u += a (b v - u); v >= 30: spike, v = c, u += d;
+//   * calcium, a running average of the spikes: Ca -= Ca / tau, then += beta on a spike;
+//   * a step t with (t + 1) % delta == 0 closes an epoch: f = spikes in it / delta.
+// Only +, -, * and comparisons on fp64 (1/tau and 1/delta come from the host), with
+// no contraction, so every value is exactly the IEEE evaluation of these formulas.
+#pragma once
+
+#include "common.hpp"
+
+namespace msp {
+
+constexpr int kActBlock = 256;
+
+struct ActParams {
+  double a[2], b[2], c[2], d[2];   // per neuron type (0 excitatory, 1 inhibitory)
+  double w_e, w_i, mu, width, beta, inv_tau, inv_delta;
+  int32_t delta;
+};
+
+// Per synapse: do its neurons lie in different ranks (fixed over a run, so the two
+// rank gathers are paid once, not every step). Endpoints are checked by act_input_k.
+__global__ void __launch_bounds__(kActBlock) act_remote_k(int64_t n, int64_t m,
+                                                         const int32_t* __restrict__ src,
+                                                         const int32_t* __restrict__ tgt,
+                                                         const int32_t* __restrict__ rank,
+                                                         uint8_t* __restrict__ remote) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= m) return;
+  const int32_t i = src[s], g = tgt[s];
+  remote[s] = (i >= 0 && i < n && g >= 0 && g < n && rank[i] != rank[g]) ? 1 : 0;
+}
+
+// remote (nullable): per-synapse flags of act_remote_k, for approx 1.
+__global__ void __launch_bounds__(kActBlock) act_input_k(
+    int64_t n, int64_t m, const int32_t* __restrict__ src, const int32_t* __restrict__ tgt,
+    const uint8_t* __restrict__ stype, const uint8_t* __restrict__ remote_of, int32_t approx,
+    uint64_t seed, uint64_t t, const uint8_t* __restrict__ spk, const double* __restrict__ freq,
+    int32_t* e, int32_t* h, int32_t* err) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= m) return;
+  const int32_t i = src[s], g = tgt[s];
+  const uint8_t ty = stype[s];
+  if (i < 0 || i >= n || g < 0 || g >= n || ty > 1) {
+    atomicOr(err, 1);
+    return;
+  }
+  const bool remote = approx == 2 || (approx == 1 && remote_of[s] != 0);
+  bool arrives;
+  if (remote) {
+    const double u = (double)(philox_word0(seed, 5, (uint64_t)s, t, 0, 0) >> 11) * 0x1p-53;
+    arrives = u < freq[i];
+  } else {
+    arrives = spk[i] != 0;
+  }
+  if (arrives) atomicAdd(ty ? &h[g] : &e[g], 1);
+}
+
+// The step's arrivals are consumed (and cleared for the next step) here.
+__global__ void __launch_bounds__(kActBlock) act_neuron_k(
+    int64_t n, const uint8_t* __restrict__ ntype, ActParams P, uint64_t seed, uint64_t t,
+    double* __restrict__ v, double* __restrict__ u, double* __restrict__ ca,
+    uint8_t* __restrict__ spk, int32_t* __restrict__ count, double* __restrict__ freq,
+    int32_t* __restrict__ e, int32_t* __restrict__ h, int32_t* __restrict__ last_input,
+    int64_t* __restrict__ part) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool f = false;
+  if (g < n) {
+    const int k = ntype[g] ? 1 : 0;
+    const int32_t ne = e[g], nh = h[g];
+    e[g] = 0;
+    h[g] = 0;
+    if (last_input) {
+      last_input[g] = ne;
+      last_input[n + g] = nh;
+    }
+    const double uu = (double)(philox_word0(seed, 6, (uint64_t)g, t, 0, 0) >> 11) * 0x1p-53;
+    const double I = P.w_e * (double)ne - P.w_i * (double)nh + (P.mu + P.width * (uu - 0.5));
+    double vv = v[g], w = u[g];
+    vv = vv + 0.5 * (0.04 * vv * vv + 5.0 * vv + 140.0 - w + I);
+    vv = vv + 0.5 * (0.04 * vv * vv + 5.0 * vv + 140.0 - w + I);
+    w = w + P.a[k] * (P.b[k] * vv - w);
+    f = vv >= 30.0;
+    if (f) {
+      vv = P.c[k];
+      w = w + P.d[k];
+    }
+    v[g] = vv;
+    u[g] = w;
+    double c = ca[g];
+    c = c - c * P.inv_tau;
+    if (f) c = c + P.beta;
+    ca[g] = c;
+    spk[g] = f ? 1 : 0;
+    int32_t cnt = count[g] + (f ? 1 : 0);
+    if ((t + 1) % (uint64_t)P.delta == 0) {
+      freq[g] = (double)cnt * P.inv_delta;
+      cnt = 0;
+    }
+    count[g] = cnt;
+  }
+  if (part) {                       // this block's spikes, added to its own slot
+    __shared__ int32_t wave_spikes[kActBlock / 64];
+    const uint64_t b = __ballot(f);
+    if ((threadIdx.x & 63) == 0) wave_spikes[threadIdx.x >> 6] = __popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t sum = 0;
+      for (int w = 0; w < kActBlock / 64; ++w) sum += wave_spikes[w];
+      part[blockIdx.x] += sum;
+    }
+  }
+}
+
+// Sum of the per-block spike counts, added to *spikes (one block).
+__global__ void __launch_bounds__(kActBlock) act_spikes_k(const int64_t* __restrict__ part,
+                                                         int64_t nblocks, int64_t* spikes) {
+  __shared__ int64_t acc[kActBlock];
+  int64_t sum = 0;
+  for (int64_t q = threadIdx.x; q < nblocks; q += kActBlock) sum += part[q];
+  acc[threadIdx.x] = sum;
+  __syncthreads();
+  for (int w = kActBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) acc[threadIdx.x] += acc[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *spikes += acc[0];
+}
+
+}  // namespace msp

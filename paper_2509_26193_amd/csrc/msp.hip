@@ -16,6 +16,7 @@
 #include "attraction.hpp"
 #include "commit.hpp"
 #include "plasticity.hpp"
+#include "activity.hpp"
 
 using namespace msp;
 
@@ -1092,6 +1093,72 @@ msp_status msp_plasticity_step(int64_t n, const msp_plasticity_params* params, u
   MSP_HIP_TRY(hipStreamSynchronize(s));
   *m_out = M;
   return MSP_OK;
+}
+
+
+msp_status msp_activity_run(int64_t n, const uint8_t* neuron_type, const int32_t* rank,
+                            int64_t m, const int32_t* syn_src, const int32_t* syn_tgt,
+                            const uint8_t* syn_type, int32_t approx,
+                            const msp_activity_params* params, uint64_t seed, uint64_t t0,
+                            int32_t steps, double* v, double* u, double* calcium,
+                            uint8_t* spiked, int32_t* epoch_count, double* freq,
+                            int32_t* last_input, int64_t* spikes, hipStream_t s) {
+  if (n < 1 || m < 0 || steps < 0 || approx < 0 || approx > 2 || !params || !neuron_type ||
+      !v || !u || !calcium || !spiked || !epoch_count || !freq)
+    return MSP_ERR_INVALID;
+  if (m > 0 && (!syn_src || !syn_tgt || !syn_type)) return MSP_ERR_INVALID;
+  if (approx == 1 && !rank) return MSP_ERR_INVALID;
+  const msp_activity_params& q = *params;
+  if (q.epoch < 1 || !(q.ca_tau > 0.0)) return MSP_ERR_INVALID;
+  if (steps == 0) return MSP_OK;
+  ActParams P;
+  P.a[0] = q.a_exc; P.b[0] = q.b_exc; P.c[0] = q.c_exc; P.d[0] = q.d_exc;
+  P.a[1] = q.a_inh; P.b[1] = q.b_inh; P.c[1] = q.c_inh; P.d[1] = q.d_inh;
+  P.w_e = q.w_exc;
+  P.w_i = q.w_inh;
+  P.mu = q.bg_mean;
+  P.width = q.bg_width;
+  P.beta = q.ca_beta;
+  P.inv_tau = 1.0 / q.ca_tau;
+  P.inv_delta = 1.0 / (double)q.epoch;
+  P.delta = q.epoch;
+  Temp arr(s), err(s), part(s), remote(s);
+  const int64_t nblocks = (int64_t)grid_for(n, kActBlock);
+  MSP_HIP_TRY(arr.alloc(sizeof(int32_t) * 2 * n));
+  MSP_HIP_TRY(err.alloc(sizeof(int32_t)));
+  int32_t* e = arr.as<int32_t>();
+  MSP_HIP_TRY(hipMemsetAsync(e, 0, sizeof(int32_t) * 2 * n, s));
+  MSP_HIP_TRY(hipMemsetAsync(err.p, 0, sizeof(int32_t), s));
+  if (spikes) {
+    MSP_HIP_TRY(part.alloc(sizeof(int64_t) * nblocks));
+    MSP_HIP_TRY(hipMemsetAsync(part.p, 0, sizeof(int64_t) * nblocks, s));
+  }
+  if (approx == 1 && m > 0) {
+    MSP_HIP_TRY(remote.alloc(sizeof(uint8_t) * m));
+    act_remote_k<<<grid_for(m, kActBlock), kActBlock, 0, s>>>(n, m, syn_src, syn_tgt, rank,
+                                                              remote.as<uint8_t>());
+    MSP_HIP_TRY(hipGetLastError());
+  }
+  for (int32_t k = 0; k < steps; ++k) {
+    const uint64_t t = t0 + (uint64_t)k;
+    if (m > 0)
+      act_input_k<<<grid_for(m, kActBlock), kActBlock, 0, s>>>(
+          n, m, syn_src, syn_tgt, syn_type, approx == 1 ? remote.as<uint8_t>() : nullptr,
+          approx, seed, t, spiked, freq, e, e + n,
+          err.as<int32_t>());
+    act_neuron_k<<<grid_for(n, kActBlock), kActBlock, 0, s>>>(
+        n, neuron_type, P, seed, t, v, u, calcium, spiked, epoch_count, freq, e, e + n,
+        k == steps - 1 ? last_input : nullptr, spikes ? part.as<int64_t>() : nullptr);
+    MSP_HIP_TRY(hipGetLastError());
+  }
+  if (spikes) {
+    act_spikes_k<<<1, kActBlock, 0, s>>>(part.as<int64_t>(), nblocks, spikes);
+    MSP_HIP_TRY(hipGetLastError());
+  }
+  int32_t bad = 0;
+  MSP_HIP_TRY(hipMemcpyAsync(&bad, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MSP_HIP_TRY(hipStreamSynchronize(s));
+  return bad ? MSP_ERR_INVALID : MSP_OK;
 }
 
 }  // extern "C"
