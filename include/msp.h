@@ -66,7 +66,8 @@ typedef struct msp_octree_s* msp_octree;
  *   out       (host) receives the handle. The library owns every node array.
  * Errors: MSP_ERR_INVALID for n < 1 or n > MSP_MAX_NEURONS, non-finite or non-positive
  * box, leaf_size != 1, null pointers; MSP_ERR_OOM. A non-finite position sets the
- * device error flag. The build synchronises on `s` once to size the node arrays.
+ * device error flag. The build waits on `s` twice (to size the node arrays and the
+ * per-depth lists); its last kernels may still run when it returns.
  */
 msp_status msp_build_octree(const double* pos, int64_t n, const double box_min[3],
                             double box_edge, int32_t leaf_size, hipStream_t s,

@@ -196,6 +196,16 @@ __global__ void __launch_bounds__(kBuildBlock) level_scatter_k(const uint8_t* __
 
 // Per-type records start with count 0 and the node's meta word: an inner node keeps
 // its subtree end and depth, a leaf its neuron id, a bucket leaf its own index.
+// Start of each depth's run in level_nodes: the exclusive prefix of the per-depth
+// counts (one thread; kMaxDepth + 1 values).
+__global__ void level_cursor_k(const int32_t* __restrict__ counts, int32_t* __restrict__ cursor) {
+  int32_t acc = 0;
+  for (int k = 0; k <= kMaxDepth; ++k) {
+    cursor[k] = acc;
+    acc += counts[k];
+  }
+}
+
 __global__ void __launch_bounds__(kBuildBlock) init_meta_k(const int32_t* __restrict__ skip,
                                                           const uint8_t* __restrict__ depth,
                                                           const int32_t* __restrict__ nbeg,

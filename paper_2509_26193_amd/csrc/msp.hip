@@ -272,26 +272,37 @@ msp_status msp_build_octree(const double* pos, int64_t n, const double box_min[3
   carve_neurons(t, static_cast<char*>(t->slab_n), &bytes);
   TRY(hipMemsetAsync(t->err, 0, sizeof(int32_t), s));
   {
-    Temp k1(s), v1(s), cnt(s), base(s), lvl(s), outside(s);
-    TRY(k1.alloc(sizeof(uint64_t) * n));
-    TRY(v1.alloc(sizeof(int32_t) * n));
-    TRY(outside.alloc(sizeof(int32_t)));
-    TRY(hipMemsetAsync(outside.p, 0, sizeof(int32_t), s));
+    // every temporary of the build in one pool block (one allocation, one free)
+    const size_t b_k1 = align_up(sizeof(uint64_t) * n), b_v1 = align_up(sizeof(int32_t) * n),
+                 b_ws = align_up(radix_sort_ws_bytes(n)), b_cnt = align_up(sizeof(int32_t) * n),
+                 b_base = align_up(sizeof(int32_t) * (n + 1)),
+                 b_lvl = align_up(sizeof(int32_t) * 2 * (kMaxDepth + 1)),
+                 b_out = align_up(sizeof(int32_t)), b_scan = align_up(scan_tmp_bytes<int32_t>(n));
+    Temp tmp(s);
+    TRY(tmp.alloc(b_k1 + b_v1 + b_ws + b_cnt + b_base + b_lvl + b_out + b_scan));
+    char* tp = tmp.as<char>();
+    uint64_t* k1 = reinterpret_cast<uint64_t*>(tp);
+    int32_t* v1 = reinterpret_cast<int32_t*>(tp + b_k1);
+    void* sort_ws = tp + b_k1 + b_v1;
+    int32_t* cntp = reinterpret_cast<int32_t*>(tp + b_k1 + b_v1 + b_ws);
+    int32_t* basep = reinterpret_cast<int32_t*>(tp + b_k1 + b_v1 + b_ws + b_cnt);
+    int32_t* lcnt = reinterpret_cast<int32_t*>(tp + b_k1 + b_v1 + b_ws + b_cnt + b_base);
+    int32_t* outside = reinterpret_cast<int32_t*>(tp + b_k1 + b_v1 + b_ws + b_cnt + b_base +
+                                                  b_lvl);
+    void* scan_ws = tp + b_k1 + b_v1 + b_ws + b_cnt + b_base + b_lvl + b_out;
+    TRY(hipMemsetAsync(outside, 0, sizeof(int32_t), s));
     keys_k<<<grid_for(n, kBuildBlock), kBuildBlock, 0, s>>>(pos, n, box_min[0], box_min[1],
                                                             box_min[2], box_edge, t->pos, t->keys,
-                                                            t->order, t->err,
-                                                            outside.as<int32_t>());
+                                                            t->order, t->err, outside);
     TRY(hipGetLastError());
-    TRY(radix_sort_pairs(t->keys, t->order, k1.as<uint64_t>(), v1.as<int32_t>(), n, 63, s));
-    TRY(cnt.alloc(sizeof(int32_t) * n));
-    TRY(base.alloc(sizeof(int32_t) * (n + 1)));
-    node_count_k<<<grid_for(n, kBuildBlock), kBuildBlock, 0, s>>>(t->keys, n, cnt.as<int32_t>());
+    TRY(radix_sort_pairs_ws(t->keys, t->order, k1, v1, n, 63, s, sort_ws));
+    node_count_k<<<grid_for(n, kBuildBlock), kBuildBlock, 0, s>>>(t->keys, n, cntp);
     TRY(hipGetLastError());
-    TRY((exclusive_scan<int32_t, int32_t, Ident<int32_t>>(cnt.as<int32_t>(), base.as<int32_t>(), n,
-                                                          Ident<int32_t>(), true, s)));
+    TRY((exclusive_scan<int32_t, int32_t, Ident<int32_t>>(cntp, basep, n, Ident<int32_t>(), true,
+                                                          s, scan_ws)));
     int32_t N32 = 0, h_outside = 1;
-    TRY(hipMemcpyAsync(&N32, base.as<int32_t>() + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    TRY(hipMemcpyAsync(&h_outside, outside.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    TRY(hipMemcpyAsync(&N32, basep + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    TRY(hipMemcpyAsync(&h_outside, outside, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     TRY(hipStreamSynchronize(s));
     double far = 0.0;
     for (int a = 0; a < 3; ++a)
@@ -308,11 +319,9 @@ msp_status msp_build_octree(const double* pos, int64_t n, const double box_min[3
     carve_nodes(t, static_cast<char*>(t->slab_N), &bytes);
     TRY(hipMemsetAsync(t->rec[0] + N, 0, sizeof(NodeRec), s));
     TRY(hipMemsetAsync(t->rec[1] + N, 0, sizeof(NodeRec), s));
-    TRY(lvl.alloc(sizeof(int32_t) * 2 * (kMaxDepth + 1)));
-    int32_t* lcnt = lvl.as<int32_t>();
     TRY(hipMemsetAsync(lcnt, 0, sizeof(int32_t) * 2 * (kMaxDepth + 1), s));
     nodes_k<<<grid_for(n, kBuildBlock), kBuildBlock, 0, s>>>(t->keys, t->order, n,
-                                                             base.as<int32_t>(), t->skip, t->depth,
+                                                             basep, t->skip, t->depth,
                                                              t->nbeg, t->nend, t->leaf_of);
     TRY(hipGetLastError());
     level_count_k<<<grid_for(N, kBuildBlock * kLevelItems), kBuildBlock, 0, s>>>(t->depth, N, lcnt);
@@ -320,18 +329,14 @@ msp_status msp_build_octree(const double* pos, int64_t n, const double box_min[3
     int32_t hc[kMaxDepth + 1];
     TRY(hipMemcpyAsync(hc, lcnt, sizeof(hc), hipMemcpyDeviceToHost, s));
     TRY(hipStreamSynchronize(s));
-    int32_t hoff[kMaxDepth + 1];
     t->level_off[0] = 0;
-    for (int k = 0; k <= kMaxDepth; ++k) {
-      hoff[k] = (int32_t)t->level_off[k];
-      t->level_off[k + 1] = t->level_off[k] + hc[k];
-    }
+    for (int k = 0; k <= kMaxDepth; ++k) t->level_off[k + 1] = t->level_off[k] + hc[k];
     if (t->level_off[kMaxDepth + 1] != N) {
       release(t);
       return MSP_ERR_HIP;
     }
     int32_t* cursor = lcnt + (kMaxDepth + 1);
-    TRY(hipMemcpyAsync(cursor, hoff, sizeof(hoff), hipMemcpyHostToDevice, s));
+    level_cursor_k<<<1, 1, 0, s>>>(lcnt, cursor);
     level_scatter_k<<<grid_for(N, kBuildBlock * kLevelItems), kBuildBlock, 0, s>>>(
         t->depth, N, cursor, t->level_nodes);
     TRY(hipGetLastError());
@@ -339,8 +344,6 @@ msp_status msp_build_octree(const double* pos, int64_t n, const double box_min[3
                                                                  t->nend, t->order, N, t->rec[0],
                                                                  t->rec[1]);
     TRY(hipGetLastError());
-    // the temporaries are released on `s`; make sure `hoff` (host) was consumed
-    TRY(hipStreamSynchronize(s));
   }
 #undef TRY
   *out = t;
@@ -409,17 +412,20 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
           h.diag.opens0;
   }
   const int64_t hbase[2] = {0, n};
-  Temp dsim(s), dbase(s);
-  MSP_HIP_TRY(dsim.alloc(sizeof(SimDesc)));
-  MSP_HIP_TRY(dbase.alloc(sizeof(hbase)));
   int slots = 0;
   MSP_HIP_TRY(ck_slots_for(t->device, n, 1, &slots));
   WorkspaceLease ws(t->device);
   void* scratch = nullptr;
-  MSP_HIP_TRY(ws.acquire(scratch_sizes(n, 1, slots).total, s, &scratch));
-  MSP_HIP_TRY(hipMemcpyAsync(dsim.p, &h, sizeof(SimDesc), hipMemcpyHostToDevice, s));
-  MSP_HIP_TRY(hipMemcpyAsync(dbase.p, hbase, sizeof(hbase), hipMemcpyHostToDevice, s));
-  SearchScratch S = carve(scratch, n, 1, slots, dsim.as<SimDesc>(), dbase.as<int64_t>());
+  // the workspace also holds the simulation descriptor and the neuron bases
+  const size_t body = scratch_sizes(n, 1, slots).total;
+  MSP_HIP_TRY(ws.acquire(body + align_up(sizeof(SimDesc)) + align_up(sizeof(hbase)), s,
+                         &scratch));
+  SimDesc* dsim = reinterpret_cast<SimDesc*>(static_cast<char*>(scratch) + body);
+  int64_t* dbase = reinterpret_cast<int64_t*>(static_cast<char*>(scratch) + body +
+                                              align_up(sizeof(SimDesc)));
+  MSP_HIP_TRY(hipMemcpyAsync(dsim, &h, sizeof(SimDesc), hipMemcpyHostToDevice, s));
+  MSP_HIP_TRY(hipMemcpyAsync(dbase, hbase, sizeof(hbase), hipMemcpyHostToDevice, s));
+  SearchScratch S = carve(scratch, n, 1, slots, dsim, dbase);
   S.own_cell = own_cell_needed(t, theta);
   if (any) S.W.wave_steps = reinterpret_cast<unsigned long long*>(diag->wave_steps);
   MSP_HIP_TRY(enqueue_prep(S, n, s));
@@ -535,50 +541,61 @@ msp_status msp_commit_synapses_ex(const int32_t* target, const int64_t* elem_off
     return MSP_OK;
   }
   if (!target) return MSP_ERR_INVALID;
-  Temp src_of(s), key(s), prio(s), cnt(s), seg_off(s), seg(s), acc(s), dst(s), err(s);
-  MSP_HIP_TRY(src_of.alloc(sizeof(int32_t) * S));
-  MSP_HIP_TRY(key.alloc(sizeof(int64_t) * S));
-  MSP_HIP_TRY(prio.alloc(sizeof(uint64_t) * S));
-  MSP_HIP_TRY(cnt.alloc(sizeof(int32_t) * 2 * n));
-  MSP_HIP_TRY(seg_off.alloc(sizeof(int32_t) * (2 * n + 1)));
-  MSP_HIP_TRY(seg.alloc(sizeof(int32_t) * S));
-  MSP_HIP_TRY(acc.alloc(sizeof(uint8_t) * S));
-  MSP_HIP_TRY(dst.alloc(sizeof(int64_t) * (S + 1)));
-  MSP_HIP_TRY(err.alloc(sizeof(int32_t)));
-  MSP_HIP_TRY(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * 2 * n, s));
-  MSP_HIP_TRY(hipMemsetAsync(err.p, 0, sizeof(int32_t), s));
-  src_of_k<<<grid_for(n, kCommitBlock), kCommitBlock, 0, s>>>(elem_offset, n, src_of.as<int32_t>());
+  // every temporary of the commit in one pool block (one allocation, one free)
+  const size_t z_src = align_up(sizeof(int32_t) * S), z_key = align_up(sizeof(int64_t) * S),
+               z_prio = align_up(sizeof(uint64_t) * S), z_cnt = align_up(sizeof(int32_t) * 2 * n),
+               z_off = align_up(sizeof(int32_t) * (2 * n + 1)), z_seg = align_up(sizeof(int32_t) * S),
+               z_acc = align_up(sizeof(uint8_t) * S), z_dst = align_up(sizeof(int64_t) * (S + 1)),
+               z_err = align_up(sizeof(int32_t)),
+               z_scan = align_up(std::max(scan_tmp_bytes<int32_t>(2 * n), scan_tmp_bytes<int64_t>(S)));
+  Temp tmp(s);
+  MSP_HIP_TRY(tmp.alloc(z_src + z_key + z_prio + z_cnt + z_off + z_seg + z_acc + z_dst + z_err +
+                        z_scan));
+  char* q = tmp.as<char>();
+  auto take = [&](size_t bytes) {
+    char* r = q;
+    q += bytes;
+    return r;
+  };
+  int32_t* src_of = reinterpret_cast<int32_t*>(take(z_src));
+  int64_t* key = reinterpret_cast<int64_t*>(take(z_key));
+  uint64_t* prio = reinterpret_cast<uint64_t*>(take(z_prio));
+  int32_t* cnt = reinterpret_cast<int32_t*>(take(z_cnt));
+  int32_t* seg_off = reinterpret_cast<int32_t*>(take(z_off));
+  int32_t* seg = reinterpret_cast<int32_t*>(take(z_seg));
+  uint8_t* acc = reinterpret_cast<uint8_t*>(take(z_acc));
+  int64_t* dst = reinterpret_cast<int64_t*>(take(z_dst));
+  int32_t* err = reinterpret_cast<int32_t*>(take(z_err));
+  void* scan_ws = take(z_scan);
+  MSP_HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int32_t) * 2 * n, s));
+  MSP_HIP_TRY(hipMemsetAsync(err, 0, sizeof(int32_t), s));
+  src_of_k<<<grid_for(n, kCommitBlock), kCommitBlock, 0, s>>>(elem_offset, n, src_of);
   req_key_k<<<grid_for(S, kCommitBlock), kCommitBlock, 0, s>>>(
-      target, elem_offset, src_of.as<int32_t>(), neuron_type, S, n, seed, step, key.as<int64_t>(),
-      prio.as<uint64_t>(), cnt.as<int32_t>(), err.as<int32_t>());
+      target, elem_offset, src_of, neuron_type, S, n, seed, step, key, prio, cnt, err);
   MSP_HIP_TRY(hipGetLastError());
-  MSP_HIP_TRY((exclusive_scan<int32_t, int32_t, Ident<int32_t>>(cnt.as<int32_t>(),
-                                                                seg_off.as<int32_t>(), 2 * n,
-                                                                Ident<int32_t>(), true, s)));
+  MSP_HIP_TRY((exclusive_scan<int32_t, int32_t, Ident<int32_t>>(cnt, seg_off, 2 * n,
+                                                                Ident<int32_t>(), true, s,
+                                                                scan_ws)));
   // cursor = copy of the group offsets
-  MSP_HIP_TRY(hipMemcpyAsync(cnt.p, seg_off.p, sizeof(int32_t) * 2 * n, hipMemcpyDeviceToDevice, s));
-  req_scatter_k<<<grid_for(S, kCommitBlock), kCommitBlock, 0, s>>>(key.as<int64_t>(), S,
-                                                                   cnt.as<int32_t>(),
-                                                                   seg.as<int32_t>());
-  req_rank_k<<<grid_for(S, kCommitBlock), kCommitBlock, 0, s>>>(
-      key.as<int64_t>(), prio.as<uint64_t>(), seg_off.as<int32_t>(), seg.as<int32_t>(), S,
-      vac_exc, vac_inh, acc.as<uint8_t>());
+  MSP_HIP_TRY(hipMemcpyAsync(cnt, seg_off, sizeof(int32_t) * 2 * n, hipMemcpyDeviceToDevice, s));
+  req_scatter_k<<<grid_for(S, kCommitBlock), kCommitBlock, 0, s>>>(key, S, cnt, seg);
+  req_rank_k<<<grid_for(S, kCommitBlock), kCommitBlock, 0, s>>>(key, prio, seg_off, seg, S,
+                                                                 vac_exc, vac_inh, acc);
   MSP_HIP_TRY(hipGetLastError());
-  MSP_HIP_TRY((exclusive_scan<int64_t, uint8_t, AccFlag>(acc.as<uint8_t>(), dst.as<int64_t>(), S,
-                                                         AccFlag(), true, s)));
+  MSP_HIP_TRY((exclusive_scan<int64_t, uint8_t, AccFlag>(acc, dst, S, AccFlag(), true, s,
+                                                         scan_ws)));
   int64_t formed = 0;
   int32_t bad = 0;
-  MSP_HIP_TRY(hipMemcpyAsync(&formed, dst.as<int64_t>() + S, sizeof(int64_t),
-                             hipMemcpyDeviceToHost, s));
-  MSP_HIP_TRY(hipMemcpyAsync(&bad, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MSP_HIP_TRY(hipMemcpyAsync(&formed, dst + S, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MSP_HIP_TRY(hipMemcpyAsync(&bad, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   MSP_HIP_TRY(hipStreamSynchronize(s));
   if (bad) return MSP_ERR_INVALID;
   if (formed > syn_capacity) return MSP_ERR_CAPACITY;
   if (formed > 0 && (!syn_src || !syn_tgt || !syn_type)) return MSP_ERR_INVALID;
   commit_write_k<<<grid_for(S, kCommitBlock), kCommitBlock, 0, s>>>(
-      acc.as<uint8_t>(), dst.as<int64_t>(), key.as<int64_t>(), src_of.as<int32_t>(), S, vac_axon,
-      vac_exc, vac_inh, syn_src, syn_tgt, syn_type, accepted_out);
-  copy_scalar_k<<<1, 64, 0, s>>>(dst.as<int64_t>() + S, n_formed);
+      acc, dst, key, src_of, S, vac_axon, vac_exc, vac_inh, syn_src, syn_tgt, syn_type,
+      accepted_out);
+  copy_scalar_k<<<1, 64, 0, s>>>(dst + S, n_formed);
   MSP_HIP_TRY(hipGetLastError());
   return MSP_OK;
 }
@@ -1025,60 +1042,64 @@ msp_status msp_plasticity_step(int64_t n, const msp_plasticity_params* params, u
   int64_t M = m;
   if (m > 0) {
     const SynList L{syn_src, syn_tgt, syn_type};
-    Temp dead(s), k0(s), v0(s), k1(s), v1(s), pos(s), exc(s), o_src(s), o_tgt(s), o_type(s);
-    MSP_HIP_TRY(dead.alloc(sizeof(uint8_t) * m));
-    MSP_HIP_TRY(k0.alloc(sizeof(uint64_t) * m));
-    MSP_HIP_TRY(v0.alloc(sizeof(int32_t) * m));
-    MSP_HIP_TRY(k1.alloc(sizeof(uint64_t) * m));
-    MSP_HIP_TRY(v1.alloc(sizeof(int32_t) * m));
-    MSP_HIP_TRY(pos.alloc(sizeof(int32_t) * (m + 1)));
-    MSP_HIP_TRY(exc.alloc(sizeof(int32_t) * n));
-    MSP_HIP_TRY(hipMemsetAsync(dead.p, 0, sizeof(uint8_t) * m, s));
-    uint8_t* dd = dead.as<uint8_t>();
+    // every temporary of the step in one pool block (one allocation, one free)
+    const size_t z_dead = align_up(sizeof(uint8_t) * m), z_k = align_up(sizeof(uint64_t) * m),
+                 z_v = align_up(sizeof(int32_t) * m), z_pos = align_up(sizeof(int32_t) * (m + 1)),
+                 z_exc = align_up(sizeof(int32_t) * n), z_sort = align_up(radix_sort_ws_bytes(m)),
+                 z_scan = align_up(scan_tmp_bytes<int32_t>(m)),
+                 z_ty = align_up(sizeof(uint8_t) * m);
+    Temp tmp(s);
+    MSP_HIP_TRY(tmp.alloc(z_dead + 2 * z_k + 4 * z_v + z_pos + z_exc + z_sort + z_scan + z_ty));
+    char* q = tmp.as<char>();
+    auto take = [&](size_t bytes) {
+      char* r = q;
+      q += bytes;
+      return r;
+    };
+    uint8_t* dd = reinterpret_cast<uint8_t*>(take(z_dead));
+    uint64_t* k0 = reinterpret_cast<uint64_t*>(take(z_k));
+    uint64_t* k1 = reinterpret_cast<uint64_t*>(take(z_k));
+    int32_t* v0 = reinterpret_cast<int32_t*>(take(z_v));
+    int32_t* v1 = reinterpret_cast<int32_t*>(take(z_v));
+    int32_t* pos = reinterpret_cast<int32_t*>(take(z_pos));
+    int32_t* exc = reinterpret_cast<int32_t*>(take(z_exc));
+    void* sort_ws = take(z_sort);
+    void* scan_ws = take(z_scan);
+    const SynList O{reinterpret_cast<int32_t*>(take(z_v)), reinterpret_cast<int32_t*>(take(z_v)),
+                    reinterpret_cast<uint8_t*>(take(z_ty))};
+    MSP_HIP_TRY(hipMemsetAsync(dd, 0, sizeof(uint8_t) * m, s));
     const int64_t n_del = (int64_t)std::floor(p.delete_fraction * (double)m + 0.5);
     if (n_del > 0) {
-      del_keys_k<<<grid_for(m, kPlastBlock), kPlastBlock, 0, s>>>(k0.as<uint64_t>(),
-                                                                 v0.as<int32_t>(), m, seed, step);
-      MSP_HIP_TRY(radix_sort_pairs(k0.as<uint64_t>(), v0.as<int32_t>(), k1.as<uint64_t>(),
-                                   v1.as<int32_t>(), m, 64, s));
+      del_keys_k<<<grid_for(m, kPlastBlock), kPlastBlock, 0, s>>>(k0, v0, m, seed, step);
+      MSP_HIP_TRY(radix_sort_pairs_ws(k0, v0, k1, v1, m, 64, s, sort_ws));
       drop_first_k<<<grid_for(n_del, kPlastBlock), kPlastBlock, 0, s>>>(
-          v0.as<int32_t>(), n_del < m ? n_del : m, L, n, dd, bound);
+          v0, n_del < m ? n_del : m, L, n, dd, bound);
     }
     int owner_bits = 1;
     while (owner_bits < 31 && ((int64_t)1 << owner_bits) < n) ++owner_bits;
     const int key_bits = (32 + owner_bits + 7) / 8 * 8;
     for (int k = 0; k < 3; ++k) {
-      excess_k<<<grid_for(n, kPlastBlock), kPlastBlock, 0, s>>>(bound + k * n, z + k * n, n,
-                                                               exc.as<int32_t>());
-      const RetractFlag F{L, dd, exc.as<int32_t>(), k};
-      MSP_HIP_TRY((exclusive_scan<int32_t, int32_t, RetractFlag>(nullptr, pos.as<int32_t>(), m, F,
-                                                                true, s)));
+      excess_k<<<grid_for(n, kPlastBlock), kPlastBlock, 0, s>>>(bound + k * n, z + k * n, n, exc);
+      const RetractFlag F{L, dd, exc, k};
+      MSP_HIP_TRY((exclusive_scan<int32_t, int32_t, RetractFlag>(nullptr, pos, m, F, true, s,
+                                                                scan_ws)));
       int32_t C = 0;
-      MSP_HIP_TRY(hipMemcpyAsync(&C, pos.as<int32_t>() + m, sizeof(int32_t),
-                                 hipMemcpyDeviceToHost, s));
+      MSP_HIP_TRY(hipMemcpyAsync(&C, pos + m, sizeof(int32_t), hipMemcpyDeviceToHost, s));
       MSP_HIP_TRY(hipStreamSynchronize(s));
       if (C == 0) continue;
-      cand_write_k<<<grid_for(m, kPlastBlock), kPlastBlock, 0, s>>>(
-          F, pos.as<int32_t>(), m, seed, step, k0.as<uint64_t>(), v0.as<int32_t>());
-      MSP_HIP_TRY(radix_sort_pairs(k0.as<uint64_t>(), v0.as<int32_t>(), k1.as<uint64_t>(),
-                                   v1.as<int32_t>(), C, key_bits, s));
-      retract_k<<<grid_for(C, kPlastBlock), kPlastBlock, 0, s>>>(
-          k0.as<uint64_t>(), v0.as<int32_t>(), C, exc.as<int32_t>(), L, n, dd, bound);
+      cand_write_k<<<grid_for(m, kPlastBlock), kPlastBlock, 0, s>>>(F, pos, m, seed, step, k0, v0);
+      MSP_HIP_TRY(radix_sort_pairs_ws(k0, v0, k1, v1, C, key_bits, s, sort_ws));
+      retract_k<<<grid_for(C, kPlastBlock), kPlastBlock, 0, s>>>(k0, v0, C, exc, L, n, dd, bound);
       MSP_HIP_TRY(hipGetLastError());
     }
-    MSP_HIP_TRY((exclusive_scan<int32_t, int32_t, LiveFlag>(nullptr, pos.as<int32_t>(), m,
-                                                           LiveFlag{dd}, true, s)));
+    MSP_HIP_TRY((exclusive_scan<int32_t, int32_t, LiveFlag>(nullptr, pos, m, LiveFlag{dd}, true, s,
+                                                           scan_ws)));
     int32_t M32 = 0;
-    MSP_HIP_TRY(hipMemcpyAsync(&M32, pos.as<int32_t>() + m, sizeof(int32_t),
-                               hipMemcpyDeviceToHost, s));
+    MSP_HIP_TRY(hipMemcpyAsync(&M32, pos + m, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     MSP_HIP_TRY(hipStreamSynchronize(s));
     M = M32;
     if (M < m) {
-      MSP_HIP_TRY(o_src.alloc(sizeof(int32_t) * (M > 0 ? M : 1)));
-      MSP_HIP_TRY(o_tgt.alloc(sizeof(int32_t) * (M > 0 ? M : 1)));
-      MSP_HIP_TRY(o_type.alloc(sizeof(uint8_t) * (M > 0 ? M : 1)));
-      const SynList O{o_src.as<int32_t>(), o_tgt.as<int32_t>(), o_type.as<uint8_t>()};
-      compact_k<<<grid_for(m, kPlastBlock), kPlastBlock, 0, s>>>(L, dd, pos.as<int32_t>(), m, O);
+      compact_k<<<grid_for(m, kPlastBlock), kPlastBlock, 0, s>>>(L, dd, pos, m, O);
       MSP_HIP_TRY(hipGetLastError());
       if (M > 0) {
         MSP_HIP_TRY(hipMemcpyAsync(syn_src, O.src, sizeof(int32_t) * M, hipMemcpyDeviceToDevice, s));
