@@ -82,7 +82,8 @@ __global__ void __launch_bounds__(kBuildBlock) nodes_k(const uint64_t* __restric
                                                       const int32_t* __restrict__ order, int64_t n,
                                                       const int32_t* __restrict__ base,
                                                       int32_t* skip, uint8_t* depth, int32_t* nbeg,
-                                                      int32_t* nend, int32_t* leaf_of) {
+                                                      int32_t* nend, int32_t* leaf_of,
+                                                      int32_t* leaf_at) {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n) return;
   const int cl = m == 0 ? -1 : common_digits(keys[m - 1], keys[m]);
@@ -122,7 +123,10 @@ __global__ void __launch_bounds__(kBuildBlock) nodes_k(const uint64_t* __restric
     nend[idx] = (int32_t)e;
     const bool leaf = (e - m == 1) || k == kMaxDepth;
     if (leaf)
-      for (int64_t p = m; p < e; ++p) leaf_of[order[p]] = (int32_t)idx;
+      for (int64_t p = m; p < e; ++p) {
+        leaf_of[order[p]] = (int32_t)idx;
+        leaf_at[p] = (int32_t)idx;
+      }
   }
 }
 
@@ -143,9 +147,16 @@ __device__ __forceinline__ uint64_t same_depth_lanes(int d) {
 // (one per depth) do not queue up on the few hot depth counters.
 constexpr int kLevelItems = 16;
 
-// Nodes per depth: one LDS atomic per distinct depth and wave, one global atomic per
-// depth and block of kBuildBlock * kLevelItems nodes.
+// Inner nodes per depth (leaves are refreshed in sorted order, not by depth): one LDS
+// atomic per distinct depth and wave, one global atomic per depth and block of
+// kBuildBlock * kLevelItems nodes. A leaf is a node whose subtree ends right after it.
+__device__ __forceinline__ int inner_depth(const uint8_t* depth, const int32_t* skip, int64_t x,
+                                           int64_t N) {
+  return (x < N && skip[x] != (int32_t)(x + 1)) ? (int)depth[x] : -1;
+}
+
 __global__ void __launch_bounds__(kBuildBlock) level_count_k(const uint8_t* __restrict__ depth,
+                                                            const int32_t* __restrict__ skip,
                                                             int64_t N, int32_t* level_cnt) {
   __shared__ int32_t c[kMaxDepth + 1];
   if (threadIdx.x <= kMaxDepth) c[threadIdx.x] = 0;
@@ -154,7 +165,7 @@ __global__ void __launch_bounds__(kBuildBlock) level_count_k(const uint8_t* __re
   const int64_t base = (int64_t)blockIdx.x * kBuildBlock * kLevelItems + threadIdx.x;
   for (int k = 0; k < kLevelItems; ++k) {
     const int64_t x = base + (int64_t)k * kBuildBlock;
-    const int d = x < N ? (int)depth[x] : -1;
+    const int d = inner_depth(depth, skip, x, N);
     const uint64_t peers = same_depth_lanes(d);
     if (d >= 0 && lane == __ffsll((unsigned long long)peers) - 1) atomicAdd(&c[d], __popcll(peers));
   }
@@ -162,9 +173,10 @@ __global__ void __launch_bounds__(kBuildBlock) level_count_k(const uint8_t* __re
   if (threadIdx.x <= kMaxDepth && c[threadIdx.x]) atomicAdd(&level_cnt[threadIdx.x], c[threadIdx.x]);
 }
 
-// Group node ids by depth (order within a depth is arbitrary: the refresh of one
+// Group inner node ids by depth (order within a depth is arbitrary: the refresh of one
 // depth treats its nodes independently). Same blocking as level_count_k.
 __global__ void __launch_bounds__(kBuildBlock) level_scatter_k(const uint8_t* __restrict__ depth,
+                                                              const int32_t* __restrict__ skip,
                                                               int64_t N, int32_t* cursor,
                                                               int32_t* level_nodes) {
   __shared__ int32_t c[kMaxDepth + 1];
@@ -178,7 +190,7 @@ __global__ void __launch_bounds__(kBuildBlock) level_scatter_k(const uint8_t* __
 #pragma unroll
   for (int k = 0; k < kLevelItems; ++k) {
     const int64_t x = base + (int64_t)k * kBuildBlock;
-    d[k] = x < N ? (int)depth[x] : -1;
+    d[k] = inner_depth(depth, skip, x, N);
     const uint64_t peers = same_depth_lanes(d[k]);
     const int leader = __ffsll((unsigned long long)peers) - 1;
     int r0 = 0;
@@ -194,8 +206,6 @@ __global__ void __launch_bounds__(kBuildBlock) level_scatter_k(const uint8_t* __
     if (d[k] >= 0) level_nodes[base_d[d[k]] + r[k]] = (int32_t)(base + (int64_t)k * kBuildBlock);
 }
 
-// Per-type records start with count 0 and the node's meta word: an inner node keeps
-// its subtree end and depth, a leaf its neuron id, a bucket leaf its own index.
 // Start of each depth's run in level_nodes: the exclusive prefix of the per-depth
 // counts (one thread; kMaxDepth + 1 values).
 __global__ void level_cursor_k(const int32_t* __restrict__ counts, int32_t* __restrict__ cursor) {
@@ -206,6 +216,8 @@ __global__ void level_cursor_k(const int32_t* __restrict__ counts, int32_t* __re
   }
 }
 
+// Per-type records start with count 0 and the node's meta word: an inner node keeps
+// its subtree end and depth, a leaf its neuron id, a bucket leaf its own index.
 __global__ void __launch_bounds__(kBuildBlock) init_meta_k(const int32_t* __restrict__ skip,
                                                           const uint8_t* __restrict__ depth,
                                                           const int32_t* __restrict__ nbeg,

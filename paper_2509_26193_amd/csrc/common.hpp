@@ -59,13 +59,14 @@ struct msp_octree_s {
   uint64_t* keys;        // [n] sorted Morton keys
   int32_t* order;        // [n] ids in (key, id) order
   int32_t* leaf_of;      // [n] by id: leaf node holding the neuron
+  int32_t* leaf_at;      // [n] by sorted position: leaf node holding it
   // topology (device), nodes in depth-first pre-order
   int32_t* skip;         // [N] subtree end
   uint8_t* depth;        // [N]
   int32_t* nbeg;         // [N] range in `order`
   int32_t* nend;         // [N]
-  int32_t* level_nodes;  // [N] node ids grouped by depth
-  int64_t level_off[msp::kMaxDepth + 2];
+  int32_t* level_nodes;  // [N] inner node ids grouped by depth
+  int64_t level_off[msp::kMaxDepth + 2];   // runs of level_nodes (inner nodes only)
   msp::NodeRec* rec[2];  // [N + 1] per type (index N: zero sentinel, never visited)
   int32_t* vs[2];        // [n] per type: counts in sorted order (bucket members)
   int32_t* err;          // [1] sticky device error flags

@@ -41,6 +41,7 @@ void carve_neurons(msp_octree_s* t, char* base, size_t* bytes) {
   t->keys = c.take<uint64_t>(n);
   t->order = c.take<int32_t>(n);
   t->leaf_of = c.take<int32_t>(n);
+  t->leaf_at = c.take<int32_t>(n);
   t->vs[0] = c.take<int32_t>(n);
   t->vs[1] = c.take<int32_t>(n);
   t->err = c.take<int32_t>(1);
@@ -322,23 +323,26 @@ msp_status msp_build_octree(const double* pos, int64_t n, const double box_min[3
     TRY(hipMemsetAsync(lcnt, 0, sizeof(int32_t) * 2 * (kMaxDepth + 1), s));
     nodes_k<<<grid_for(n, kBuildBlock), kBuildBlock, 0, s>>>(t->keys, t->order, n,
                                                              basep, t->skip, t->depth,
-                                                             t->nbeg, t->nend, t->leaf_of);
+                                                             t->nbeg, t->nend, t->leaf_of,
+                                                             t->leaf_at);
     TRY(hipGetLastError());
-    level_count_k<<<grid_for(N, kBuildBlock * kLevelItems), kBuildBlock, 0, s>>>(t->depth, N, lcnt);
+    TRY(hipGetLastError());
+    level_count_k<<<grid_for(N, kBuildBlock * kLevelItems), kBuildBlock, 0, s>>>(t->depth, t->skip,
+                                                                                N, lcnt);
     TRY(hipGetLastError());
     int32_t hc[kMaxDepth + 1];
     TRY(hipMemcpyAsync(hc, lcnt, sizeof(hc), hipMemcpyDeviceToHost, s));
     TRY(hipStreamSynchronize(s));
     t->level_off[0] = 0;
     for (int k = 0; k <= kMaxDepth; ++k) t->level_off[k + 1] = t->level_off[k] + hc[k];
-    if (t->level_off[kMaxDepth + 1] != N) {
+    if (t->level_off[kMaxDepth + 1] > N) {
       release(t);
       return MSP_ERR_HIP;
     }
     int32_t* cursor = lcnt + (kMaxDepth + 1);
     level_cursor_k<<<1, 1, 0, s>>>(lcnt, cursor);
     level_scatter_k<<<grid_for(N, kBuildBlock * kLevelItems), kBuildBlock, 0, s>>>(
-        t->depth, N, cursor, t->level_nodes);
+        t->depth, t->skip, N, cursor, t->level_nodes);
     TRY(hipGetLastError());
     init_meta_k<<<grid_for(N, kBuildBlock), kBuildBlock, 0, s>>>(t->skip, t->depth, t->nbeg,
                                                                  t->nend, t->order, N, t->rec[0],
@@ -377,12 +381,15 @@ msp_status msp_last_device_error(msp_octree t) {
 msp_status msp_update_vacant_counts(msp_octree t, const int32_t* vac_dend_exc,
                                     const int32_t* vac_dend_inh, hipStream_t s) {
   if (!handle_ok(t) || !vac_dend_exc || !vac_dend_inh) return MSP_ERR_INVALID;
+  refresh_leaves_k<<<grid_for(t->n, kRefreshBlock), kRefreshBlock, 0, s>>>(
+      t->n, t->rec[0], t->rec[1], t->leaf_at, t->nbeg, t->nend, t->order, t->pos, vac_dend_exc,
+      vac_dend_inh, t->vs[0], t->vs[1], t->err);
+  MSP_HIP_TRY(hipGetLastError());
   for (int k = kMaxDepth; k >= 0; --k) {
     const int64_t cnt = t->level_off[k + 1] - t->level_off[k];
     if (cnt == 0) continue;
     refresh_level_k<<<grid_for(cnt, kRefreshBlock), kRefreshBlock, 0, s>>>(
-        t->level_nodes + t->level_off[k], cnt, t->rec[0], t->rec[1], t->nbeg, t->nend, t->order,
-        t->pos, vac_dend_exc, vac_dend_inh, t->vs[0], t->vs[1], t->err);
+        t->level_nodes + t->level_off[k], cnt, t->rec[0], t->rec[1], t->err);
     MSP_HIP_TRY(hipGetLastError());
   }
   t->refreshed = true;
