@@ -158,24 +158,50 @@ __global__ void __launch_bounds__(kSortBlock) rs_hist_k(const uint64_t* keys, in
   hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
+// One tile of kSortTile items: ranked by digit (stable) into LDS first, then written
+// out digit run by digit run, so consecutive threads store to consecutive addresses.
+// The tile's count of each digit is the difference of consecutive entries of the
+// scanned (digit-major) histogram.
 __global__ void __launch_bounds__(kSortBlock) rs_scatter_k(const uint64_t* kin, const int32_t* vin,
                                                           uint64_t* kout, int32_t* vout, int64_t n,
                                                           int shift, const uint32_t* off, int nb) {
-  __shared__ uint32_t run[256];
+  __shared__ uint64_t lk[kSortTile];
+  __shared__ int32_t lv[kSortTile];
+  __shared__ uint32_t lstart[256];      // tile-local start of each digit's run
+  __shared__ uint32_t gstart[256];      // global start of this tile's run of each digit
+  __shared__ uint32_t run[256];         // items of each digit placed so far
   __shared__ uint32_t wcnt[kSortBlock / kWave][256];
   const int t = threadIdx.x;
   const int w = t / kWave;
   const int lane = t & (kWave - 1);
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (kWave - lane));
-  run[t] = off[(int64_t)t * nb + blockIdx.x];
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const int64_t rem = n - base;
+  const int tile_n = rem < kSortTile ? (int)rem : kSortTile;
+  const int64_t h = (int64_t)t * nb + blockIdx.x;
+  const uint32_t g0 = off[h];
+  const uint32_t g1 = h + 1 < 256 * (int64_t)nb ? off[h + 1] : (uint32_t)n;
+  const uint32_t count = g1 - g0;       // this tile's items of digit t
+  gstart[t] = g0;
+  lstart[t] = count;
+  run[t] = 0;
+  __syncthreads();
+  // inclusive scan of the 256 counts (Hillis-Steele), then exclusive = inclusive - own
+  for (int d = 1; d < 256; d <<= 1) {
+    const uint32_t v = t >= d ? lstart[t - d] : 0u;
+    __syncthreads();
+    lstart[t] += v;
+    __syncthreads();
+  }
+  lstart[t] -= count;
+  __syncthreads();
   for (int c = 0; c < kSortItems; ++c) {
 #pragma unroll
     for (int k = 0; k < kSortBlock / kWave; ++k) wcnt[k][t] = 0;
     __syncthreads();
-    const int64_t idx = base + (int64_t)c * kSortBlock + t;
-    const bool valid = idx < n;
-    const uint64_t key = valid ? kin[idx] : 0ull;
+    const int li = c * kSortBlock + t;
+    const bool valid = li < tile_n;
+    const uint64_t key = valid ? kin[base + li] : 0ull;
     const uint32_t d = (uint32_t)(key >> shift) & 255u;
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -188,16 +214,28 @@ __global__ void __launch_bounds__(kSortBlock) rs_scatter_k(const uint64_t* kin, 
     if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
     __syncthreads();
     if (valid) {
-      uint32_t p = run[d] + rank;
+      uint32_t p = lstart[d] + run[d] + rank;
       for (int k = 0; k < w; ++k) p += wcnt[k][d];
-      kout[p] = key;
-      vout[p] = vin[idx];
+      if (p < (uint32_t)kSortTile) {
+        lk[p] = key;
+        lv[p] = vin[base + li];
+      }
     }
     __syncthreads();
     uint32_t add = 0;
 #pragma unroll
     for (int k = 0; k < kSortBlock / kWave; ++k) add += wcnt[k][t];
     run[t] += add;
+  }
+  __syncthreads();
+  for (int i = t; i < tile_n; i += kSortBlock) {
+    const uint64_t key = lk[i];
+    const uint32_t d = (uint32_t)(key >> shift) & 255u;
+    const uint32_t g = gstart[d] + ((uint32_t)i - lstart[d]);
+    if ((int64_t)g < n) {
+      kout[g] = key;
+      vout[g] = lv[i];
+    }
   }
 }
 
