@@ -35,3 +35,26 @@ def test_invalid_handles_rejected_without_device():
     assert L.msp_build_octree(ctypes.c_void_p(8), 10, bm, 1.0, 2, None, ctypes.byref(h)) == _lib.MSP_ERR_INVALID
     assert L.msp_build_octree(ctypes.c_void_p(8), 10, bm, -1.0, 1, None, ctypes.byref(h)) == _lib.MSP_ERR_INVALID
     assert L.msp_build_octree(ctypes.c_void_p(8), 10, bm, float("nan"), 1, None, ctypes.byref(h)) == _lib.MSP_ERR_INVALID
+
+
+def test_activity_arguments_rejected_without_device():
+    L = msp.lib()
+    P = _lib.ActivityParams(*[_lib.ACTIVITY[f] for f, _ in _lib.ActivityParams._fields_])
+    p8 = ctypes.c_void_p(8)
+    args = [p8, None, 0, None, None, None, 0, ctypes.byref(P), 1, 0, 1, p8, p8, p8, p8, p8, p8,
+            None, None, None]
+    assert L.msp_activity_run(0, *args) == _lib.MSP_ERR_INVALID          # n < 1
+    bad = list(args)
+    bad[6] = 3                                                          # approx outside 0..2
+    assert L.msp_activity_run(10, *bad) == _lib.MSP_ERR_INVALID
+    bad = list(args)
+    bad[6] = 1                                                          # approx 1 needs ranks
+    assert L.msp_activity_run(10, *bad) == _lib.MSP_ERR_INVALID
+    Q = _lib.ActivityParams(*[_lib.ACTIVITY[f] for f, _ in _lib.ActivityParams._fields_])
+    Q.epoch = 0
+    bad = list(args)
+    bad[7] = ctypes.byref(Q)                                            # epoch < 1
+    assert L.msp_activity_run(10, *bad) == _lib.MSP_ERR_INVALID
+    bad = list(args)
+    bad[11] = None                                                      # no v
+    assert L.msp_activity_run(10, *bad) == _lib.MSP_ERR_INVALID
