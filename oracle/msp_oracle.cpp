@@ -242,11 +242,13 @@ struct Geometry {        // what the acceptance decisions and the weights read
   const std::vector<double>* cen;       // node centroids of the searched type
 };
 
+// Squared distance: dx^2 + dy^2 + dz^2 with the last two terms fused (one rounding
+// each for dx^2, dy^2 + that, dz^2 + that).
 double dist2(const double* a, const double* b) {
   double dx = a[0] - b[0];
   double dy = a[1] - b[1];
   double dz = a[2] - b[2];
-  return dx * dx + dy * dy + dz * dz;
+  return std::fma(dz, dz, std::fma(dy, dy, dx * dx));
 }
 
 double kernel_weight(int64_t v, double d2, double sigma) {
@@ -592,7 +594,7 @@ int oracle_attraction(const OracleTree* t, const uint8_t* neuron_type, const int
     for (const Entry& e : list) {
       const double* c = e.neuron ? &t->pos[3 * e.id] : &t->cen[ty][3 * e.id];
       double diff[3] = {xi[0] - c[0], xi[1] - c[1], xi[2] - c[2]};
-      double d2 = diff[0] * diff[0] + diff[1] * diff[1] + diff[2] * diff[2];
+      double d2 = dist2(xi, c);
       double f = e.w / Z[i];
       for (int a = 0; a < 3; ++a) {
         double gi = f * (-2.0 * diff[a] / s2);

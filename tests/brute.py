@@ -9,8 +9,19 @@ and the exact implied target distribution are written from the paper's descripti
 from __future__ import annotations
 
 import math
+from fractions import Fraction
 
 import numpy as np
+
+
+def fma(a: float, b: float, c: float) -> float:
+    """a * b + c rounded once (exact rational arithmetic, then one rounding)."""
+    return float(Fraction(a) * Fraction(b) + Fraction(c))
+
+
+def sqdist(dx: float, dy: float, dz: float) -> float:
+    """dx^2 + dy^2 + dz^2 with the last two terms fused, as the method's reading fixes."""
+    return fma(dz, dz, fma(dy, dy, dx * dx))
 
 DEPTH = 21
 CELLS = 2097152.0  # 2^21
@@ -156,7 +167,7 @@ class InsertTree:
             dx = xi[0] - c[0]
             dy = xi[1] - c[1]
             dz = xi[2] - c[2]
-            d2 = dx * dx + dy * dy + dz * dz
+            d2 = sqdist(dx, dy, dz)
             return float(v) * math.exp(-(d2 / (sigma * sigma))), d2
 
         def leaf_members(c):
@@ -256,7 +267,7 @@ def brute_theta0(pos, order, vac, i, j, sigma, seed, step):
         dx = float(xi[0]) - float(pos[g][0])
         dy = float(xi[1]) - float(pos[g][1])
         dz = float(xi[2]) - float(pos[g][2])
-        d2 = dx * dx + dy * dy + dz * dz
+        d2 = sqdist(dx, dy, dz)
         ws.append(float(vac[g]) * math.exp(-(d2 / (sigma * sigma))))
         ids.append(g)
     Z = 0.0
