@@ -13,7 +13,8 @@ LIB = os.path.join(HERE, "libmsp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -ffp-contract=off: every product and sum is rounded on its own, which keeps the
-# float64 centroids and acceptance tests identical to a plain IEEE evaluation.
+# float64 centroids and acceptance tests identical to a plain IEEE evaluation (the
+# squared distance is written with explicit fused multiply-adds, as the oracle's is).
 # -packed-fp32-ops: no packed fp32 instructions are generated.
 # -structurizecfg-skip-uniform-regions: branches on wave-uniform values (the node
 # kind and count in the search walks) stay plain scalar branches instead of being

@@ -112,7 +112,7 @@ __device__ void attract_tile(const SearchArgs& A, const AttractArgs& O, int tile
     fx = fy = fz = 0.0;
     if (!on) return;
     const double dx = xi - cx, dy = yi - cy, dz = zi - cz;
-    const double d2 = dx * dx + dy * dy + dz * dz;
+    const double d2 = dist2(xi, yi, zi, cx, cy, cz);
     const double w = kernel_weight(v, d2, A.k2);
     const double f = g * w * O.two_over_s2;
     fx = f * dx;

@@ -116,7 +116,7 @@ __device__ __forceinline__ double dist2(double ax, double ay, double az, double 
   const double dx = ax - bx;
   const double dy = ay - by;
   const double dz = az - bz;
-  return dx * dx + dy * dy + dz * dz;
+  return __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));   // two fused steps
 }
 
 // Members of a leaf node x (record r) other than the source, with their counts.
