@@ -15,13 +15,20 @@
  *   4. msp_commit_synapses     -- each neuron accepts as many requests as it has
  *                                 vacant dendritic elements, at random; the rest are
  *                                 declined (Sec. III-A, "Update of synapses").
+ * Around it: the batched search of many simulations (msp_batch_*), the expected
+ * attraction and its adjoint (msp_attraction_*), the change of the network between
+ * updates (msp_plasticity_*), the two-phase search of Sec. IV-A (branch_level of
+ * msp_find_targets_diag) and the electrical activity with the firing-rate
+ * approximation of Sec. IV-B (msp_activity_run).
  *
  * Conventions for every entry point:
  *   - Array arguments are DEVICE pointers owned by the caller unless marked (host).
  *     The caller keeps them alive until the work queued on the stream has finished.
  *   - Work is queued on the given stream `s` (0 = the default stream). Calls that
- *     must size an output (find_targets, commit) read one scalar back to the host
- *     and therefore synchronise on `s`; every other call is asynchronous.
+ *     must size something or report an error found on the device (build,
+ *     find_targets, commit, the plasticity step, the activity run) read values back
+ *     to the host and therefore wait on `s`, as each one states; the others are
+ *     asynchronous.
  *   - Every call returns an msp_status and never throws. Arguments are validated
  *     before anything is queued; on an error nothing is written.
  *   - Data-dependent errors found on the device (a non-finite position, a negative
