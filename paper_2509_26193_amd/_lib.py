@@ -256,6 +256,9 @@ def find_targets(tree: Octree, neuron_type: torch.Tensor, vac_axon: torch.Tensor
     st = _stream(stream)
     ms = (ctypes.c_float * 3)(0.0, 0.0, 0.0)
     extra = {}
+    if target_out is None:                  # size the output once instead of retrying
+        S0 = int(torch.clamp(vac_axon, min=0).sum().item())
+        target_out = torch.empty(max(S0, 1), dtype=torch.int32, device=dev)
     for attempt in range(2):
         cap = 0 if target_out is None else target_out.numel()
         d = SearchDiag()

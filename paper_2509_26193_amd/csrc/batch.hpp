@@ -223,8 +223,12 @@ __global__ void b_check_k(BatchDev B, int64_t total) {
     const bool inv = __ballot((f & kSimInvalid) != 0) != 0;
     const bool cap = __ballot((f & kSimCapacity) != 0) != 0;
     const int first = __ffsll((unsigned long long)__ballot(1)) - 1;
-    if ((inv || cap) && (int)(threadIdx.x & (kWave - 1)) == first)
-      atomicOr(&B.status[s0], (inv ? kSimInvalid : 0) | (cap ? kSimCapacity : 0));
+    const int32_t want = (inv ? kSimInvalid : 0) | (cap ? kSimCapacity : 0);
+    // most waves of a failing simulation find the flags already set: no atomic then
+    if (want && (int)(threadIdx.x & (kWave - 1)) == first &&
+        (__hip_atomic_load(&B.status[s0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & want) !=
+            want)
+      atomicOr(&B.status[s0], want);
   } else if (f) {
     atomicOr(&B.status[s], f);
   }
