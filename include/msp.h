@@ -106,7 +106,11 @@ msp_status msp_update_vacant_counts(msp_octree t, const int32_t* vac_dend_exc,
  *             or -1 if no neuron with a vacancy of the right type has nonzero weight.
  *   elem_offset_out [n+1] int64: exclusive prefix sum of vac_axon (CSR by source).
  * Every search reads the octree as refreshed last (all requests are formed before
- * any is answered). Errors: MSP_ERR_CAPACITY if S = sum(vac_axon) > capacity_S:
+ * any is answered). The level-0 normaliser Z of a source (Sec. III-A) is added up in
+ * float64 in the walk's depth-first order; a call with few sources (under 2^21) cuts
+ * the walk into up to 8 consecutive pre-order ranges, searched in parallel, whose sums
+ * are then added in order, so Z's last bits depend on the cut (the draw follows the
+ * same sums). Errors: MSP_ERR_CAPACITY if S = sum(vac_axon) > capacity_S:
  * then only elem_offset_out is written (elem_offset_out[n] = S sizes the buffer);
  * MSP_ERR_INVALID for sigma <= 0, theta < 0, a negative vac_axon or a type > 1
  * (the last two found on the device before the search: target_out is not written).
@@ -149,6 +153,10 @@ msp_status msp_find_targets(msp_octree t, const uint8_t* neuron_type, const int3
  *           0: the library's default (one phase); above 21 or negative: one phase.
  *           The second phase needs about 40 B per search of working memory.
  *   phase2_requests (device int64 scalar): set to the number of second-phase requests.
+ *   parts_per_tile: 0 (the default): the library's choice; 1, 2, 4 or 8: every tile's
+ *           level-0 walk is cut into this many parts (see msp_find_targets); other
+ *           values are MSP_ERR_INVALID. Visits and opens do not depend on it; z0 does
+ *           in its last bits only.
  */
 typedef struct msp_search_diag {
   double* z0;
@@ -161,6 +169,7 @@ typedef struct msp_search_diag {
   int64_t* wave_steps;
   int32_t branch_level;
   int64_t* phase2_requests;
+  int32_t parts_per_tile;
 } msp_search_diag;
 
 /* msp_find_targets with diagnostics (diag may be null). */

@@ -41,7 +41,7 @@ class SearchDiag(ctypes.Structure):
     _fields_ = [("z0", _vp), ("levels", _vp), ("visits", _vp), ("opens", _vp),
                 ("visits0", _vp), ("opens0", _vp), ("kernel_ms", ctypes.POINTER(ctypes.c_float)),
                 ("wave_steps", _vp), ("branch_level", ctypes.c_int32),
-                ("phase2_requests", _vp)]
+                ("phase2_requests", _vp), ("parts_per_tile", ctypes.c_int32)]
 
 
 class SimSpec(ctypes.Structure):
@@ -236,7 +236,7 @@ def find_targets(tree: Octree, neuron_type: torch.Tensor, vac_axon: torch.Tensor
                  theta: float, seed: int, step: int, target_out: torch.Tensor | None = None,
                  elem_offset_out: torch.Tensor | None = None, diag: bool = False,
                  counters: bool = False, timing: dict | None = None, stream=None,
-                 branch_level: int = 0, phase2: dict | None = None):
+                 branch_level: int = 0, phase2: dict | None = None, parts: int = 0):
     """Returns (target[S], elem_offset[n+1]); with diag also (z0[S], levels[S]); with
     counters also a dict of visits/opens/visits0/opens0 [S]. target_out may be a
     preallocated int32 buffer of any capacity >= S. If `timing` is a dict, the kernel
@@ -245,7 +245,8 @@ def find_targets(tree: Octree, neuron_type: torch.Tensor, vac_axon: torch.Tensor
     and "kernel_ms" (all). branch_level selects the two-phase search (restarts from
     cells at that depth or deeper run in a second pass, in cell order; 0: the library's
     default); if `phase2` is a dict, phase2["requests"] is set to the number of
-    second-phase requests."""
+    second-phase requests. parts: the level-0 walk of every tile in 1, 2, 4 or 8
+    pre-order parts (0: the library's choice)."""
     n = tree.n
     dev = tree.device
     ty = _dev(neuron_type, torch.uint8, "neuron_type", n)
@@ -272,6 +273,7 @@ def find_targets(tree: Octree, neuron_type: torch.Tensor, vac_axon: torch.Tensor
         for k, v in extra.items():
             setattr(d, k, v.data_ptr())
         d.branch_level = int(branch_level)
+        d.parts_per_tile = int(parts)
         if phase2 is not None:
             nreq = torch.zeros(1, dtype=torch.int64, device=dev)
             d.phase2_requests = nreq.data_ptr()

@@ -204,13 +204,21 @@ __global__ void __launch_bounds__(256) attract_bwd_k(BatchDev B, AttractArgs O) 
   attract_tile(A, O, (int)tile, lane);
 }
 
-// Z of every source from the sweep's per-slot sums (float32); other neurons keep 0.
-__global__ void z_scatter_k(const int32_t* __restrict__ work, const double* __restrict__ Zs,
-                            const int32_t* tile_count, float* __restrict__ Z) {
+// Z of every source from the sweep's part sums (added in part order, then rounded to
+// float32); other neurons keep 0.
+__global__ void z_scatter_k(BatchDev B, SweepOut W, float* __restrict__ Z) {
   const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= (int64_t)*tile_count * kWave) return;
-  const int32_t i = work[slot];
-  if (i >= 0) Z[i] = (float)Zs[slot];
+  const int64_t tile = slot / kWave;
+  if (tile >= *W.tile_count) return;
+  const int32_t i = B.work[slot];
+  if (i < 0) return;
+  const int sim = find_sim(B.tile_base, B.nsims, tile);
+  const int plog = B.plog[sim];
+  const int64_t u0 = (int64_t)B.unit_base[sim] + ((tile - (int64_t)B.tile_base[sim]) << plog);
+  const int64_t lane = slot % kWave;
+  double z = 0.0;
+  for (int q = 0; q < (1 << plog); ++q) z = z + W.Z[(u0 + q) * kWave + lane];
+  Z[i] = (float)z;
 }
 
 // G = sum of the per-die copies, in die order.

@@ -53,6 +53,8 @@ struct BatchDev {
   int32_t* p1;                  // [total + 1] flat scan: inhibitory sources, Morton order
   uint8_t* src_type;            // [total] type of the source at flat position g, 2: none
   int32_t* tile_base;           // [nsims + 1]
+  int32_t* unit_base;           // [nsims + 1] sweep units (a tile's parts) before each
+  uint8_t* plog;                // [nsims] log2 of the parts per tile
   int32_t* status;              // [nsims]
   int32_t* work;                // [max_slots] source id per slot, -1 = padding
   int64_t max_slots;
@@ -95,20 +97,22 @@ __device__ __forceinline__ SearchArgs args_of(const SimDesc* sims, int s, const 
   return A;
 }
 
-// Persistent waves pull 64-source tiles: first from the Morton range of their own
-// die (neighbouring sources share upper-tree nodes in that die's L2), then from the
-// other dies' ranges. A tile's simulation is found from the tile bases.
+// Persistent waves pull units (parts of 64-source tiles, in tile order): first from
+// the Morton range of their own die (neighbouring sources share upper-tree nodes in
+// that die's L2), then from the other dies' ranges. A unit's simulation is found from
+// the unit bases.
 template <bool DIAG, int SLOTS, bool OWN>
 __global__ void __launch_bounds__(kWaveBlock) search_sweep_k(BatchDev B, SweepOut W) {
   const int lane = threadIdx.x & (kWave - 1);
   const int home = blockIdx.x % kXcd;
-  const int ntiles = *W.tile_count;
+  const int nunits = *W.unit_count;
+  const bool own = nunits <= W.ck_units;
   int q = 0;
-  int step0 = 2 * kCkptStepMin;
+  int prev = 0;                          // wave steps of this wave's previous unit
   while (q < kXcd) {
     const int qq = (home + q) % kXcd;
-    const int lo = (int)((int64_t)ntiles * qq / kXcd);
-    const int hi = (int)((int64_t)ntiles * (qq + 1) / kXcd);
+    const int lo = (int)((int64_t)nunits * qq / kXcd);
+    const int hi = (int)((int64_t)nunits * (qq + 1) / kXcd);
     int got = 0;
     if (lane == 0) got = atomicAdd(&W.queue[qq], 1);
     got = __shfl(got, 0, kWave);
@@ -116,16 +120,24 @@ __global__ void __launch_bounds__(kWaveBlock) search_sweep_k(BatchDev B, SweepOu
       ++q;
       continue;
     }
-    const int tile = lo + got;
+    const int unit = lo + got;
     const int sim = __builtin_amdgcn_readfirstlane(
-        find_sim(as_const(B.tile_base), B.nsims, (int64_t)tile));
+        find_sim(as_const(B.unit_base), B.nsims, (int64_t)unit));
+    const int plog = __builtin_amdgcn_readfirstlane((int)as_const(B.plog)[sim]);
+    const int local = unit - as_const(B.unit_base)[sim];
+    const int tile = as_const(B.tile_base)[sim] + (local >> plog);
+    const int part = local & ((1 << plog) - 1);
     const SearchArgs A = args_of(B.sims, sim, B.work);
-    const int steps = sweep_tile<DIAG, SLOTS, OWN>(A, W, tile, lane, step0);
-    if constexpr (SLOTS > 0) {
-      // next interval: about SLOTS checkpoints over a sweep as long as this one
+    // checkpoint interval: about as many checkpoints as the part has slots over a
+    // walk as long as the previous one
+    int step0 = 2 * kCkptStepMin;
+    if (SLOTS > 0 && prev > 0) {
+      // as many checkpoints per tile as without parts: a unit with a region of its
+      // own keeps the rest of its slots as headroom (no thinning in long parts)
       step0 = kCkptStepMin;
-      while (step0 * SLOTS < steps) step0 <<= 1;
+      while (step0 * (SLOTS >> plog) < prev) step0 <<= 1;
     }
+    prev = sweep_tile<DIAG, SLOTS, OWN>(A, W, tile, part, plog, unit, own, lane, step0);
   }
 }
 
@@ -138,6 +150,9 @@ __global__ void __launch_bounds__(256) search_draw_k(BatchDev B, SweepOut W) {
   if (tile >= *W.tile_count) return;
   const int sim = __builtin_amdgcn_readfirstlane(find_sim(as_const(B.tile_base), B.nsims, tile));
   const SearchArgs A = args_of(B.sims, sim, B.work);
+  const int plog = __builtin_amdgcn_readfirstlane((int)as_const(B.plog)[sim]);
+  const int64_t u0 = (int64_t)as_const(B.unit_base)[sim] +
+                     ((tile - (int64_t)as_const(B.tile_base)[sim]) << plog);
   DiagOut D{};
   if (DIAG) {
     const cptr<SimDesc> d = as_const(B.sims) + sim;
@@ -148,7 +163,7 @@ __global__ void __launch_bounds__(256) search_draw_k(BatchDev B, SweepOut W) {
     D.visits0 = d->diag.visits0;
     D.opens0 = d->diag.opens0;
   }
-  draw_slot<DIAG, SLOTS, DEFER>(A, D, W, slot);
+  draw_slot<DIAG, SLOTS, DEFER>(A, D, W, slot, u0, plog, *W.unit_count <= W.ck_units);
 }
 
 // Second phase of a two-phase search (one simulation): one thread per request in
@@ -281,18 +296,41 @@ struct FlatSource {             // flat Morton position g is a type-`want` sourc
 };
 
 // Tiles per simulation: excitatory sources padded to a multiple of 64, then
-// inhibitory ones, so no tile mixes simulations or types. One thread.
-__global__ void b_tiles_k(BatchDev B, int32_t* tile_count) {
+// inhibitory ones, so no tile mixes simulations or types. A simulation with few tiles
+// cuts each into 2^p parts (p <= kPartLogMax): as many as keep its units within
+// kPartUnits and, for a launch with checkpoints, within its share of the checkpoint
+// regions (one per 64 neurons, so every unit keeps a region of its own); else 2 parts
+// sharing each tile's region where that stays within kPartUnits. p depends on the
+// simulation alone, so a simulation's results do not depend on the batch it runs in
+// (force >= 0: p = force). One thread. Also writes the unit count and the number of
+// sources (the length of the Hilbert sort).
+__global__ void b_tiles_k(BatchDev B, int32_t* tile_count, int32_t* unit_count,
+                          int32_t* sources, int64_t total, int force, bool ckpt) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int32_t t = 0;
+  int32_t t = 0, u = 0;
   for (int s = 0; s < B.nsims; ++s) {
     B.tile_base[s] = t;
+    B.unit_base[s] = u;
     const int64_t b = B.nbase[s], e = B.nbase[s + 1];
     const int32_t c0 = B.p0[e] - B.p0[b], c1 = B.p1[e] - B.p1[b];
-    t += (c0 + kWave - 1) / kWave + (c1 + kWave - 1) / kWave;
+    const int32_t ts = (c0 + kWave - 1) / kWave + (c1 + kWave - 1) / kWave;
+    int p = force;
+    if (p < 0) {
+      const int64_t regions = (e - b) / kWave + 2;
+      const int64_t lim = ckpt && regions < kPartUnits ? regions : kPartUnits;
+      p = 0;
+      while (p < kPartLogMax && ((int64_t)ts << (p + 1)) <= lim) ++p;
+      if (p == 0 && 2 * (int64_t)ts <= kPartUnits) p = 1;
+    }
+    B.plog[s] = (uint8_t)p;
+    t += ts;
+    u += ts << p;
   }
   B.tile_base[B.nsims] = t;
+  B.unit_base[B.nsims] = u;
   *tile_count = t;
+  *unit_count = u;
+  *sources = B.p0[total] + B.p1[total];
 }
 
 // Hilbert index of a cell of the 2^21 grid (J. Skilling, "Programming the Hilbert
@@ -340,15 +378,9 @@ __device__ __forceinline__ void morton_decode(uint64_t k, uint32_t& x, uint32_t&
   }
 }
 
-__global__ void fill_u64_k(uint64_t* p, int64_t n, uint64_t v) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) p[k] = v;
-}
-
 // Sort keys of the sources: (simulation, type) group in the top `gb` of `kb` bits, then
 // the leading kb - gb bits of the Hilbert index; value = flat Morton position. Sources
-// are packed in Morton order (position p0 + p1); the rest of the array keeps the
-// padding key written before (all kb bits set), which sorts last.
+// are packed in Morton order (position p0 + p1), so only that prefix is sorted.
 __global__ void b_hkeys_k(BatchDev B, int64_t total, int gb, int kb, uint64_t* key,
                           int32_t* val) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -390,7 +422,7 @@ __global__ void b_work_sorted_k(BatchDev B, int64_t total, const int32_t* __rest
 struct SearchScratch {
   BatchDev B;
   SweepOut W;
-  int32_t* counters;            // [0] tile count, [1..8] die queues
+  int32_t* counters;            // [0] tile count, [1..8] die queues, [9] sources, [10] units
   void* scan_tmp;
   uint64_t* hkey[2];            // [total_n] sort keys of the Hilbert-ordered worklist
   int32_t* hval[2];             // [total_n] their flat positions
@@ -402,9 +434,18 @@ inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 inline int64_t max_tiles_for(int64_t total_n, int nsims) { return total_n / kWave + 2 * nsims + 1; }
 
+// Sweep units: a simulation has at most 2^kPartLogMax units per tile, and more units
+// than tiles only while they stay within kPartUnits; with the parts forced to 2^force
+// (force >= 0), exactly that many per tile.
+inline int64_t max_units_for(int64_t total_n, int nsims, int force = -1) {
+  const int64_t mt = max_tiles_for(total_n, nsims);
+  if (force >= 0) return mt << force;
+  return std::min(mt << kPartLogMax, mt + (int64_t)nsims * kPartUnits);
+}
+
 struct ScratchSizes {
-  size_t ea, p, tile_base, status, work, Z, v, nck, ckx, ckP, ckme, counters, scan, srct, hkey,
-      hval, hsort, total;
+  size_t ea, p, tile_base, unit_base, plog, status, work, Z, v, nck, ckx, ckP, ckme, counters,
+      scan, srct, hkey, hval, hsort, total;
 };
 
 // Checkpoint bytes per slot of a tile: the wave position and, per lane, the running
@@ -412,35 +453,39 @@ struct ScratchSizes {
 constexpr size_t kCkptSlotBytes = sizeof(int32_t) + kWave * (sizeof(double) + sizeof(int32_t));
 
 // `slots` checkpoint slots per tile (0: no checkpoints, for launches without draws).
-inline ScratchSizes scratch_sizes(int64_t total_n, int nsims, int slots) {
+inline ScratchSizes scratch_sizes(int64_t total_n, int nsims, int slots, int force = -1) {
   ScratchSizes z;
   const int64_t mt = max_tiles_for(total_n, nsims);
   const int64_t ms = mt * kWave;
+  const int64_t mu = max_units_for(total_n, nsims, force);
   z.ea = align_up(sizeof(int64_t) * (total_n + 1));
   z.p = align_up(sizeof(int32_t) * (total_n + 1));
   z.tile_base = align_up(sizeof(int32_t) * (nsims + 1));
+  z.unit_base = align_up(sizeof(int32_t) * (nsims + 1));
+  z.plog = align_up(sizeof(uint8_t) * nsims);
   z.status = align_up(sizeof(int32_t) * nsims);
   z.work = align_up(sizeof(int32_t) * ms);
-  z.Z = align_up(sizeof(double) * ms);
-  z.v = align_up(sizeof(int32_t) * ms);
-  z.nck = align_up(sizeof(int32_t) * mt);
+  z.Z = align_up(sizeof(double) * mu * kWave);
+  z.v = align_up(sizeof(int32_t) * mu * kWave);
+  z.nck = align_up(sizeof(int32_t) * mu);
   z.ckx = align_up(sizeof(int32_t) * mt * slots);
   z.ckP = align_up(sizeof(double) * mt * slots * kWave);
   z.ckme = align_up(sizeof(int32_t) * mt * slots * kWave);
-  z.counters = align_up(sizeof(int32_t) * (1 + kXcd));
+  z.counters = align_up(sizeof(int32_t) * (3 + kXcd));
   z.scan = align_up(std::max(scan_tmp_bytes<int64_t>(total_n), scan_tmp_bytes<int32_t>(total_n)));
   z.srct = align_up(sizeof(uint8_t) * total_n);
   z.hkey = align_up(sizeof(uint64_t) * total_n);
   z.hval = align_up(sizeof(int32_t) * total_n);
   z.hsort = align_up(radix_sort_ws_bytes(total_n));
-  z.total = z.ea + 2 * z.p + z.tile_base + z.status + z.work + z.Z + 2 * z.v + z.nck + z.ckx +
+  z.total = z.ea + 2 * z.p + z.tile_base + z.unit_base + z.plog + z.status + z.work + z.Z +
+            2 * z.v + z.nck + z.ckx +
             z.ckP + z.ckme + z.counters + z.scan + z.srct + 2 * z.hkey + 2 * z.hval + z.hsort;
   return z;
 }
 
 inline SearchScratch carve(void* base, int64_t total_n, int nsims, int slots,
-                           const SimDesc* d_sims, const int64_t* d_nbase) {
-  const ScratchSizes z = scratch_sizes(total_n, nsims, slots);
+                           const SimDesc* d_sims, const int64_t* d_nbase, int force = -1) {
+  const ScratchSizes z = scratch_sizes(total_n, nsims, slots, force);
   char* p = static_cast<char*>(base);
   auto take = [&](size_t bytes) {
     char* q = p;
@@ -455,6 +500,8 @@ inline SearchScratch carve(void* base, int64_t total_n, int nsims, int slots,
   S.B.p0 = reinterpret_cast<int32_t*>(take(z.p));
   S.B.p1 = reinterpret_cast<int32_t*>(take(z.p));
   S.B.tile_base = reinterpret_cast<int32_t*>(take(z.tile_base));
+  S.B.unit_base = reinterpret_cast<int32_t*>(take(z.unit_base));
+  S.B.plog = reinterpret_cast<uint8_t*>(take(z.plog));
   S.B.status = reinterpret_cast<int32_t*>(take(z.status));
   S.B.work = reinterpret_cast<int32_t*>(take(z.work));
   S.B.max_slots = max_tiles_for(total_n, nsims) * kWave;
@@ -466,8 +513,10 @@ inline SearchScratch carve(void* base, int64_t total_n, int nsims, int slots,
   S.W.ck_P = reinterpret_cast<double*>(take(z.ckP));
   S.W.ck_me = reinterpret_cast<int32_t*>(take(z.ckme));
   S.W.ck_slots = slots;
+  S.W.ck_units = max_tiles_for(total_n, nsims);
   S.counters = reinterpret_cast<int32_t*>(take(z.counters));
   S.W.tile_count = S.counters;
+  S.W.unit_count = S.counters + 2 + kXcd;
   S.W.queue = S.counters + 1;
   S.W.wave_steps = nullptr;
   S.own_cell = true;
@@ -481,13 +530,16 @@ inline SearchScratch carve(void* base, int64_t total_n, int nsims, int slots,
   return S;
 }
 
-// Preparation: status, CSR offsets, worklists, tile bases. Kernels only.
-inline hipError_t enqueue_prep(SearchScratch& S, int64_t total_n, hipStream_t s) {
+// Preparation: status, CSR offsets, worklists, tile and unit bases. Kernels only.
+// force >= 0: every tile has 2^force parts (the scratch carved for it). ckpt: the
+// sweep will write checkpoints.
+inline hipError_t enqueue_prep(SearchScratch& S, int64_t total_n, hipStream_t s, int force = -1,
+                               bool ckpt = true) {
   BatchDev& B = S.B;
   const unsigned g = grid_for(total_n, 256);
   fill_i32_k<<<grid_for(B.nsims, 256), 256, 0, s>>>(B.status, B.nsims, 0);
   fill_i32_k<<<grid_for(B.max_slots, 256), 256, 0, s>>>(B.work, B.max_slots, -1);
-  fill_i32_k<<<1, 64, 0, s>>>(S.counters, 1 + kXcd, 0);
+  fill_i32_k<<<1, 64, 0, s>>>(S.counters, 3 + kXcd, 0);
   b_check_k<<<g, 256, 0, s>>>(B, total_n);
   hipError_t e = exclusive_scan<int64_t, int32_t, FlatAxon>(nullptr, B.ea, total_n, FlatAxon{B},
                                                              true, s, S.scan_tmp);
@@ -500,16 +552,17 @@ inline hipError_t enqueue_prep(SearchScratch& S, int64_t total_n, hipStream_t s)
   e = exclusive_scan<int32_t, int32_t, FlatSource>(nullptr, B.p1, total_n,
                                                    FlatSource{B.src_type, 1}, true, s, S.scan_tmp);
   if (e != hipSuccess) return e;
-  b_tiles_k<<<1, 64, 0, s>>>(B, S.counters);
+  b_tiles_k<<<1, 64, 0, s>>>(B, S.counters, S.counters + 2 + kXcd, S.counters + 1 + kXcd,
+                             total_n, force, ckpt);
   // 64-source tiles in Hilbert order within each (simulation, type) group
   // (32-bit keys keep 20 or more Hilbert bits, cells of about a hundredth of the box
   // edge or finer, for up to 2048 simulations)
   int gb = 1;
   while ((1ll << gb) < 2ll * B.nsims) ++gb;
   const int kb = gb <= 12 ? 32 : 48;
-  fill_u64_k<<<g, 256, 0, s>>>(S.hkey[0], total_n, (1ull << kb) - 1);
   b_hkeys_k<<<g, 256, 0, s>>>(B, total_n, gb, kb, S.hkey[0], S.hval[0]);
-  e = radix_sort_pairs_ws(S.hkey[0], S.hval[0], S.hkey[1], S.hval[1], total_n, kb, s, S.hsort);
+  e = radix_sort_pairs_ws(S.hkey[0], S.hval[0], S.hkey[1], S.hval[1], total_n, kb, s, S.hsort,
+                          S.counters + 1 + kXcd);
   if (e != hipSuccess) return e;
   b_work_sorted_k<<<g, 256, 0, s>>>(B, total_n, S.hval[0]);
   return hipGetLastError();

@@ -117,8 +117,8 @@ bool own_cell_needed(const msp_octree_s* t, double theta) {
 }
 
 // Persistent sweep blocks: occupancy x CUs (times `frac` in [0, 1]), at most one
-// wave per tile.
-hipError_t sweep_blocks_for(int device, bool diag, int64_t max_tiles, double frac,
+// wave per unit (a tile's part).
+hipError_t sweep_blocks_for(int device, bool diag, int64_t max_units, double frac,
                             unsigned* blocks_out) {
   int ncu = 0, per_cu = 0;
   hipError_t e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
@@ -131,7 +131,7 @@ hipError_t sweep_blocks_for(int device, bool diag, int64_t max_tiles, double fra
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
   int64_t blocks = (int64_t)((double)ncu * per_cu * frac);
-  const int64_t need = (max_tiles + (kWaveBlock / kWave) - 1) / (kWaveBlock / kWave);
+  const int64_t need = (max_units + (kWaveBlock / kWave) - 1) / (kWaveBlock / kWave);
   if (blocks > need) blocks = need;
   if (blocks < 1) blocks = 1;
   *blocks_out = (unsigned)blocks;
@@ -419,12 +419,18 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
           h.diag.opens0;
   }
   const int64_t hbase[2] = {0, n};
+  int force = -1;                       // parts per tile: automatic
+  if (diag && diag->parts_per_tile != 0) {
+    const int pp = diag->parts_per_tile;
+    if (pp != 1 && pp != 2 && pp != 4 && pp != 8) return MSP_ERR_INVALID;
+    force = pp == 1 ? 0 : pp == 2 ? 1 : pp == 4 ? 2 : 3;
+  }
   int slots = 0;
   MSP_HIP_TRY(ck_slots_for(t->device, n, 1, &slots));
   WorkspaceLease ws(t->device);
   void* scratch = nullptr;
   // the workspace also holds the simulation descriptor and the neuron bases
-  const size_t body = scratch_sizes(n, 1, slots).total;
+  const size_t body = scratch_sizes(n, 1, slots, force).total;
   MSP_HIP_TRY(ws.acquire(body + align_up(sizeof(SimDesc)) + align_up(sizeof(hbase)), s,
                          &scratch));
   SimDesc* dsim = reinterpret_cast<SimDesc*>(static_cast<char*>(scratch) + body);
@@ -432,14 +438,15 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
                                               align_up(sizeof(SimDesc)));
   MSP_HIP_TRY(hipMemcpyAsync(dsim, &h, sizeof(SimDesc), hipMemcpyHostToDevice, s));
   MSP_HIP_TRY(hipMemcpyAsync(dbase, hbase, sizeof(hbase), hipMemcpyHostToDevice, s));
-  SearchScratch S = carve(scratch, n, 1, slots, dsim, dbase);
+  SearchScratch S = carve(scratch, n, 1, slots, dsim, dbase, force);
   S.own_cell = own_cell_needed(t, theta);
   if (any) S.W.wave_steps = reinterpret_cast<unsigned long long*>(diag->wave_steps);
-  MSP_HIP_TRY(enqueue_prep(S, n, s));
-  int32_t status = 0, ntiles = 0;
+  MSP_HIP_TRY(enqueue_prep(S, n, s, force));
+  int32_t status = 0, ntiles = 0, nunits = 0;
   int64_t total_S = 0;
   MSP_HIP_TRY(hipMemcpyAsync(&status, S.B.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   MSP_HIP_TRY(hipMemcpyAsync(&ntiles, S.counters, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MSP_HIP_TRY(hipMemcpyAsync(&nunits, S.W.unit_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   MSP_HIP_TRY(hipMemcpyAsync(&total_S, elem_offset_out + n, sizeof(int64_t),
                              hipMemcpyDeviceToHost, s));
   MSP_HIP_TRY(hipStreamSynchronize(s));
@@ -480,7 +487,7 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
     D.level = reinterpret_cast<uint8_t*>(p + 2 * ks + 5 * vs);
   }
   unsigned blocks = 0;
-  MSP_HIP_TRY(sweep_blocks_for(t->device, any, ntiles, 1.0, &blocks));
+  MSP_HIP_TRY(sweep_blocks_for(t->device, any, nunits, 1.0, &blocks));
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   if (timed) {
     for (auto& e : ev) MSP_HIP_TRY(hipEventCreate(&e));
@@ -727,7 +734,7 @@ hipError_t batch_enqueue(msp_batch_s* b, hipStream_t s) {
 hipError_t batch_autotune(msp_batch_s* b, hipStream_t s) {
   const double fracs[] = {1.0, 0.75, 0.5};
   const int draws[] = {256, 128, 64};
-  const int64_t max_tiles = max_tiles_for(b->total_n, b->nsims);
+  const int64_t max_units = max_units_for(b->total_n, b->nsims);
   hipEvent_t e0, e1;
   hipError_t e = hipEventCreate(&e0);
   if (e != hipSuccess) return e;
@@ -739,7 +746,7 @@ hipError_t batch_autotune(msp_batch_s* b, hipStream_t s) {
   for (double f : fracs) {
     for (int d : draws) {
       unsigned blocks = 0;
-      if ((e = sweep_blocks_for(b->device, false, max_tiles, f, &blocks)) != hipSuccess) break;
+      if ((e = sweep_blocks_for(b->device, false, max_units, f, &blocks)) != hipSuccess) break;
       b->sweep_blocks = blocks;
       b->draw_block = d;
       float ms = 0.0f;
@@ -814,7 +821,7 @@ msp_status msp_batch_create(const msp_sim* sims, int32_t n_sims, int32_t flags, 
   if (e == hipSuccess)
     e = hipMemcpy(b->d_nbase, base.data(), sizeof(int64_t) * (n_sims + 1), hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = sweep_blocks_for(dev, false, max_tiles_for(total, n_sims), 1.0, &b->sweep_blocks);
+    e = sweep_blocks_for(dev, false, max_units_for(total, n_sims), 1.0, &b->sweep_blocks);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     batch_release(b);
@@ -929,7 +936,7 @@ msp_status attraction(msp_octree t, const uint8_t* neuron_type, const int32_t* v
   MSP_HIP_TRY(hipMemcpyAsync(dsim.p, &h, sizeof(SimDesc), hipMemcpyHostToDevice, s));
   MSP_HIP_TRY(hipMemcpyAsync(dbase.p, hbase, sizeof(hbase), hipMemcpyHostToDevice, s));
   SearchScratch S = carve(scratch.p, n, 1, 0, dsim.as<SimDesc>(), dbase.as<int64_t>());
-  MSP_HIP_TRY(enqueue_prep(S, n, s));
+  MSP_HIP_TRY(enqueue_prep(S, n, s, -1, false));
   int32_t status = 0;
   MSP_HIP_TRY(hipMemcpyAsync(&status, S.B.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   MSP_HIP_TRY(hipStreamSynchronize(s));
@@ -938,11 +945,11 @@ msp_status attraction(msp_octree t, const uint8_t* neuron_type, const int32_t* v
   if (!bwd) {
     // Z_i is the level-0 sum of the search: the sweep without checkpoints
     unsigned blocks = 0;
-    MSP_HIP_TRY(sweep_blocks_for(t->device, false, max_tiles_for(n, 1), 1.0, &blocks));
+    MSP_HIP_TRY(sweep_blocks_for(t->device, false, max_units_for(n, 1), 1.0, &blocks));
     fill_i32_k<<<grid_for(n, 256), 256, 0, s>>>(reinterpret_cast<int32_t*>(Z_out), n, 0);
     S.own_cell = own_cell_needed(t, theta);
     launch_sweep<false, 0>(S, blocks, s);
-    z_scatter_k<<<grid_for(S.B.max_slots, 256), 256, 0, s>>>(S.B.work, S.W.Z, S.counters, Z_out);
+    z_scatter_k<<<grid_for(S.B.max_slots, 256), 256, 0, s>>>(S.B, S.W, Z_out);
     MSP_HIP_TRY(hipGetLastError());
     return MSP_OK;
   }

@@ -144,13 +144,22 @@ constexpr int kSortBlock = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortBlock * kSortItems;
 
+// dn (nullable): a device count that lowers n (items past it are left alone; the
+// tiles beyond it contribute empty histograms and write nothing).
+__device__ __forceinline__ int64_t sort_count(int64_t n, const int32_t* dn) {
+  if (!dn) return n;
+  const int64_t c = *dn;
+  return c < 0 ? 0 : (c < n ? c : n);
+}
+
 __global__ void __launch_bounds__(kSortBlock) rs_hist_k(const uint64_t* keys, int64_t n, int shift,
-                                                       uint32_t* hist, int nb) {
+                                                       uint32_t* hist, int nb, const int32_t* dn) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
+  n = sort_count(n, dn);
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
-  for (int k = 0; k < kSortItems; ++k) {
+  for (int k = 0; k < kSortItems && base < n; ++k) {
     int64_t idx = base + (int64_t)k * kSortBlock + threadIdx.x;
     if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
   }
@@ -164,7 +173,8 @@ __global__ void __launch_bounds__(kSortBlock) rs_hist_k(const uint64_t* keys, in
 // scanned (digit-major) histogram.
 __global__ void __launch_bounds__(kSortBlock) rs_scatter_k(const uint64_t* kin, const int32_t* vin,
                                                           uint64_t* kout, int32_t* vout, int64_t n,
-                                                          int shift, const uint32_t* off, int nb) {
+                                                          int shift, const uint32_t* off, int nb,
+                                                          const int32_t* dn) {
   __shared__ uint64_t lk[kSortTile];
   __shared__ int32_t lv[kSortTile];
   __shared__ uint32_t lstart[256];      // tile-local start of each digit's run
@@ -175,7 +185,9 @@ __global__ void __launch_bounds__(kSortBlock) rs_scatter_k(const uint64_t* kin, 
   const int w = t / kWave;
   const int lane = t & (kWave - 1);
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (kWave - lane));
+  n = sort_count(n, dn);
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  if (base >= n) return;                // uniform over the block
   const int64_t rem = n - base;
   const int tile_n = rem < kSortTile ? (int)rem : kSortTile;
   const int64_t h = (int64_t)t * nb + blockIdx.x;
@@ -250,8 +262,12 @@ inline size_t radix_sort_ws_bytes(int64_t n) {
 // Sort (keys, vals) of length n ascending by the low `bits` key bits (a multiple of 8).
 // Buffers k0/v0 hold the input and receive the output; k1/v1 are scratch of size n;
 // `ws` holds radix_sort_ws_bytes(n) bytes. Allocates nothing, so it can be captured.
+// dn (nullable, device): sort only the first min(n, *dn) items, a count known on the
+// device alone; the launches stay sized for n. Needs an even number of passes.
 inline hipError_t radix_sort_pairs_ws(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1,
-                                      int64_t n, int bits, hipStream_t s, void* ws) {
+                                      int64_t n, int bits, hipStream_t s, void* ws,
+                                      const int32_t* dn = nullptr) {
+  if (dn && ((bits + 7) / 8) % 2 != 0) return hipErrorInvalidValue;
   if (n <= 1) return hipSuccess;
   const int64_t nb = (n + kSortTile - 1) / kSortTile;
   uint32_t* hist = static_cast<uint32_t*>(ws);
@@ -262,11 +278,12 @@ inline hipError_t radix_sort_pairs_ws(uint64_t* k0, int32_t* v0, uint64_t* k1, i
   int32_t* vb = v1;
   hipError_t e = hipSuccess;
   for (int shift = 0; shift < bits; shift += 8) {
-    rs_hist_k<<<(unsigned)nb, kSortBlock, 0, s>>>(ka, n, shift, hist, (int)nb);
+    rs_hist_k<<<(unsigned)nb, kSortBlock, 0, s>>>(ka, n, shift, hist, (int)nb, dn);
     e = exclusive_scan<uint32_t, uint32_t, Ident<uint32_t>>(hist, hist, 256 * nb, Ident<uint32_t>(),
                                                             false, s, scan_ws);
     if (e != hipSuccess) return e;
-    rs_scatter_k<<<(unsigned)nb, kSortBlock, 0, s>>>(ka, va, kb, vb, n, shift, hist, (int)nb);
+    rs_scatter_k<<<(unsigned)nb, kSortBlock, 0, s>>>(ka, va, kb, vb, n, shift, hist, (int)nb,
+                                                     dn);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     uint64_t* tk = ka; ka = kb; kb = tk;

@@ -12,6 +12,12 @@
 // It produces each source's level-0 normaliser Z and, every `interval` wave steps,
 // a checkpoint per lane (running sum, mask_end) with the wave position.
 //
+// Parts: where a simulation has few tiles, each tile's pre-order range is cut into
+// 2^p consecutive parts walked by different waves (a work unit is a tile's part).
+// A part's walk starts from the lane states at its first node, found from that node's
+// ancestors, so every lane sees the same nodes as in one walk; the part sums add up
+// to Z and every part keeps its own checkpoints (running sums from the part's start).
+//
 // search_draw_k: one thread per source and element j: T = u Z, then the source's
 // own walk restarts from the last checkpoint whose running sum does not exceed T
 // (not from the root), then restart levels (a drawn cell) run per thread.
@@ -24,6 +30,9 @@ namespace msp {
 constexpr int kCkptMax = 256;      // checkpoint slots per tile: this many where memory
 constexpr int kCkptMin = 32;       // allows, else this many (both powers of two)
 constexpr int kCkptStepMin = 16;   // smallest checkpoint interval, wave steps
+constexpr int kPartLogMax = 3;     // at most 2^3 parts per tile
+constexpr int kPartUnits = 131072; // parts are added while a simulation's units stay
+                                   // within this (16 per wave of a full launch)
 constexpr int kWaveBlock = 256;    // 4 independent waves per block
 constexpr int kXcd = 8;            // accelerator dies; workgroup b runs on die b % 8
 
@@ -45,15 +54,17 @@ struct DeferOut {
 };
 
 struct SweepOut {
-  double* Z;                       // [slots] level-0 sum
-  int32_t* v0;                     // [slots] level-0 visits (counting launches only)
-  int32_t* o0;                     // [slots] level-0 opens
-  int32_t* nck;                    // [tiles] checkpoints written
-  int32_t* ck_x;                   // [tiles][ck_slots] wave position
-  double* ck_P;                    // [tiles][ck_slots][64] running sum
-  int32_t* ck_me;                  // [tiles][ck_slots][64] mask_end
-  int ck_slots;                    // checkpoint slots per tile: kCkptMax or kCkptMin
+  double* Z;                       // [units][64] level-0 sum of the unit's part
+  int32_t* v0;                     // [units][64] level-0 visits (counting launches only)
+  int32_t* o0;                     // [units][64] level-0 opens
+  int32_t* nck;                    // [units] checkpoints written
+  int32_t* ck_x;                   // [ck_units][ck_slots] wave position
+  double* ck_P;                    // [ck_units][ck_slots][64] running sum
+  int32_t* ck_me;                  // [ck_units][ck_slots][64] mask_end
+  int ck_slots;                    // checkpoint slots per region: kCkptMax or kCkptMin
+  int64_t ck_units;                // checkpoint regions (see unit_slots)
   const int32_t* tile_count;       // device scalar
+  const int32_t* unit_count;       // device scalar: tiles times their parts
   int32_t* queue;                  // [kXcd] tile counters, zero at launch
   unsigned long long* wave_steps;  // counting launches: total wave steps (nullable)
   DeferOut defer;                  // two-phase search (depth kNoDefer: one phase)
@@ -98,9 +109,96 @@ __device__ __forceinline__ NodeRec load_rec(cptr<NodeRec> R, int64_t x) {
   return r;
 }
 
+// The pre-order range [x_lo, x_hi) of part `part` of a tile cut into 2^plog parts
+// (wave-uniform; every wave that walks a part of the tile finds the same cuts). The
+// cuts lie around m, the median of the sources' leaf positions, at m - c s and m + c s
+// for a ladder of multipliers c, s being the sources' leaf range (at least 64),
+// clamped into [1, end]: the union walk's steps are densest around the sources and
+// thin out with the distance from them along the pre-order.
+__device__ __forceinline__ void part_range(int32_t li, bool valid, int lane, int plog, int part,
+                                           int32_t end, int32_t& x_lo, int32_t& x_hi) {
+  const int32_t key = valid ? li : INT32_MAX;
+  int32_t lo = INT32_MAX, hi = -1, rank = 0;
+  for (int m = 0; m < kWave; ++m) {
+    const int32_t km = __builtin_amdgcn_readlane(key, m);
+    if (km != INT32_MAX) {
+      lo = km < lo ? km : lo;
+      hi = km > hi ? km : hi;
+    }
+    rank += (km < key || (km == key && m < lane)) ? 1 : 0;
+  }
+  const int nv = __popcll(__ballot(valid));
+  const uint64_t at = __ballot(valid && rank == nv / 2);
+  const int32_t med = __builtin_amdgcn_readlane(key, __ffsll((unsigned long long)at) - 1);
+  const int64_t span = (int64_t)hi - lo + 1 > 64 ? (int64_t)hi - lo + 1 : 64;
+  const int np = 1 << plog;
+  // cut k (1 <= k < np) at med + mult(k - np / 2) span
+  auto cut = [&](int k) -> int32_t {
+    const int c = k - np / 2;
+    const int a = c < 0 ? -c : c;
+    int64_t mult = 0;
+    if (a != 0) mult = plog == 3 ? (a == 1 ? 1 : a == 2 ? 8 : 64) : 4;
+    int64_t x = (int64_t)med + (c < 0 ? -mult : mult) * span;
+    x = x < 1 ? 1 : x;
+    return (int32_t)(x > end ? end : x);
+  };
+  x_lo = __builtin_amdgcn_readfirstlane(part == 0 ? 1 : cut(part));
+  x_hi = __builtin_amdgcn_readfirstlane(part == np - 1 ? end : cut(part + 1));
+}
+
+// The checkpoint slots of unit `unit`, part `part` of its tile's 2^plog parts: the
+// first slot and the count. Where the launch has no more units than checkpoint
+// regions (W.ck_units, one per tile of the largest launch), every unit has a region
+// of its own; otherwise the parts of a tile share its region equally.
+__device__ __forceinline__ void unit_slots(const SweepOut& W, int slots, bool own, int64_t tile,
+                                           int plog, int part, int64_t unit, int64_t& first,
+                                           int& count) {
+  if (own) {
+    first = unit * slots;
+    count = slots;
+  } else {
+    count = slots >> plog;
+    first = tile * slots + (int64_t)part * count;
+  }
+}
+
+// A lane's mask end at node x0 > 1 of a walk that starts there: the end of the
+// subtree of the first ancestor of x0 that the lane's own walk does not enter
+// (accepted, or holding no vacancy), else 0 (the lane is active at x0). The
+// ancestors are found by following the pre-order from the root's first child:
+// over a subtree that ends at or before x0, into one that holds it.
+template <bool OWN>
+__device__ __forceinline__ int32_t mask_at(const SearchArgs& A, cptr<NodeRec> R, int32_t x0,
+                                           int32_t me, int32_t li, double xi, double yi,
+                                           double zi) {
+  int32_t y = 1;
+  while (y < x0) {
+    const NodeRec r = load_rec_u(R, (uint32_t)y);
+    int32_t sk = y + 1;
+    if ((int32_t)r.meta >= 0) {
+      const int32_t e = (int32_t)(r.meta & kSkipMask);
+      sk = e > y ? e : y + 1;
+    }
+    if (sk > x0) {                       // an ancestor of x0 (inner node)
+      bool out = true;                   // v == 0: the walk jumps over the subtree
+      if (r.v != 0) {
+        const double d2 = dist2(xi, yi, zi, r.x, r.y, r.z);
+        const bool contains = OWN && (uint32_t)(li - y) < (uint32_t)(sk - y);
+        out = !contains && bh_accept(A.L2, A.theta2, d2, r.meta >> (kSkipBits - 1));
+      }
+      if (me <= y && out) me = sk;
+      y = y + 1;
+    } else {
+      y = sk;
+    }
+  }
+  return me;
+}
+
 // `step0`: initial checkpoint interval (a power of two), chosen from the length of
 // the wave's previous sweep so that the buffer rarely has to be thinned out.
-// Returns the number of wave steps of this tile.
+// Returns the number of wave steps of this unit: part `part` of the tile's 2^plog
+// parts (unit index `unit`); own: the unit has a checkpoint region of its own.
 // OWN: test whether an inner node holds the source's own leaf (such a node is always
 // opened). Launches drop the test only where it can never fire: with theta <= 1/2 and
 // every position inside the cube, the source and the node's centroid lie in (or,
@@ -108,7 +206,8 @@ __device__ __forceinline__ NodeRec load_rec(cptr<NodeRec> R, int64_t x) {
 // so d^2 <= 3 l^2 (1 + 2^-4) and theta^2 d^2 < l^2: the acceptance test fails anyway.
 template <bool DIAG, int SLOTS, bool OWN>
 __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W, int tile,
-                                          int lane, int step0) {
+                                          int part, int plog, int64_t unit, bool own, int lane,
+                                          int step0) {
   const int64_t slot = (int64_t)tile * kWave + lane;
   const int32_t i = A.work[slot];                                // -1: padding lane
   const bool valid = i >= 0;
@@ -134,33 +233,40 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
   const NodeRec root = load_rec(R, 0);
   if (root.meta & kLeafBit) {
     // a one-neuron tree: the only neuron is the source itself, so the list is empty
-    if (DIAG && valid) c0.visits = 1;
+    if (DIAG && valid && part == 0) c0.visits = 1;
   } else {
-    const int32_t end = (int32_t)(root.meta & kSkipMask);
-    int32_t* ckx = W.ck_x + (int64_t)tile * SLOTS;
-    double* ckP = W.ck_P + (int64_t)tile * SLOTS * kWave + lane;
-    int32_t* ckme = W.ck_me + (int64_t)tile * SLOTS * kWave + lane;
-    if (DIAG && valid) {
+    const int32_t root_end = (int32_t)(root.meta & kSkipMask);
+    int32_t x = 1, end = root_end;
+    int32_t me = valid ? 0 : 0x7FFFFFFF;     // padding lanes are never active
+    if (plog > 0) {
+      part_range(li, valid, lane, plog, part, root_end, x, end);
+      if (x > 1 && x < end) me = mask_at<OWN>(A, R, x, me, li, xi, yi, zi);
+    }
+    int64_t ck0 = 0;                        // this unit's checkpoint slots
+    int ns = 0;
+    unit_slots(W, SLOTS, own, tile, plog, part, unit, ck0, ns);
+    int32_t* ckx = W.ck_x + ck0;
+    double* ckP = W.ck_P + ck0 * kWave + lane;
+    int32_t* ckme = W.ck_me + ck0 * kWave + lane;
+    if (DIAG && valid && part == 0) {
       c0.visits = 1;
       c0.opens = 1;
     }
-    int32_t x = 1;
-    int32_t me = valid ? 0 : 0x7FFFFFFF;     // padding lanes are never active
     int imask = __builtin_amdgcn_readfirstlane(step0 - 1);   // interval - 1 (power of 2)
-    NodeRec cur = load_rec_u(R, 1);
+    NodeRec cur = load_rec_u(R, (uint32_t)x);
     while (x < end) {
       int chunk = 0x7FFFFFFF;                 // without checkpoints: one chunk to the end
       if constexpr (SLOTS > 0) {
         // checkpoints at multiples of the interval; a full buffer keeps every other
         // one and doubles the interval
-        if (nck == SLOTS) {
+        if (nck == ns) {
 #pragma unroll 1
-          for (int k = 1; k < SLOTS / 2; ++k) {
+          for (int k = 1; k < ns / 2; ++k) {
             ckP[k * kWave] = ckP[2 * k * kWave];
             ckme[k * kWave] = ckme[2 * k * kWave];
             if (lane == 0) ckx[k] = ckx[2 * k];
           }
-          nck = SLOTS / 2;
+          nck = ns / 2;
           imask = __builtin_amdgcn_readfirstlane(2 * imask + 1);
         }
         if ((steps & imask) == 0) {
@@ -222,7 +328,7 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
           }
         }
         x = next < end ? next : end;
-        cur = load_rec_u(R, (uint32_t)x);     // index end = N: the sentinel record
+        cur = load_rec_u(R, (uint32_t)x);     // index N: the sentinel record
         if (x >= end) {
           --left;
           break;
@@ -231,21 +337,23 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
       steps += chunk - left;
     }
   }
-  if (lane == 0) W.nck[tile] = nck;
-  W.Z[slot] = sum.Z;
+  const int64_t us = unit * kWave + lane;
+  if (lane == 0) W.nck[unit] = nck;
+  W.Z[us] = sum.Z;
   if (DIAG) {
-    W.v0[slot] = c0.visits;
-    W.o0[slot] = c0.opens;
+    W.v0[us] = c0.visits;
+    W.o0[us] = c0.opens;
     if (W.wave_steps && lane == 0) atomicAdd(W.wave_steps, (unsigned long long)steps);
   }
   return steps;
 }
 
 // The draws and restarts of the source in worklist slot `slot` (DEFER: restarts from
-// cells at depth >= W.defer.depth become second-phase requests).
+// cells at depth >= W.defer.depth become second-phase requests). The slot's tile has
+// 2^plog parts, units u0, u0 + 1, ...
 template <bool DIAG, int SLOTS, bool DEFER>
 __device__ __forceinline__ void draw_slot(const SearchArgs& A, const DiagOut& D, const SweepOut& W,
-                                          int64_t slot) {
+                                          int64_t slot, int64_t u0, int plog, bool own) {
   const int32_t i = A.work[slot];
   if (i < 0) return;
   const int64_t tile = slot / kWave;
@@ -256,19 +364,20 @@ __device__ __forceinline__ void draw_slot(const SearchArgs& A, const DiagOut& D,
   const int32_t li = A.leaf_of[i];
   const double xi = A.pos[3 * (int64_t)i], yi = A.pos[3 * (int64_t)i + 1],
                zi = A.pos[3 * (int64_t)i + 2];
-  const double Z = W.Z[slot];
-  const int nck = W.nck[tile];
+  const int np = 1 << plog;
+  const double* Zp = W.Z + u0 * kWave + lane;        // the part sums, in part order
+  double Z = 0.0;
+  for (int q = 0; q < np; ++q) Z = Z + Zp[q * kWave];
   const NodeRec root = R[0];             // Z > 0 implies an inner root
   const int32_t end = (int32_t)(root.meta & kSkipMask);
-  const int32_t* ckx = W.ck_x + tile * SLOTS;
-  const double* ckP = W.ck_P + tile * SLOTS * kWave + lane;
-  const int32_t* ckme = W.ck_me + tile * SLOTS * kWave + lane;
   const int32_t a = A.vac_axon[i];
   const int64_t off = A.elem_off[i];
   Count c0;
   if (DIAG) {
-    c0.visits = W.v0[slot];
-    c0.opens = W.o0[slot];
+    for (int q = 0; q < np; ++q) {
+      c0.visits += W.v0[(u0 + q) * kWave + lane];
+      c0.opens += W.o0[(u0 + q) * kWave + lane];
+    }
   }
   for (int32_t j = 0; j < a; ++j) {
     int lev = 1;
@@ -279,15 +388,38 @@ __device__ __forceinline__ void draw_slot(const SearchArgs& A, const DiagOut& D,
       const double T = draw_u(A.seed, i, j, A.step, 0) * Z;
       SelectPass p{A.k2, T};
       Count none;
-      // last checkpoint whose running sum does not exceed T (checkpoint 0 holds 0)
-      int lo = 0, hi = nck - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (ckP[mid * kWave] <= T) lo = mid; else hi = mid - 1;
+      // the part where the running sum crosses T (the sums added as for Z), and T
+      // from that part's start
+      int k = -1;
+      double Tk = T, pre = 0.0;
+      for (int q = 0; q < np; ++q) {
+        const double zq = Zp[q * kWave];
+        const double nxt = pre + zq;
+        if (k < 0 && zq > 0.0 && nxt > T) {
+          k = q;
+          Tk = T - pre;
+        }
+        pre = nxt;
       }
-      p.P = ckP[lo * kWave];
-      const int32_t cx = ckx[lo], cm = ckme[lo * kWave];
-      expand_range<false>(A, R, vs, cx > cm ? cx : cm, end, i, li, xi, yi, zi, p, none);
+      if (k >= 0) {
+        const int nck = W.nck[u0 + k];
+        int64_t ck0 = 0;
+        int ns = 0;
+        unit_slots(W, SLOTS, own, tile, plog, k, u0 + k, ck0, ns);
+        const int32_t* ckx = W.ck_x + ck0;
+        const double* ckP = W.ck_P + ck0 * kWave + lane;
+        const int32_t* ckme = W.ck_me + ck0 * kWave + lane;
+        // last checkpoint whose running sum does not exceed Tk (checkpoint 0 holds 0)
+        int lo = 0, hi = nck - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (ckP[mid * kWave] <= Tk) lo = mid; else hi = mid - 1;
+        }
+        p.P = ckP[lo * kWave];
+        p.T = Tk;
+        const int32_t cx = ckx[lo], cm = ckme[lo * kWave];
+        expand_range<false>(A, R, vs, cx > cm ? cx : cm, end, i, li, xi, yi, zi, p, none);
+      }
       if (p.chosen < 0) {                       // not crossed (rounding): full walk
         p = SelectPass{A.k2, T};
         expand_range<false>(A, R, vs, 1, end, i, li, xi, yi, zi, p, none);
