@@ -35,7 +35,7 @@ struct AttractArgs {
   double two_over_s2;           // 2 / sigma^2
   double two_over_s3;           // 2 / sigma^3
   int64_t N;
-  const int32_t* tile_count;
+  const int32_t* unit_count;    // device scalar: the sweep units (parts of tiles)
 };
 
 // The die (XCC) this wave runs on: bits 3:0 of hardware register XCC_ID (20). It only
@@ -87,7 +87,10 @@ __device__ __forceinline__ void wave_add3(double fx, double fy, double fz, doubl
   }
 }
 
-__device__ void attract_tile(const SearchArgs& A, const AttractArgs& O, int tile, int lane) {
+// Part `part` of the tile's 2^plog parts (the search's level-0 sweep cut into parts:
+// the lane states at the part's first node come from its ancestors).
+__device__ void attract_tile(const SearchArgs& A, const AttractArgs& O, int tile, int part,
+                             int plog, int lane) {
   const int64_t slot = (int64_t)tile * kWave + lane;
   const int32_t i = A.work[slot];
   const bool valid = i >= 0;
@@ -125,9 +128,13 @@ __device__ void attract_tile(const SearchArgs& A, const AttractArgs& O, int tile
   };
   const NodeRec root = load_rec(R, 0);
   if (!(root.meta & kLeafBit)) {
-    const int32_t end = (int32_t)(root.meta & kSkipMask);
-    int32_t x = 1;
+    const int32_t root_end = (int32_t)(root.meta & kSkipMask);
+    int32_t x = 1, end = root_end;
     int32_t me = valid ? 0 : 0x7FFFFFFF;
+    if (plog > 0) {
+      part_range(li, valid, lane, plog, part, root_end, x, end);
+      if (x > 1 && x < end) me = mask_at<true>(A, R, x, me, li, xi, yi, zi);
+    }
     while (x < end) {
       const NodeRec cur = load_rec(R, x);
       const bool active = x >= me;
@@ -195,13 +202,17 @@ __device__ void attract_tile(const SearchArgs& A, const AttractArgs& O, int tile
   if (lane == 0 && ds != 0.0) atomicAdd(O.dsigma, ds);
 }
 
-// One wave per tile (the batch path's worklist of sources with a_i > 0).
+// One wave per unit, a part of a tile of the batch path's worklist of sources with
+// a_i > 0 (one simulation).
 __global__ void __launch_bounds__(256) attract_bwd_k(BatchDev B, AttractArgs O) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  if (tile >= *O.tile_count) return;
+  const int64_t unit = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  if (unit >= *O.unit_count) return;
   const SearchArgs A = args_of(B.sims, 0, B.work);
-  attract_tile(A, O, (int)tile, lane);
+  const int plog = __builtin_amdgcn_readfirstlane((int)as_const(B.plog)[0]);
+  const int local = __builtin_amdgcn_readfirstlane((int)(unit - as_const(B.unit_base)[0]));
+  const int tile = as_const(B.tile_base)[0] + (local >> plog);
+  attract_tile(A, O, tile, local & ((1 << plog) - 1), plog, lane);
 }
 
 // Z of every source from the sweep's part sums (added in part order, then rounded to

@@ -958,7 +958,7 @@ msp_status attraction(msp_octree t, const uint8_t* neuron_type, const int32_t* v
   O.two_over_s2 = 2.0 / (sigma_um * sigma_um);
   O.two_over_s3 = 2.0 / (sigma_um * sigma_um * sigma_um);
   O.N = N;
-  O.tile_count = S.counters;
+  O.unit_count = S.W.unit_count;
   const int64_t ng = 2 * N * 3, nh = 2 * N * 3, np = 3 * n;
   MSP_HIP_TRY(grads.alloc(sizeof(double) * (size_t)(kGradCopies * ng + nh + np)));
   O.G = grads.as<double>();
@@ -968,7 +968,7 @@ msp_status attraction(msp_octree t, const uint8_t* neuron_type, const int32_t* v
   fill_f64_k<<<grid_for(kGradCopies * ng + nh + np, 256), 256, 0, s>>>(
       O.G, kGradCopies * ng + nh + np, 0.0);
   fill_f64_k<<<1, 64, 0, s>>>(dsigma, 1, 0.0);
-  attract_bwd_k<<<grid_for(S.B.max_slots, 256), 256, 0, s>>>(S.B, O);
+  attract_bwd_k<<<grid_for(max_units_for(n, 1) * kWave, 256), 256, 0, s>>>(S.B, O);
   grad_sum_k<<<grid_for(ng, 256), 256, 0, s>>>(O.G, ng);
   for (int k = 0; k <= kMaxDepth; ++k) {
     const int64_t cnt = t->level_off[k + 1] - t->level_off[k];
