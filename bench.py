@@ -552,6 +552,10 @@ def main():
                     help="instead of the benchmark: visits and throughput over n and theta")
     ap.add_argument("--updates", type=int, default=100,
                     help="updates of the multi-update workload measured with the others")
+    ap.add_argument("--only", choices=["clusters", "batched", "attraction", "activity",
+                                       "plasticity"], default=None,
+                    help="instead of the benchmark: one of the other workloads alone (for "
+                         "profiling), its result as one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this benchmark runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -566,6 +570,23 @@ def main():
         import torch
         import paper_2509_26193_amd as msp
         study_complexity(msp, torch)
+        return
+    if args.only:
+        import torch
+        import paper_2509_26193_amd as msp
+        if args.only == "clusters":
+            from synth_inputs import config_clusters
+            r = bench_plain_update(msp, torch, config_clusters(theta=0.3), steps=args.steps,
+                                   warmup=args.warmup)
+        elif args.only == "batched":
+            r = bench_batched(msp, torch)
+        elif args.only == "attraction":
+            r = bench_attraction(msp, torch)
+        elif args.only == "activity":
+            r = bench_activity(msp, torch, make_workload("large", None))
+        else:
+            r = bench_plasticity(msp, torch, args.updates)
+        print(json.dumps({"only": args.only, **r}), flush=True)
         return
 
     import torch
