@@ -73,18 +73,47 @@ __device__ __forceinline__ double wave_sum(double v) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// Add the wave's contributions (fx, fy, fz) to dst[3] of this die's copy (skipped if
+// v from lane (lane ^ m), through the LDS crossbar (both 32-bit halves).
+__device__ __forceinline__ double shfl_xor_f64(double v, int lane, int m) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int addr = (lane ^ m) << 2;
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)b);
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// The wave sums of three values at once (every lane active): the lanes split the
+// values between them as they add, so each exchange moves one or two values instead of
+// three. After the pair and quad steps lane l holds a partial sum of value
+// {0, 2, 1, 3}[l % 4] (value 3 is zero), then the four lanes of a row with that value
+// and the four rows are added. Returns lane l's full sum of that value; `comp` is set
+// to its index (3: none).
+__device__ __forceinline__ double wave_sum3(double fx, double fy, double fz, int lane, int& comp) {
+  const bool odd = lane & 1;
+  // pairs: even lanes keep (x, y) and send (z, 0); odd lanes the other way round
+  const double s0 = odd ? fx : fz, s1 = odd ? fy : 0.0;
+  const double k0 = odd ? fz : fx, k1 = odd ? 0.0 : fy;
+  const double p = k0 + dpp_f64<0xB1, 0xF>(s0);      // quad_perm [1,0,3,2]
+  const double q = k1 + dpp_f64<0xB1, 0xF>(s1);
+  // quads: lanes 0, 1 of a quad keep p (x, z), lanes 2, 3 keep q (y, 0)
+  const bool up = (lane >> 1) & 1;
+  double v = (up ? q : p) + dpp_f64<0x4E, 0xF>(up ? p : q);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x124, 0xF>(v);                       // row_ror:4
+  v += dpp_f64<0x128, 0xF>(v);                       // row_ror:8
+  v += shfl_xor_f64(v, lane, 16);
+  v += shfl_xor_f64(v, lane, 32);
+  const int r = lane & 3;
+  comp = r == 0 ? 0 : r == 1 ? 2 : r == 2 ? 1 : 3;
+  return v;
+}
+
+// Add the wave's contributions (fx, fy, fz) to dst[0..2] (skipped if
 // all are zero).
 __device__ __forceinline__ void wave_add3(double fx, double fy, double fz, double* dst, int lane) {
   if (!__any(fx != 0.0 || fy != 0.0 || fz != 0.0)) return;
-  fx = wave_sum(fx);
-  fy = wave_sum(fy);
-  fz = wave_sum(fz);
-  if (lane == 0) {
-    atomicAdd(dst + 0, fx);
-    atomicAdd(dst + 1, fy);
-    atomicAdd(dst + 2, fz);
-  }
+  int comp = 3;
+  const double v = wave_sum3(fx, fy, fz, lane, comp);
+  if (lane < 3) atomicAdd(dst + comp, v);
 }
 
 // Part `part` of the tile's 2^plog parts (the search's level-0 sweep cut into parts:
@@ -159,16 +188,7 @@ __device__ void attract_tile(const SearchArgs& A, const AttractArgs& O, int tile
               double fx, fy, fz;
               take(active && id != i && v != 0, v, pos[3 * (int64_t)id], pos[3 * (int64_t)id + 1],
                    pos[3 * (int64_t)id + 2], fx, fy, fz);
-              if (__any(fx != 0.0 || fy != 0.0 || fz != 0.0)) {
-                fx = wave_sum(fx);
-                fy = wave_sum(fy);
-                fz = wave_sum(fz);
-                if (lane == 0) {
-                  atomicAdd(O.dpos + 3 * (int64_t)id + 0, fx);
-                  atomicAdd(O.dpos + 3 * (int64_t)id + 1, fy);
-                  atomicAdd(O.dpos + 3 * (int64_t)id + 2, fz);
-                }
-              }
+              wave_add3(fx, fy, fz, O.dpos + 3 * (int64_t)id, lane);
             }
           }
         }
