@@ -289,16 +289,21 @@ def bench_activity(msp, torch, w, steps=100):
               spikes=sp)
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t0) / steps
-        # per step: the neuron state read and written (74 B) and per synapse its
-        # endpoints, type and the source's spike (10 B), the frequency instead of the
-        # spike where approximated (+7 B), and the rank-split flag (+1 B, approx 1)
+        # per step: the neuron state read and written (74 B per neuron); a spike sent
+        # along an exact synapse (its index, target and type, the target's count: 13 B,
+        # for the synapses of the neurons that fired); an approximated synapse (its
+        # endpoints, type and the source's frequency: 17 B) and, with approx 1, the
+        # rank-split flag of every synapse (1 B)
         n_apx = 0 if approx == 0 else (m * remote if approx == 1 else m)
-        B = int(74 * w.n + 10 * m + 7 * n_apx + (m if approx == 1 else 0))
+        spikes_per_step = int(sp.item()) / steps
+        sends = spikes_per_step * (m - n_apx) / w.n
+        B = int(74 * w.n + 13 * sends + 17 * n_apx + (m if approx == 1 else 0))
         out[name] = dict(ms_per_step=sec * 1e3, neuron_steps_per_s=w.n / sec,
                          spikes=int(sp.item()), rate_hz=int(sp.item()) / w.n / (steps * 1e-3),
-                         roofline=hbm_roofline(B, sec, "74 B per neuron + 10 B per synapse "
-                                               "(+7 B approximated, +1 B rank flag) and "
-                                               "step / wall time per step"))
+                         roofline=hbm_roofline(B, sec, "74 B per neuron + 13 B per spike sent "
+                                               "along an exact synapse + 17 B per "
+                                               "approximated synapse (+1 B per synapse, "
+                                               "approx 1) and step / wall time per step"))
     # the oracle: 3 steps of the same network, all 8M neurons, one host thread
     from oracle import oracle as orc
     o = orc.Activity(w.neuron_type)

@@ -1,11 +1,16 @@
 // Electrical activity between connectivity updates (Sec. II, "Update of electrical
 // activity"), with the firing-rate approximation of Sec. IV-B. One step is 1 ms:
-//   * exchange (act_input_k, one thread per synapse): the spike a source recorded in
-//     the previous step reaches the target. Approximated synapses (approx 1: those
-//     whose two neurons carry different ranks; approx 2: all) carry a spike at step
-//     t iff u < f_i, f_i being the source's frequency over the previous epoch (spikes
-//     per step) and u = (Philox word 0 >> 11) 2^-53, key (seed, 5), counter (s, t, 0,
-//     0). Targets count excitatory and inhibitory arrivals (exact integer atomics);
+//   * exchange: the spike a source recorded in the previous step reaches the target.
+//     Exact synapses are grouped by source once per run (act_setup_k, act_group_k),
+//     and a neuron that spikes delivers along its own group into the next step's
+//     arrival counts (act_neuron_k; act_deliver_k for the spikes recorded before the
+//     run), so a step touches only the synapses of the neurons that fired.
+//     Approximated synapses (approx 1: those whose two neurons carry different ranks;
+//     approx 2: all) carry a spike at step t iff u < f_i, f_i being the source's
+//     frequency over the previous epoch (spikes per step) and u = (Philox word 0 >> 11)
+//     2^-53, key (seed, 5), counter (s, t, 0, 0) (act_approx_k, every step, one thread
+//     per synapse). Targets count excitatory and inhibitory arrivals (exact integer
+//     atomics, so the order of the deliveries does not matter);
 //   * neuron model (act_neuron_k, one thread per neuron): Izhikevich 2003, regular
 //     spiking (excitatory) or fast spiking (inhibitory):
 //       I = w_e e - w_i h + mu + width (u' - 1/2), u' from key (seed, 6), counter (g, t, 0, 0);
@@ -29,51 +34,104 @@ struct ActParams {
   int32_t delta;
 };
 
-// Per synapse: do its neurons lie in different ranks (fixed over a run, so the two
-// rank gathers are paid once, not every step). Endpoints are checked by act_input_k.
-__global__ void __launch_bounds__(kActBlock) act_remote_k(int64_t n, int64_t m,
-                                                         const int32_t* __restrict__ src,
-                                                         const int32_t* __restrict__ tgt,
-                                                         const int32_t* __restrict__ rank,
-                                                         uint8_t* __restrict__ remote) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= m) return;
-  const int32_t i = src[s], g = tgt[s];
-  remote[s] = (i >= 0 && i < n && g >= 0 && g < n && rank[i] != rank[g]) ? 1 : 0;
-}
-
-// remote (nullable): per-synapse flags of act_remote_k, for approx 1.
-__global__ void __launch_bounds__(kActBlock) act_input_k(
+// Run setup, one thread per synapse: a synapse with an endpoint outside [0, n) or a
+// type > 1 sets *err and takes no part in the run. Exact synapses are counted per
+// source (cnt); with approx 1, remote[s] = 1 marks the approximated ones (neurons of
+// different ranks: the two rank gathers are paid once per run, not every step).
+__global__ void __launch_bounds__(kActBlock) act_setup_k(
     int64_t n, int64_t m, const int32_t* __restrict__ src, const int32_t* __restrict__ tgt,
-    const uint8_t* __restrict__ stype, const uint8_t* __restrict__ remote_of, int32_t approx,
-    uint64_t seed, uint64_t t, const uint8_t* __restrict__ spk, const double* __restrict__ freq,
-    int32_t* e, int32_t* h, int32_t* err) {
+    const uint8_t* __restrict__ stype, const int32_t* __restrict__ rank, int32_t approx,
+    int32_t* cnt, uint8_t* __restrict__ remote, int32_t* err) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= m) return;
   const int32_t i = src[s], g = tgt[s];
-  const uint8_t ty = stype[s];
-  if (i < 0 || i >= n || g < 0 || g >= n || ty > 1) {
-    atomicOr(err, 1);
-    return;
-  }
-  const bool remote = approx == 2 || (approx == 1 && remote_of[s] != 0);
-  bool arrives;
-  if (remote) {
-    const double u = (double)(philox_word0(seed, 5, (uint64_t)s, t, 0, 0) >> 11) * 0x1p-53;
-    arrives = u < freq[i];
-  } else {
-    arrives = spk[i] != 0;
-  }
-  if (arrives) atomicAdd(ty ? &h[g] : &e[g], 1);
+  const bool ok = i >= 0 && i < n && g >= 0 && g < n && stype[s] <= 1;
+  if (!ok) atomicOr(err, 1);
+  const bool approxd = approx == 2 || (approx == 1 && ok && rank[i] != rank[g]);
+  if (remote) remote[s] = ok && approxd ? 1 : 0;
+  if (ok && !approxd) atomicAdd(&cnt[i], 1);
 }
 
-// The step's arrivals are consumed (and cleared for the next step) here.
+// Exact synapses by source: perm[soff[i] .. soff[i + 1]) (cur: zeroed cursors).
+__global__ void __launch_bounds__(kActBlock) act_group_k(
+    int64_t n, int64_t m, const int32_t* __restrict__ src, const int32_t* __restrict__ tgt,
+    const uint8_t* __restrict__ stype, const int32_t* __restrict__ rank, int32_t approx,
+    const int32_t* __restrict__ soff, int32_t* cur, int32_t* __restrict__ perm) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= m) return;
+  const int32_t i = src[s], g = tgt[s];
+  const bool ok = i >= 0 && i < n && g >= 0 && g < n && stype[s] <= 1;
+  const bool approxd = approx == 2 || (approx == 1 && ok && rank[i] != rank[g]);
+  if (ok && !approxd) perm[soff[i] + atomicAdd(&cur[i], 1)] = (int32_t)s;
+}
+
+// Neuron g's spike along its exact synapses, into the arrival counts e, h.
+__device__ __forceinline__ void act_send(int64_t g, const int32_t* __restrict__ soff,
+                                         const int32_t* __restrict__ perm,
+                                         const int32_t* __restrict__ tgt,
+                                         const uint8_t* __restrict__ stype, int32_t* e,
+                                         int32_t* h) {
+  const int32_t q1 = soff[g + 1];
+  for (int32_t q = soff[g]; q < q1; ++q) {
+    const int32_t s = perm[q];
+    atomicAdd(stype[s] ? &h[tgt[s]] : &e[tgt[s]], 1);
+  }
+}
+
+// The spikes recorded before the run (spk), delivered for its first step.
+__global__ void __launch_bounds__(kActBlock) act_deliver_k(
+    int64_t n, const uint8_t* __restrict__ spk, const int32_t* __restrict__ soff,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ tgt,
+    const uint8_t* __restrict__ stype, int32_t* e, int32_t* h) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n || !spk[g]) return;
+  act_send(g, soff, perm, tgt, stype, e, h);
+}
+
+// The approximated synapses of approx 1, packed in synapse order (pos: exclusive scan
+// of remote): their index (the draw's counter), endpoints and type.
+__global__ void __launch_bounds__(kActBlock) act_pack_k(
+    int64_t m, const int32_t* __restrict__ src, const int32_t* __restrict__ tgt,
+    const uint8_t* __restrict__ stype, const uint8_t* __restrict__ remote,
+    const int32_t* __restrict__ pos, int32_t* __restrict__ aidx, int32_t* __restrict__ asrc,
+    int32_t* __restrict__ atgt, uint8_t* __restrict__ atype) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= m || !remote[s]) return;
+  const int32_t q = pos[s];
+  aidx[q] = (int32_t)s;
+  asrc[q] = src[s];
+  atgt[q] = tgt[s];
+  atype[q] = stype[s];
+}
+
+// Approximated synapses at step t: the packed list of approx 1 (aidx non-null, count
+// *na), or every synapse with valid endpoints (approx 2).
+__global__ void __launch_bounds__(kActBlock) act_approx_k(
+    int64_t n, int64_t m, const int32_t* __restrict__ src, const int32_t* __restrict__ tgt,
+    const uint8_t* __restrict__ stype, const int32_t* __restrict__ aidx,
+    const int32_t* __restrict__ na, uint64_t seed, uint64_t t, const double* __restrict__ freq,
+    int32_t* e, int32_t* h) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (aidx ? (int64_t)*na : m)) return;
+  const int32_t i = src[q], g = tgt[q];
+  const uint8_t ty = stype[q];
+  if (i < 0 || i >= n || g < 0 || g >= n || ty > 1) return;     // reported at setup
+  const uint64_t s = aidx ? (uint64_t)aidx[q] : (uint64_t)q;
+  const double u = (double)(philox_word0(seed, 5, s, t, 0, 0) >> 11) * 0x1p-53;
+  if (u < freq[i]) atomicAdd(ty ? &h[g] : &e[g], 1);
+}
+
+// The step's arrivals e, h are consumed (and cleared for the step after next) here; a
+// neuron that fires sends along its exact synapses into the next step's e2, h2 (soff
+// null: no exact synapses).
 __global__ void __launch_bounds__(kActBlock) act_neuron_k(
     int64_t n, const uint8_t* __restrict__ ntype, ActParams P, uint64_t seed, uint64_t t,
     double* __restrict__ v, double* __restrict__ u, double* __restrict__ ca,
     uint8_t* __restrict__ spk, int32_t* __restrict__ count, double* __restrict__ freq,
     int32_t* __restrict__ e, int32_t* __restrict__ h, int32_t* __restrict__ last_input,
-    int64_t* __restrict__ part) {
+    int64_t* __restrict__ part, const int32_t* __restrict__ soff,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ tgt,
+    const uint8_t* __restrict__ stype, int32_t* e2, int32_t* h2) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool f = false;
   if (g < n) {
@@ -103,6 +161,7 @@ __global__ void __launch_bounds__(kActBlock) act_neuron_k(
     if (f) c = c + P.beta;
     ca[g] = c;
     spk[g] = f ? 1 : 0;
+    if (f && soff) act_send(g, soff, perm, tgt, stype, e2, h2);
     int32_t cnt = count[g] + (f ? 1 : 0);
     if ((t + 1) % (uint64_t)P.delta == 0) {
       freq[g] = (double)cnt * P.inv_delta;

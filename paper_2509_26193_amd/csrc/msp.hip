@@ -1157,33 +1157,93 @@ msp_status msp_activity_run(int64_t n, const uint8_t* neuron_type, const int32_t
   P.inv_tau = 1.0 / q.ca_tau;
   P.inv_delta = 1.0 / (double)q.epoch;
   P.delta = q.epoch;
-  Temp arr(s), err(s), part(s), remote(s);
+  Temp arr(s), err(s), part(s), grp(s);
   const int64_t nblocks = (int64_t)grid_for(n, kActBlock);
-  MSP_HIP_TRY(arr.alloc(sizeof(int32_t) * 2 * n));
+  // arrival counts (e, h) of two consecutive steps: step k consumes buffer k % 2 and its
+  // spikes are delivered into the other
+  MSP_HIP_TRY(arr.alloc(sizeof(int32_t) * 4 * n));
   MSP_HIP_TRY(err.alloc(sizeof(int32_t)));
-  int32_t* e = arr.as<int32_t>();
-  MSP_HIP_TRY(hipMemsetAsync(e, 0, sizeof(int32_t) * 2 * n, s));
+  int32_t* buf = arr.as<int32_t>();
+  MSP_HIP_TRY(hipMemsetAsync(buf, 0, sizeof(int32_t) * 4 * n, s));
   MSP_HIP_TRY(hipMemsetAsync(err.p, 0, sizeof(int32_t), s));
   if (spikes) {
     MSP_HIP_TRY(part.alloc(sizeof(int64_t) * nblocks));
     MSP_HIP_TRY(hipMemsetAsync(part.p, 0, sizeof(int64_t) * nblocks, s));
   }
-  if (approx == 1 && m > 0) {
-    MSP_HIP_TRY(remote.alloc(sizeof(uint8_t) * m));
-    act_remote_k<<<grid_for(m, kActBlock), kActBlock, 0, s>>>(n, m, syn_src, syn_tgt, rank,
-                                                              remote.as<uint8_t>());
+  const int32_t* soff = nullptr;       // exact synapses by source (null: none)
+  const int32_t* perm = nullptr;
+  // approximated synapses: approx 1 packs them (index, endpoints, type); approx 2 reads
+  // the caller's arrays
+  const int32_t *a_idx = nullptr, *a_src = syn_src, *a_tgt = syn_tgt, *a_n = nullptr;
+  const uint8_t* a_type = syn_type;
+  if (m > 0) {
+    const bool pack = approx == 1;
+    const size_t z_off = align_up(sizeof(int32_t) * (n + 1)), z_cur = align_up(sizeof(int32_t) * n),
+                 z_perm = align_up(sizeof(int32_t) * m),
+                 z_rem = pack ? align_up(sizeof(uint8_t) * m) : 0,
+                 z_pos = pack ? align_up(sizeof(int32_t) * (m + 1)) : 0,
+                 z_pk = pack ? 3 * align_up(sizeof(int32_t) * m) + align_up(m) : 0,
+                 z_scan = align_up(std::max(scan_tmp_bytes<int32_t>(n), scan_tmp_bytes<int32_t>(m)));
+    MSP_HIP_TRY(grp.alloc(z_off + z_cur + z_perm + z_rem + z_pos + z_pk + z_scan));
+    char* q = grp.as<char>();
+    auto take = [&](size_t bytes) {
+      char* r = q;
+      q += bytes;
+      return r;
+    };
+    int32_t* off = reinterpret_cast<int32_t*>(take(z_off));
+    int32_t* cur = reinterpret_cast<int32_t*>(take(z_cur));
+    int32_t* pm = reinterpret_cast<int32_t*>(take(z_perm));
+    uint8_t* rem = pack ? reinterpret_cast<uint8_t*>(take(z_rem)) : nullptr;
+    int32_t* rpos = pack ? reinterpret_cast<int32_t*>(take(z_pos)) : nullptr;
+    char* pk = take(z_pk);
+    void* scan_ws = take(z_scan);
+    MSP_HIP_TRY(hipMemsetAsync(off, 0, sizeof(int32_t) * (n + 1), s));
+    MSP_HIP_TRY(hipMemsetAsync(cur, 0, sizeof(int32_t) * n, s));
+    act_setup_k<<<grid_for(m, kActBlock), kActBlock, 0, s>>>(n, m, syn_src, syn_tgt, syn_type,
+                                                             rank, approx, off, rem,
+                                                             err.as<int32_t>());
     MSP_HIP_TRY(hipGetLastError());
+    if (pack) {
+      const size_t zi = align_up(sizeof(int32_t) * m);
+      int32_t* ai = reinterpret_cast<int32_t*>(pk);
+      int32_t* as = reinterpret_cast<int32_t*>(pk + zi);
+      int32_t* at = reinterpret_cast<int32_t*>(pk + 2 * zi);
+      uint8_t* ay = reinterpret_cast<uint8_t*>(pk + 3 * zi);
+      MSP_HIP_TRY((exclusive_scan<int32_t, uint8_t, Ident<int32_t>>(rem, rpos, m, Ident<int32_t>(),
+                                                                    true, s, scan_ws)));
+      act_pack_k<<<grid_for(m, kActBlock), kActBlock, 0, s>>>(m, syn_src, syn_tgt, syn_type, rem,
+                                                              rpos, ai, as, at, ay);
+      MSP_HIP_TRY(hipGetLastError());
+      a_idx = ai;
+      a_src = as;
+      a_tgt = at;
+      a_type = ay;
+      a_n = rpos + m;
+    }
+    if (approx != 2) {
+      MSP_HIP_TRY((exclusive_scan<int32_t, int32_t, Ident<int32_t>>(off, off, n, Ident<int32_t>(),
+                                                                    true, s, scan_ws)));
+      act_group_k<<<grid_for(m, kActBlock), kActBlock, 0, s>>>(n, m, syn_src, syn_tgt, syn_type,
+                                                               rank, approx, off, cur, pm);
+      act_deliver_k<<<grid_for(n, kActBlock), kActBlock, 0, s>>>(n, spiked, off, pm, syn_tgt,
+                                                                 syn_type, buf, buf + n);
+      MSP_HIP_TRY(hipGetLastError());
+      soff = off;
+      perm = pm;
+    }
   }
   for (int32_t k = 0; k < steps; ++k) {
     const uint64_t t = t0 + (uint64_t)k;
-    if (m > 0)
-      act_input_k<<<grid_for(m, kActBlock), kActBlock, 0, s>>>(
-          n, m, syn_src, syn_tgt, syn_type, approx == 1 ? remote.as<uint8_t>() : nullptr,
-          approx, seed, t, spiked, freq, e, e + n,
-          err.as<int32_t>());
+    int32_t* e = buf + (int64_t)(k & 1) * 2 * n;
+    int32_t* e2 = buf + (int64_t)((k + 1) & 1) * 2 * n;
+    if (m > 0 && approx >= 1)
+      act_approx_k<<<grid_for(m, kActBlock), kActBlock, 0, s>>>(
+          n, m, a_src, a_tgt, a_type, a_idx, a_n, seed, t, freq, e, e + n);
     act_neuron_k<<<grid_for(n, kActBlock), kActBlock, 0, s>>>(
         n, neuron_type, P, seed, t, v, u, calcium, spiked, epoch_count, freq, e, e + n,
-        k == steps - 1 ? last_input : nullptr, spikes ? part.as<int64_t>() : nullptr);
+        k == steps - 1 ? last_input : nullptr, spikes ? part.as<int64_t>() : nullptr, soff, perm,
+        syn_tgt, syn_type, e2, e2 + n);
     MSP_HIP_TRY(hipGetLastError());
   }
   if (spikes) {

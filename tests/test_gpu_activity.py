@@ -92,3 +92,20 @@ def test_activity_rejects_bad_synapses():
     with pytest.raises(msp.MspError):                # approx 1 needs ranks
         g.run(T(src[:10], torch.int32), T(tgt[:10], torch.int32), T(sty[:10], torch.uint8),
               seed=1, t0=0, steps=1, approx=1)
+
+
+@pytest.mark.parametrize("approx", [0, 1])
+def test_activity_split_runs_equal_one_run(approx):
+    """Runs continue from the state of the last one: the spikes recorded in a run's last
+    step reach their targets in the first step of the next run."""
+    n, m = 65536, 300000
+    ty, src, tgt, sty, rank = _net(n, m, seed=9)
+    g, o = _pair(ty, seed=10, spk_share=0.02, freq_hi=0.05)
+    args = (T(src, torch.int32), T(tgt, torch.int32), T(sty, torch.uint8))
+    g.run(*args, seed=13, t0=40, steps=70, approx=approx, rank=T(rank, torch.int32))
+    li_g = g.run(*args, seed=13, t0=110, steps=50, approx=approx, rank=T(rank, torch.int32),
+                 last_input=True)
+    total, li_o = o.run(src, tgt, sty, seed=13, t0=40, steps=120, approx=approx, rank=rank,
+                        last_input=True)
+    say(f"[activity split runs approx={approx}] {total} spikes in 120 steps")
+    _same(g, o, li_g, li_o, f"split approx {approx}")
