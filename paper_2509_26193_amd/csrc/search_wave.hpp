@@ -150,7 +150,7 @@ __device__ __forceinline__ void part_range(int32_t li, bool valid, int lane, int
 // first slot and the count. Where the launch has no more units than checkpoint
 // regions (W.ck_units, one per tile of the largest launch), every unit has a region
 // of its own; otherwise the parts of a tile share its region equally.
-__device__ __forceinline__ void unit_slots(const SweepOut& W, int slots, bool own, int64_t tile,
+__device__ __forceinline__ void unit_slots(int slots, bool own, int64_t tile,
                                            int plog, int part, int64_t unit, int64_t& first,
                                            int& count) {
   if (own) {
@@ -244,7 +244,7 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
     }
     int64_t ck0 = 0;                        // this unit's checkpoint slots
     int ns = 0;
-    unit_slots(W, SLOTS, own, tile, plog, part, unit, ck0, ns);
+    unit_slots(SLOTS, own, tile, plog, part, unit, ck0, ns);
     int32_t* ckx = W.ck_x + ck0;
     double* ckP = W.ck_P + ck0 * kWave + lane;
     int32_t* ckme = W.ck_me + ck0 * kWave + lane;
@@ -405,7 +405,7 @@ __device__ __forceinline__ void draw_slot(const SearchArgs& A, const DiagOut& D,
         const int nck = W.nck[u0 + k];
         int64_t ck0 = 0;
         int ns = 0;
-        unit_slots(W, SLOTS, own, tile, plog, k, u0 + k, ck0, ns);
+        unit_slots(SLOTS, own, tile, plog, k, u0 + k, ck0, ns);
         const int32_t* ckx = W.ck_x + ck0;
         const double* ckP = W.ck_P + ck0 * kWave + lane;
         const int32_t* ckme = W.ck_me + ck0 * kWave + lane;
