@@ -152,10 +152,17 @@ def cpu_baseline(w, gpu_target, sample, threads):
     ts = time.time() - t0
     differ = int((r["target"] != gpu_target[q]).sum())
     outside = int(((r["target"] != gpu_target[q]) & ~(r["window"] < 1e-6)).sum())
+    # the same oracle on one thread, on the first 5000 of those searches
+    q1 = q[:5000]
+    t0 = time.time()
+    t.find_targets(w.neuron_type, w.sigma, w.theta, w.seed, w.step, src[q1], elem[q1], nthreads=1)
+    t1 = time.time() - t0
     return dict(value=m / ts, unit="searches/s", cores=threads, kind="oracle",
                 sample=(f"{m} random searches of the {src.size} in one update of {w.name} "
                         f"(fp64 oracle, OpenMP {threads} threads); tree build {tb:.1f} s and "
                         f"refresh {tr:.1f} s not included"),
+                one_thread=dict(value=q1.size / t1, unit="searches/s",
+                                sample=f"the first {q1.size} of those searches, 1 thread"),
                 parity=dict(sampled=m, differing=differ, outside_window=outside))
 
 
