@@ -114,7 +114,7 @@ msp_status msp_update_vacant_counts(msp_octree t, const int32_t* vac_dend_exc,
  * then only elem_offset_out is written (elem_offset_out[n] = S sizes the buffer);
  * MSP_ERR_INVALID for sigma <= 0, theta < 0, a negative vac_axon or a type > 1
  * (the last two found on the device before the search: target_out is not written).
- * Working memory: about 60 B per neuron plus the search checkpoints, up to 3 KB per
+ * Working memory: about 200 B per neuron plus the search checkpoints, up to 3 KB per
  * neuron but never more than an eighth of the device's memory. The library keeps it
  * per device between calls and grows it when a larger search needs more (it is held
  * until the process ends; MSP_ERR_OOM if it cannot be had). Searches on one device
