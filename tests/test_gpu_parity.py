@@ -77,6 +77,13 @@ def test_tree_and_search_degenerate(case):
     assert np.array_equal(g["off"], off)
     o = t.find_targets(w.neuron_type, w.sigma, w.theta, w.seed, w.step, src, elem)
     compare_search(g["target"], g["z0"], o, case)
+    # every tile's walk cut into 8 parts: cuts in buckets, near the ends, empty parts
+    tgt, _, z0, lv, cnt = msp.find_targets(g["tree"], g["ty"], g["va"], w.sigma, w.theta, w.seed,
+                                           w.step, diag=True, counters=True, parts=8)
+    torch.cuda.synchronize()
+    compare_search(tgt.cpu().numpy().astype(np.int64), z0.cpu().numpy(), o, f"{case} 8 parts")
+    assert np.array_equal(cnt["visits"].cpu().numpy(), g["visits"]), case
+    assert np.array_equal(lv.cpu().numpy(), g["levels"]), case
     g["tree"].free()
 
 
