@@ -112,9 +112,10 @@ __device__ __forceinline__ NodeRec load_rec(cptr<NodeRec> R, int64_t x) {
 // The pre-order range [x_lo, x_hi) of part `part` of a tile cut into 2^plog parts
 // (wave-uniform; every wave that walks a part of the tile finds the same cuts). The
 // cuts lie around m, the median of the sources' leaf positions, at m - c s and m + c s
-// for a ladder of multipliers c, s being the sources' leaf range (at least 64),
-// clamped into [1, end]: the union walk's steps are densest around the sources and
-// thin out with the distance from them along the pre-order.
+// for a ladder of multipliers c (8 parts: 1, 8, 64; 4 parts: 4; 2 parts: m alone), s
+// being the sources' leaf range (at least 64), clamped into [1, end]: the union walk's
+// steps are densest around the sources and thin out with the distance from them along
+// the pre-order.
 __device__ __forceinline__ void part_range(int32_t li, bool valid, int lane, int plog, int part,
                                            int32_t end, int32_t& x_lo, int32_t& x_hi) {
   const int32_t key = valid ? li : INT32_MAX;
@@ -164,7 +165,7 @@ __device__ __forceinline__ void unit_slots(int slots, bool own, int64_t tile,
 
 // A lane's mask end at node x0 > 1 of a walk that starts there: the end of the
 // subtree of the first ancestor of x0 that the lane's own walk does not enter
-// (accepted, or holding no vacancy), else 0 (the lane is active at x0). The
+// (accepted, or holding no vacancy), else `me` unchanged (the lane is active at x0). The
 // ancestors are found by following the pre-order from the root's first child:
 // over a subtree that ends at or before x0, into one that holds it.
 template <bool OWN>
