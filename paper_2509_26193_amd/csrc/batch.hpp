@@ -298,12 +298,13 @@ struct FlatSource {             // flat Morton position g is a type-`want` sourc
 // Tiles per simulation: excitatory sources padded to a multiple of 64, then
 // inhibitory ones, so no tile mixes simulations or types. A simulation with few tiles
 // cuts each into 2^p parts (p <= kPartLogMax): as many as keep its units within
-// kPartUnits and, for a launch with checkpoints, within its share of the checkpoint
-// regions (one per 64 neurons, so every unit keeps a region of its own); else 2 parts
-// sharing each tile's region where that stays within kPartUnits. p depends on the
-// simulation alone, so a simulation's results do not depend on the batch it runs in
-// (force >= 0: p = force). One thread. Also writes the unit count and the number of
-// sources (the length of the Hilbert sort).
+// kPartUnits and, for a launch with checkpoints, within one checkpoint region per 64 of
+// its neurons (every launch has at least that many); else 2 parts where that stays
+// within 2 kPartUnits (a launch has up to twice those regions where memory allows, else
+// the two parts share their tile's region). p depends on the simulation alone, so a
+// simulation's results do not depend on the batch it runs in (force >= 0: p = force).
+// One thread. Also writes the unit count and the number of sources (the length of the
+// Hilbert sort).
 __global__ void b_tiles_k(BatchDev B, int32_t* tile_count, int32_t* unit_count,
                           int32_t* sources, int64_t total, int force, bool ckpt) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -320,7 +321,7 @@ __global__ void b_tiles_k(BatchDev B, int32_t* tile_count, int32_t* unit_count,
       const int64_t lim = ckpt && regions < kPartUnits ? regions : kPartUnits;
       p = 0;
       while (p < kPartLogMax && ((int64_t)ts << (p + 1)) <= lim) ++p;
-      if (p == 0 && 2 * (int64_t)ts <= kPartUnits) p = 1;
+      if (p == 0 && 2 * (int64_t)ts <= 2 * (int64_t)kPartUnits) p = 1;
     }
     B.plog[s] = (uint8_t)p;
     t += ts;
@@ -435,8 +436,8 @@ inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 inline int64_t max_tiles_for(int64_t total_n, int nsims) { return total_n / kWave + 2 * nsims + 1; }
 
 // Sweep units: a simulation has at most 2^kPartLogMax units per tile, and more units
-// than tiles only while they stay within kPartUnits; with the parts forced to 2^force
-// (force >= 0), exactly that many per tile.
+// than tiles only while they stay within kPartUnits or, with 2 parts, while its tiles do;
+// with the parts forced to 2^force (force >= 0), exactly that many per tile.
 inline int64_t max_units_for(int64_t total_n, int nsims, int force = -1) {
   const int64_t mt = max_tiles_for(total_n, nsims);
   if (force >= 0) return mt << force;
@@ -453,7 +454,9 @@ struct ScratchSizes {
 constexpr size_t kCkptSlotBytes = sizeof(int32_t) + kWave * (sizeof(double) + sizeof(int32_t));
 
 // `slots` checkpoint slots per tile (0: no checkpoints, for launches without draws).
-inline ScratchSizes scratch_sizes(int64_t total_n, int nsims, int slots, int force = -1) {
+// regions: checkpoint regions of `slots` slots (< 0: one per tile).
+inline ScratchSizes scratch_sizes(int64_t total_n, int nsims, int slots, int force = -1,
+                                  int64_t regions = -1) {
   ScratchSizes z;
   const int64_t mt = max_tiles_for(total_n, nsims);
   const int64_t ms = mt * kWave;
@@ -468,9 +471,10 @@ inline ScratchSizes scratch_sizes(int64_t total_n, int nsims, int slots, int for
   z.Z = align_up(sizeof(double) * mu * kWave);
   z.v = align_up(sizeof(int32_t) * mu * kWave);
   z.nck = align_up(sizeof(int32_t) * mu);
-  z.ckx = align_up(sizeof(int32_t) * mt * slots);
-  z.ckP = align_up(sizeof(double) * mt * slots * kWave);
-  z.ckme = align_up(sizeof(int32_t) * mt * slots * kWave);
+  const int64_t mr = regions < 0 ? mt : regions;
+  z.ckx = align_up(sizeof(int32_t) * mr * slots);
+  z.ckP = align_up(sizeof(double) * mr * slots * kWave);
+  z.ckme = align_up(sizeof(int32_t) * mr * slots * kWave);
   z.counters = align_up(sizeof(int32_t) * (3 + kXcd));
   z.scan = align_up(std::max(scan_tmp_bytes<int64_t>(total_n), scan_tmp_bytes<int32_t>(total_n)));
   z.srct = align_up(sizeof(uint8_t) * total_n);
@@ -484,8 +488,9 @@ inline ScratchSizes scratch_sizes(int64_t total_n, int nsims, int slots, int for
 }
 
 inline SearchScratch carve(void* base, int64_t total_n, int nsims, int slots,
-                           const SimDesc* d_sims, const int64_t* d_nbase, int force = -1) {
-  const ScratchSizes z = scratch_sizes(total_n, nsims, slots, force);
+                           const SimDesc* d_sims, const int64_t* d_nbase, int force = -1,
+                           int64_t regions = -1) {
+  const ScratchSizes z = scratch_sizes(total_n, nsims, slots, force, regions);
   char* p = static_cast<char*>(base);
   auto take = [&](size_t bytes) {
     char* q = p;
@@ -513,7 +518,7 @@ inline SearchScratch carve(void* base, int64_t total_n, int nsims, int slots,
   S.W.ck_P = reinterpret_cast<double*>(take(z.ckP));
   S.W.ck_me = reinterpret_cast<int32_t*>(take(z.ckme));
   S.W.ck_slots = slots;
-  S.W.ck_units = max_tiles_for(total_n, nsims);
+  S.W.ck_units = regions < 0 ? max_tiles_for(total_n, nsims) : regions;
   S.counters = reinterpret_cast<int32_t*>(take(z.counters));
   S.W.tile_count = S.counters;
   S.W.unit_count = S.counters + 2 + kXcd;

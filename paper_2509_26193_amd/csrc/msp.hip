@@ -138,10 +138,13 @@ hipError_t sweep_blocks_for(int device, bool diag, int64_t max_units, double fra
   return hipSuccess;
 }
 
-// Checkpoint slots per tile: kCkptMax if those arrays fit in an eighth of the device's
-// memory, else kCkptMin. More slots mean shorter re-walks in the draw kernel; the
-// targets do not depend on the choice.
-hipError_t ck_slots_for(int device, int64_t total_n, int nsims, int* slots_out) {
+// Checkpoint slots per region: kCkptMax if one region per tile fits in an eighth of the
+// device's memory, else kCkptMin. More slots mean shorter re-walks in the draw kernel;
+// the targets do not depend on the choice. Regions: one per tile, and as many more as
+// that eighth holds up to twice that (automatic parts) or the forced parts' units, so
+// that most launches cut into parts give every part a region of its own.
+hipError_t ck_slots_for(int device, int64_t total_n, int nsims, int force, int* slots_out,
+                        int64_t* regions_out) {
   static size_t mem[64] = {};
   if (device < 0 || device >= 64) return hipErrorInvalidDevice;
   if (mem[device] == 0) {
@@ -150,9 +153,13 @@ hipError_t ck_slots_for(int device, int64_t total_n, int nsims, int* slots_out) 
     if (e != hipSuccess) return e;
     mem[device] = p.totalGlobalMem;
   }
-  const double tiles = (double)max_tiles_for(total_n, nsims);
-  *slots_out = tiles * kCkptMax * (double)kCkptSlotBytes <= (double)(mem[device] / 8) ? kCkptMax
-                                                                                      : kCkptMin;
+  const int64_t mt = max_tiles_for(total_n, nsims);
+  const double budget = (double)(mem[device] / 8);
+  const int slots = (double)mt * kCkptMax * (double)kCkptSlotBytes <= budget ? kCkptMax : kCkptMin;
+  const int64_t want = force >= 0 ? (mt << force) : 2 * mt;
+  const int64_t fit = (int64_t)(budget / ((double)slots * (double)kCkptSlotBytes));
+  *slots_out = slots;
+  *regions_out = std::max(mt, std::min(want, fit));
   return hipSuccess;
 }
 
@@ -426,11 +433,12 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
     force = pp == 1 ? 0 : pp == 2 ? 1 : pp == 4 ? 2 : 3;
   }
   int slots = 0;
-  MSP_HIP_TRY(ck_slots_for(t->device, n, 1, &slots));
+  int64_t regions = 0;
+  MSP_HIP_TRY(ck_slots_for(t->device, n, 1, force, &slots, &regions));
   WorkspaceLease ws(t->device);
   void* scratch = nullptr;
   // the workspace also holds the simulation descriptor and the neuron bases
-  const size_t body = scratch_sizes(n, 1, slots, force).total;
+  const size_t body = scratch_sizes(n, 1, slots, force, regions).total;
   MSP_HIP_TRY(ws.acquire(body + align_up(sizeof(SimDesc)) + align_up(sizeof(hbase)), s,
                          &scratch));
   SimDesc* dsim = reinterpret_cast<SimDesc*>(static_cast<char*>(scratch) + body);
@@ -438,7 +446,7 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
                                               align_up(sizeof(SimDesc)));
   MSP_HIP_TRY(hipMemcpyAsync(dsim, &h, sizeof(SimDesc), hipMemcpyHostToDevice, s));
   MSP_HIP_TRY(hipMemcpyAsync(dbase, hbase, sizeof(hbase), hipMemcpyHostToDevice, s));
-  SearchScratch S = carve(scratch, n, 1, slots, dsim, dbase, force);
+  SearchScratch S = carve(scratch, n, 1, slots, dsim, dbase, force, regions);
   S.own_cell = own_cell_needed(t, theta);
   if (any) S.W.wave_steps = reinterpret_cast<unsigned long long*>(diag->wave_steps);
   MSP_HIP_TRY(enqueue_prep(S, n, s, force));
@@ -695,7 +703,8 @@ struct msp_batch_s {
   bool staged_pending;
   unsigned sweep_blocks;
   int draw_block;
-  int ck_slots;             // checkpoint slots per tile
+  int ck_slots;             // checkpoint slots per region
+  int64_t ck_regions;       // checkpoint regions
   bool tuned;
   bool captured_own;        // own-cell test of the captured sweep
   hipGraphExec_t exec;
@@ -812,8 +821,10 @@ msp_status msp_batch_create(const msp_sim* sims, int32_t n_sims, int32_t flags, 
   hipError_t e = hipHostMalloc((void**)&b->h_sims, sizeof(SimDesc) * n_sims, hipHostMallocDefault);
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_sims, sizeof(SimDesc) * n_sims);
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_nbase, sizeof(int64_t) * (n_sims + 1));
-  if (e == hipSuccess) e = ck_slots_for(dev, total, n_sims, &b->ck_slots);
-  if (e == hipSuccess) e = hipMalloc(&b->scratch, scratch_sizes(total, n_sims, b->ck_slots).total);
+  b->ck_regions = 0;
+  if (e == hipSuccess) e = ck_slots_for(dev, total, n_sims, -1, &b->ck_slots, &b->ck_regions);
+  if (e == hipSuccess)
+    e = hipMalloc(&b->scratch, scratch_sizes(total, n_sims, b->ck_slots, -1, b->ck_regions).total);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
   b->cap_stream = nullptr;
   if (e == hipSuccess && (flags & MSP_BATCH_GRAPH))
@@ -827,7 +838,7 @@ msp_status msp_batch_create(const msp_sim* sims, int32_t n_sims, int32_t flags, 
     batch_release(b);
     return e == hipErrorOutOfMemory ? MSP_ERR_OOM : MSP_ERR_HIP;
   }
-  b->S = carve(b->scratch, total, n_sims, b->ck_slots, b->d_sims, b->d_nbase);
+  b->S = carve(b->scratch, total, n_sims, b->ck_slots, b->d_sims, b->d_nbase, -1, b->ck_regions);
   *out = b;
   return MSP_OK;
 }
