@@ -1072,9 +1072,11 @@ msp_status msp_plasticity_step(int64_t n, const msp_plasticity_params* params, u
                  z_v = align_up(sizeof(int32_t) * m), z_pos = align_up(sizeof(int32_t) * (m + 1)),
                  z_exc = align_up(sizeof(int32_t) * n), z_sort = align_up(radix_sort_ws_bytes(m)),
                  z_scan = align_up(scan_tmp_bytes<int32_t>(m)),
-                 z_ty = align_up(sizeof(uint8_t) * m);
+                 z_ty = align_up(sizeof(uint8_t) * m),
+                 z_sel = align_up(sizeof(DelSelect)) + align_up(sizeof(uint32_t) * 256);
     Temp tmp(s);
-    MSP_HIP_TRY(tmp.alloc(z_dead + 2 * z_k + 4 * z_v + z_pos + z_exc + z_sort + z_scan + z_ty));
+    MSP_HIP_TRY(tmp.alloc(z_dead + 2 * z_k + 4 * z_v + z_pos + z_exc + z_sort + z_scan + z_ty +
+                          z_sel));
     char* q = tmp.as<char>();
     auto take = [&](size_t bytes) {
       char* r = q;
@@ -1092,13 +1094,26 @@ msp_status msp_plasticity_step(int64_t n, const msp_plasticity_params* params, u
     void* scan_ws = take(z_scan);
     const SynList O{reinterpret_cast<int32_t*>(take(z_v)), reinterpret_cast<int32_t*>(take(z_v)),
                     reinterpret_cast<uint8_t*>(take(z_ty))};
+    char* sel = take(z_sel);
+    DelSelect* st = reinterpret_cast<DelSelect*>(sel);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(sel + align_up(sizeof(DelSelect)));
     MSP_HIP_TRY(hipMemsetAsync(dd, 0, sizeof(uint8_t) * m, s));
     const int64_t n_del = (int64_t)std::floor(p.delete_fraction * (double)m + 0.5);
     if (n_del > 0) {
+      // the n_del synapses of smallest (priority, index): a radix selection of the
+      // threshold key, most significant digit first, then one marking pass
       del_keys_k<<<grid_for(m, kPlastBlock), kPlastBlock, 0, s>>>(k0, v0, m, seed, step);
-      MSP_HIP_TRY(radix_sort_pairs_ws(k0, v0, k1, v1, m, 64, s, sort_ws));
-      drop_first_k<<<grid_for(n_del, kPlastBlock), kPlastBlock, 0, s>>>(
-          v0, n_del < m ? n_del : m, L, n, dd, bound);
+      del_select_init_k<<<1, 256, 0, s>>>(st, n_del < m ? n_del : m, hist);
+      const unsigned hg = std::min(grid_for(m, kPlastBlock), 2048u);
+      for (int shift = 56; shift >= 0; shift -= 8) {
+        del_select_hist_k<<<hg, kPlastBlock, 0, s>>>(k0, m, st, shift, hist);
+        del_select_pick_k<<<1, 256, 0, s>>>(st, hist, shift);
+      }
+      MSP_HIP_TRY((exclusive_scan<int32_t, uint64_t, DelTie>(k0, pos, m, DelTie{st}, false, s,
+                                                             scan_ws)));
+      del_select_mark_k<<<grid_for(m, kPlastBlock), kPlastBlock, 0, s>>>(k0, m, st, pos, L, n, dd,
+                                                                        bound);
+      MSP_HIP_TRY(hipGetLastError());
     }
     int owner_bits = 1;
     while (owner_bits < 31 && ((int64_t)1 << owner_bits) < n) ++owner_bits;

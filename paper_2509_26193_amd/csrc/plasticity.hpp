@@ -66,16 +66,87 @@ __global__ void __launch_bounds__(kPlastBlock) del_keys_k(uint64_t* __restrict__
   val[s] = (int32_t)s;
 }
 
-// The first `cnt` synapses in sorted order go.
-__global__ void __launch_bounds__(kPlastBlock) drop_first_k(const int32_t* __restrict__ val,
-                                                           int64_t cnt, SynList L, int64_t n,
-                                                           uint8_t* __restrict__ dead,
-                                                           int32_t* bound) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= cnt) return;
-  const int64_t s = val[q];
-  dead[s] = 1;
-  unbind(L, s, n, bound);
+// Deletion as a selection, not a sort: the `want` synapses of smallest (priority,
+// index) go. Most significant digit first, each pass narrows the candidates to the
+// keys that share the digits chosen so far, and counts the candidates' next digit.
+struct DelSelect {
+  uint64_t prefix;              // digits chosen so far (the threshold key, at the end)
+  uint64_t mask;                // their bits
+  int64_t want;                 // synapses still to choose among the candidates
+};
+
+__global__ void del_select_init_k(DelSelect* st, int64_t want, uint32_t* hist) {
+  if (threadIdx.x == 0) {
+    st->prefix = 0;
+    st->mask = 0;
+    st->want = want;
+  }
+  hist[threadIdx.x] = 0;        // 256 threads
+}
+
+// Histogram of digit (key >> shift) & 255 over the keys that match the chosen digits.
+__global__ void __launch_bounds__(kPlastBlock) del_select_hist_k(const uint64_t* __restrict__ key,
+                                                                int64_t m, const DelSelect* st,
+                                                                int shift, uint32_t* hist) {
+  __shared__ uint32_t h[256];
+  for (int d = threadIdx.x; d < 256; d += blockDim.x) h[d] = 0;
+  __syncthreads();
+  const uint64_t prefix = st->prefix, mask = st->mask;
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < m;
+       s += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = key[s];
+    if ((k & mask) == prefix) atomicAdd(&h[(k >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < 256; d += blockDim.x)
+    if (h[d]) atomicAdd(&hist[d], h[d]);
+}
+
+// One block of 256 threads: the digit whose candidates hold the want-th smallest key;
+// the candidates with smaller digits are all chosen. Clears the histogram.
+__global__ void __launch_bounds__(256) del_select_pick_k(DelSelect* st, uint32_t* hist,
+                                                         int shift) {
+  __shared__ int64_t c[256];
+  const int d = threadIdx.x;
+  const int64_t h = hist[d];
+  c[d] = h;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {             // inclusive scan (Hillis-Steele)
+    const int64_t v = d >= o ? c[d - o] : 0;
+    __syncthreads();
+    c[d] += v;
+    __syncthreads();
+  }
+  const int64_t before = c[d] - h;
+  const int64_t want = st->want;
+  __syncthreads();
+  if (h > 0 && before < want && want <= c[d]) {
+    st->prefix |= (uint64_t)d << shift;
+    st->mask |= (uint64_t)255 << shift;
+    st->want = want - before;
+  }
+  hist[d] = 0;
+}
+
+// Keys equal to the threshold (in index order, so ties go as a stable sort would).
+struct DelTie {
+  const DelSelect* st;
+  __device__ int32_t operator()(uint64_t k, int64_t) const { return k == st->prefix ? 1 : 0; }
+};
+
+// Below the threshold key, or among its first `want` ties (tie_pos: exclusive scan of
+// the ties), a synapse goes.
+__global__ void __launch_bounds__(kPlastBlock) del_select_mark_k(
+    const uint64_t* __restrict__ key, int64_t m, const DelSelect* st,
+    const int32_t* __restrict__ tie_pos, SynList L, int64_t n, uint8_t* __restrict__ dead,
+    int32_t* bound) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= m) return;
+  const uint64_t k = key[s], kt = st->prefix;
+  if (k < kt || (k == kt && tie_pos[s] < st->want)) {
+    dead[s] = 1;
+    unbind(L, s, n, bound);
+  }
 }
 
 __global__ void __launch_bounds__(kPlastBlock) excess_k(const int32_t* __restrict__ bound_k,
