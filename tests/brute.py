@@ -231,6 +231,109 @@ class InsertTree:
             S = ch[1]
         raise RuntimeError("restart chain longer than the tree depth")
 
+    def bh_list_counted(self, agg, vac, i, start, sigma, theta):
+        """bh_list with the work of the expansion counted, written out separately:
+        node records examined (the start node once, every node reached below it,
+        skipped ones included, a bucket leaf once) and nodes replaced by their
+        children (the start node included when it is inner)."""
+        xi = self.pos[i]
+        out = []
+        cnt = [0, 0]                      # visits, opens
+
+        def w_of(v, c):
+            d2 = sqdist(xi[0] - c[0], xi[1] - c[1], xi[2] - c[2])
+            return float(v) * math.exp(-(d2 / (sigma * sigma))), d2
+
+        def members(c):
+            for j in sorted(c.members):
+                if j != i and vac[j] > 0:
+                    out.append(("n", j, w_of(vac[j], self.pos[j])[0]))
+
+        def visit(c):
+            cnt[0] += 1
+            v, cen = agg[id(c)]
+            if v == 0:
+                return
+            if c.leaf:
+                members(c)
+                return
+            if self.contains(c, i):
+                op = True
+            else:
+                l = math.ldexp(self.L, -c.depth)
+                op = not (l * l < (theta * theta) * w_of(v, cen)[1])
+            if not op:
+                out.append(("c", c, w_of(v, cen)[0]))
+                return
+            cnt[1] += 1
+            for d in sorted(c.kids):
+                visit(c.kids[d])
+
+        cnt[0] += 1
+        if start.leaf:
+            if agg[id(start)][0] > 0:
+                members(start)
+        else:
+            cnt[1] += 1
+            for d in sorted(start.kids):
+                visit(start.kids[d])
+        return out, cnt[0], cnt[1]
+
+    def search_full(self, agg, vac, i, j, sigma, theta, seed, step):
+        """One search with every per-search output of the method's checker: target,
+        level-0 normaliser, the levels drawn, the node records examined and the nodes
+        opened over all levels, and the boundary distance of the draw: at each level
+        the chosen entry covers [P_prev / Z, P / Z) of the cumulative distribution
+        (running sums in list order), its distance is min(u - P_prev / Z, P / Z - u),
+        and the search's is the smallest over its levels (1 if it never draws).
+        Returns a dict, and for each level the exact rational bounds of the chosen
+        entry (Fractions of the same float weights) so that callers can check the
+        float distance against exact arithmetic."""
+        S = self.root
+        res = dict(target=-1, z0=None, window=1.0, levels=0, visits=0, opens=0)
+        exact = []
+        for level in range(64):
+            lst, nv, no = self.bh_list_counted(agg, vac, i, S, sigma, theta)
+            res["visits"] += nv
+            res["opens"] += no
+            res["levels"] += 1
+            Z = 0.0
+            for e in lst:
+                Z = Z + e[2]
+            if res["z0"] is None:
+                res["z0"] = Z
+            if not lst or Z == 0.0:
+                res["target"] = -1
+                return res, exact
+            u, _ = philox_u(seed, 0, (i, j, step, level))
+            T = u * Z
+            P = 0.0
+            k = None
+            prefix = []
+            for n_, e in enumerate(lst):
+                prev = P
+                P = P + e[2]
+                prefix.append((prev, P))
+                if P > T:
+                    k = n_
+                    break
+            if k is None:                     # rounding: the last entry with weight
+                k = max(n_ for n_, e in enumerate(lst) if e[2] > 0.0)
+                lo = hi = Z
+            else:
+                lo, hi = prefix[k]
+            res["window"] = min(res["window"], min(abs(u - lo / Z), abs(hi / Z - u)))
+            ws = [Fraction(e[2]) for e in lst]
+            Ze = sum(ws, Fraction(0))
+            exact.append((Fraction(u), sum(ws[:k], Fraction(0)) / Ze,
+                          sum(ws[:k + 1], Fraction(0)) / Ze))
+            ch = lst[k]
+            if ch[0] == "n":
+                res["target"] = ch[1]
+                return res, exact
+            S = ch[1]
+        raise RuntimeError("restart chain longer than the tree depth")
+
     def implied_distribution(self, agg, vac, i, sigma, theta):
         """Exact P(target = g | source i) of the restart process, as a dict; the mass
         of 'no target' is under key -1."""

@@ -218,6 +218,62 @@ def test_search_matches_independent_python_bh(theta):
     assert theta < 0.3 or r["levels"].max() > 1
 
 
+def _counted_cases():
+    """(label, positions, cube edge) for the per-search output pins: the 120-neuron
+    cube of the theta sweep and the degenerate trees."""
+    rng = np.random.default_rng(21)
+    cases = [("uniform120", uniform_cube(120, 1000.0, seed=21).pos)]
+    for k, pos in enumerate(_tree_cases()):
+        if pos.shape[0] >= 2:
+            cases.append((f"tree{k}", pos))
+    cases.append(("outside", rng.uniform(-300, 1300, size=(80, 3))))
+    return cases
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.2, 0.3, 0.5, 0.9])
+def test_window_and_work_counters_match_independent_search(theta):
+    """The oracle's boundary distance of the draw (the only quantity that excuses a
+    differing choice) and its visit/open counters (the numerator of the roofline) per
+    search, against an independent Barnes-Hut written from Sec. III-B ("Division of
+    work": the list, the draw by probability, the restart): bitwise equal, and the
+    distance equal to exact rational arithmetic on the same weights to 1e-12."""
+    for label, pos in _counted_cases():
+        n = pos.shape[0]
+        rng = np.random.default_rng(7 + n)
+        ve = rng.integers(0, 4, size=n).astype(np.int32)
+        vi = rng.integers(0, 4, size=n).astype(np.int32)
+        va = rng.integers(0, 3, size=n).astype(np.int32)
+        ty = (rng.random(n) < 0.3).astype(np.uint8)
+        t = orc.OracleTree(pos, np.zeros(3), 1000.0)
+        t.update_counts(ve, vi)
+        off, src, elem = orc.search_list(va)
+        sigma = 300.0
+        r = t.find_targets(ty, sigma, theta, 9, 4, src, elem)
+        ref = brute.InsertTree(pos, (0.0, 0.0, 0.0), 1000.0)
+        vacs = [[int(x) for x in ve], [int(x) for x in vi]]
+        aggs = [ref.aggregate(vacs[0]), ref.aggregate(vacs[1])]
+        restarts = 0
+        for q in range(src.size):
+            i, j = int(src[q]), int(elem[q])
+            k = int(ty[i])
+            b, exact = ref.search_full(aggs[k], vacs[k], i, j, sigma, theta, 9, 4)
+            assert r["target"][q] == b["target"], (label, q)
+            assert r["levels"][q] == b["levels"], (label, q)
+            assert r["visits"][q] == b["visits"], (label, q, r["visits"][q], b["visits"])
+            assert r["opens"][q] == b["opens"], (label, q, r["opens"][q], b["opens"])
+            assert r["window"][q] == b["window"], (label, q, r["window"][q], b["window"])
+            # the chosen entry's exact interval holds u, and the float distance is the
+            # exact one up to the rounding of the running sums
+            we = 1.0
+            for u, lo, hi in exact:
+                assert lo - 1e-12 <= u <= hi + 1e-12, (label, q)
+                we = min(we, float(min(u - lo, hi - u)))
+            assert abs(r["window"][q] - we) <= 1e-12, (label, q)
+            restarts += max(0, b["levels"] - 1)
+        if theta >= 0.3 and label == "uniform120":
+            assert restarts > 0            # restart levels are exercised
+
+
 def test_targets_valid_and_never_self():
     w = uniform_cube(2000, 1000.0, seed=4)
     t = orc.OracleTree(w.pos, w.box_min, w.box_edge)
