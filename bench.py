@@ -24,10 +24,28 @@ sys.path.insert(0, ROOT)
 HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
 EXP2_PEAK = 256 * 64 * 2.4e9 / 4   # float32 exp2 per second, quarter-rate transcendental
 FP64_VECTOR_PEAK = 78.6e12  # MI355X fp64 vector FLOP/s (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
+# vector lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, every
+# vector operation (an FMA included) counted once (= the fp64 vector peak / 2)
+VALU_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 REC_BYTES = 16             # one per-type node record {x, y, z, count} at 4 bytes each
 OPEN_BYTES = 8             # child link + mask + depth of an opened node
 SRC_BYTES = 16             # source record
 OUT_BYTES = 4              # one int32 target
+# vector operations the method needs per source and level-0 record (the survey's
+# per-visit figure): a record with vacancy 8 (3 differences and 3 multiply-adds for
+# d^2, the theta^2 d^2 product and its compare), an accepted entry 3 more (exp2, the
+# product with v, the running sum), a record without vacancy 1 (the zero test)
+OPS_VISIT, OPS_ENTRY, OPS_EMPTY = 8, 3, 1
+WALK_REC_BYTES = 32        # the 32-byte record one wave step of the shared walk loads
+WALK_SRC_BYTES = 40        # per source: position 24 B, leaf 4 B, worklist 4 B, Z out 8 B
+PAPER_CONTEXT = dict(
+    value=0.93e6, unit="searches/s",
+    hardware="1024 MPI ranks on Lichtenberg 2 nodes (2x Intel Xeon Platinum 8470Q, 52 cores "
+             "each, 2.1 GHz; InfiniBand HDR100)",
+    workload="1024 x 65,536 neurons, theta 0.2, 10 connectivity updates",
+    note="derived, not printed: at least 67.1 M searches (one per neuron on the first "
+         "update) in the 72 s of Barnes-Hut computation (Sec. V-B, V-E); another workload "
+         "and machine, context only (vs_baseline stays null)")
 
 
 def log(msg):
@@ -72,6 +90,43 @@ def sweep_bytes(cnt, off):
     return int((REC_BYTES * v0[first] + OPEN_BYTES * o0[first] + SRC_BYTES).sum())
 
 
+def sweep_alu_ops(cnt, off):
+    """Vector operations the method needs in the level-0 sweep, from the exact
+    per-search counters of one counting launch (first element of every source)."""
+    first = off[:-1][np.diff(off) > 0]
+    v0 = cnt["visits0"][first].astype(np.int64)
+    o0 = cnt["opens0"][first].astype(np.int64)
+    e0 = cnt["entries0"][first].astype(np.int64)
+    empty = np.maximum(v0 - o0 - e0, 0)
+    return int((OPS_VISIT * (v0 - empty) + OPS_ENTRY * e0 + OPS_EMPTY * empty).sum())
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def measured_counters(workload):
+    """Issue counters of the sweep from the committed rocprofv3 summary, if they were
+    taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "search_sweep_counters.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = d.get(workload)
+    if not e or e.get("kernel_sources") != kernel_sources_hash():
+        return None
+    return e
+
+
 def oracle_threads():
     """Host threads the oracle runs on: every core, at most 64."""
     return min(os.cpu_count() or 1, 64)
@@ -89,6 +144,16 @@ def hbm_roofline(bytes_, seconds, what):
     return dict(bound="hbm", unit="GB/s", achieved=bytes_ / seconds / 1e9,
                 peak=HBM_PEAK / 1e9, frac=bytes_ / seconds / HBM_PEAK, bytes=int(bytes_),
                 basis=what)
+
+
+def alu_roofline(ops, logical_bytes, seconds, what):
+    """The search rows' bound: vector operations the method needs over the kernels'
+    time against the vector-op peak; the survey's logical traversal bytes beside it
+    (every lane charged separately, so above 1 where lanes share record loads)."""
+    return dict(bound="alu", unit="Tops/s", achieved=ops / seconds / 1e12,
+                peak=VALU_OPS_PEAK / 1e12, frac=ops / seconds / VALU_OPS_PEAK, ops=int(ops),
+                basis=what, logical_bytes=int(logical_bytes),
+                logical_traversal_frac=logical_bytes / seconds / HBM_PEAK)
 
 
 def kernel_sources_hash():
@@ -152,6 +217,7 @@ def cpu_baseline(w, gpu_target, sample, threads):
     ts = time.time() - t0
     differ = int((r["target"] != gpu_target[q]).sum())
     outside = int(((r["target"] != gpu_target[q]) & ~(r["window"] < 1e-6)).sum())
+    window_hits = int((r["window"] < 1e-6).sum())
     # the same oracle on one thread, on the first 5000 of those searches
     q1 = q[:5000]
     t0 = time.time()
@@ -161,9 +227,11 @@ def cpu_baseline(w, gpu_target, sample, threads):
                 sample=(f"{m} random searches of the {src.size} in one update of {w.name} "
                         f"(fp64 oracle, OpenMP {threads} threads); tree build {tb:.1f} s and "
                         f"refresh {tr:.1f} s not included"),
+                cpu_model=cpu_model(), nproc=os.cpu_count(),
                 one_thread=dict(value=q1.size / t1, unit="searches/s",
                                 sample=f"the first {q1.size} of those searches, 1 thread"),
-                parity=dict(sampled=m, differing=differ, outside_window=outside))
+                parity=dict(targets="the last timed step's", sampled=m, differing=differ,
+                            outside_window=outside, oracle_window_hits=window_hits))
 
 
 def bench_plain_update(msp, torch, w, steps, warmup):
@@ -203,6 +271,7 @@ def bench_plain_update(msp, torch, w, steps, warmup):
     cnt, off = counted(msp, tree, ty, va0, w.sigma, w.theta, w.seed, w.step)
     tree.free()
     B, _ = algorithmic_bytes(cnt, off)
+    ops = sweep_alu_ops(cnt, off)
     ks = float(np.mean(kern)) / 1e3
     # the oracle on 20000 sampled searches of the same update
     from oracle import oracle as orc
@@ -217,14 +286,14 @@ def bench_plain_update(msp, torch, w, steps, warmup):
     t_or = time.perf_counter() - t0
     return dict(workload=w.name, neurons=w.n, searches=S, theta=w.theta, ms_per_update=sec * 1e3,
                 searches_per_s=S / sec, search_kernels_ms=ks * 1e3,
-                roofline=hbm_roofline(B, ks, "algorithmic bytes of the search kernels (sweep "
-                                      "+ draw) / their HIP-event time"),
+                roofline=alu_roofline(ops, B, ks, "level-0 vector operations of the method / "
+                                      "the search kernels' (sweep + draw) HIP-event time"),
                 oracle=dict(value=q.size / t_or, unit="searches/s", cores=oracle_threads(),
                             kind="oracle", sample=f"{q.size} sampled searches of the same "
                             "update, tree build and refresh not included"))
 
 
-def bench_two_phase(msp, torch, w, alg_bytes, branch_level=6, reps=4):
+def bench_two_phase(msp, torch, w, alg_bytes, alg_ops, branch_level=6, reps=4):
     """The two-phase (location-aware) search of Sec. IV-A on the headline workload:
     restarts from cells at depth >= branch_level run as a second pass in cell order.
     Times both forms on the same refreshed tree and checks that the targets agree."""
@@ -256,9 +325,9 @@ def bench_two_phase(msp, torch, w, alg_bytes, branch_level=6, reps=4):
                                   phase2=two["phase2_ms"]),
                 identical_targets=bool(np.array_equal(one["target"], two["target"])),
                 searches_per_s=w.searches / kern_s,
-                roofline=hbm_roofline(alg_bytes, kern_s, "algorithmic bytes of the one-phase "
-                                      "search (the same lists are read) / the two-phase "
-                                      "kernels' HIP-event time"),
+                roofline=alu_roofline(alg_ops, alg_bytes, kern_s, "level-0 vector operations "
+                                      "of the one-phase search (the same lists) / the "
+                                      "two-phase kernels' HIP-event time"),
                 oracle="as cpu_baseline: the two-phase targets equal the one-phase ones",
                 note="on one GPU the second phase only regroups work; the paper's gain is the "
                      "communication it removes between processes")
@@ -361,11 +430,12 @@ def bench_batched(msp, torch, reps=5):
     tp = (time.perf_counter() - t0) / reps
     same = all(np.array_equal(o.cpu().numpy(), x) for o, x in zip(outs, bt))
     b.free()
-    B = 0
+    B = ops = 0
     for k, d in enumerate(sims):
         cnt, off = counted(msp, d["tree"], d["neuron_type"], d["vac_axon"], d["sigma"], 0.3,
                            d["seed"], reps - 1)
         B += algorithmic_bytes(cnt, off)[0]
+        ops += sweep_alu_ops(cnt, off)
     for d in sims:
         d["tree"].free()
     # the oracle on the simulations of up to 2^14 neurons, all of their searches
@@ -386,8 +456,8 @@ def bench_batched(msp, torch, reps=5):
                 batched_ms=tb * 1e3, batched_searches_per_s=S / tb,
                 per_simulation_ms=tp * 1e3, per_simulation_searches_per_s=S / tp,
                 speedup=tp / tb, identical_targets=bool(same),
-                roofline=hbm_roofline(B, tb, "algorithmic bytes of all 64 searches / the "
-                                      "batched launch's wall time"),
+                roofline=alu_roofline(ops, B, tb, "level-0 vector operations of all 64 "
+                                      "searches / the batched launch's wall time"),
                 oracle=dict(value=S_small / t_or, unit="searches/s",
                             cores=oracle_threads(), kind="oracle",
                             sample=f"all {S_small} searches of the {len(small)} simulations "
@@ -521,8 +591,12 @@ def bench_attraction(msp, torch, reps=5):
     ns = int(src.sum().item())
     Bf = sweep_bytes(cnt, off)
     first = off[:-1][np.diff(off) > 0]
-    accepted = int((cnt["visits0"][first].astype(np.int64) - cnt["opens0"][first]).sum())
+    accepted = int(cnt["entries0"][first].astype(np.int64).sum())
     Bb = Bf + 24 * accepted              # plus one gradient (3 x float64) per accepted entry
+    ops_f = sweep_alu_ops(cnt, off)
+    # backward: the forward's operations plus, per accepted entry, the gradient
+    # g w (2 / sigma^2) (x - c): 3 differences, 4 products
+    ops_b = ops_f + 7 * accepted
     # the oracle (fp64, forward and analytic gradient) on a 32768-neuron cube at the
     # same density
     from oracle import oracle as orc
@@ -536,10 +610,10 @@ def bench_attraction(msp, torch, reps=5):
     return dict(workload=w.name, neurons=w.n, sources=ns, forward_ms=tf * 1e3,
                 backward_ms=tb * 1e3, sources_per_s_forward=ns / tf,
                 sources_per_s_backward=ns / tb,
-                roofline_forward=hbm_roofline(Bf, tf, "level-0 algorithmic bytes / forward "
-                                              "wall time"),
-                roofline_backward=hbm_roofline(Bb, tb, "level-0 algorithmic bytes + 24 B per "
-                                               "accepted entry / backward wall time"),
+                roofline_forward=alu_roofline(ops_f, Bf, tf, "level-0 vector operations / "
+                                              "forward wall time"),
+                roofline_backward=alu_roofline(ops_b, Bb, tb, "level-0 vector operations + 7 "
+                                               "per accepted entry / backward wall time"),
                 oracle=dict(value=int((wo.vac_axon > 0).sum()) / t_or, unit="sources/s",
                             cores=oracle_threads(), kind="oracle",
                             sample="forward and gradient of all sources of a 32768-neuron "
@@ -657,6 +731,10 @@ def main():
     sec = (t1 - t0) / args.steps
     value = S / sec
 
+    # the last timed step's targets (the commit does not touch them): the cpu_baseline
+    # leg compares them with the oracle
+    gpu_target = tgt_buf[:S].cpu().numpy().astype(np.int64)
+
     # exact algorithmic work of the launch (the kernel's own counters, untimed pass)
     tree = msp.build_octree(pos, w.box_min, w.box_edge)
     va.copy_(va0); ve.copy_(ve0); vi.copy_(vi0)
@@ -665,49 +743,67 @@ def main():
     torch.cuda.synchronize()
     off_h = off.cpu().numpy()
     cnt_h = {k: v.cpu().numpy() for k, v in cnt.items()}
-    gpu_target = tgt.cpu().numpy().astype(np.int64)
+    counting_equal = bool(np.array_equal(tgt.cpu().numpy().astype(np.int64), gpu_target))
     tree.free()
     B, visits = algorithmic_bytes(cnt_h, off_h)
     first = off_h[:-1][np.diff(off_h) > 0]
     lane_steps = int((cnt_h["visits0"][first].astype(np.int64) - 1).sum())
     wave_steps = int(cnt_h["wave_steps"][0])
     union_eff = lane_steps / max(1, 64 * wave_steps)
-    evals = int((cnt_h["visits0"][first].astype(np.int64)
-                 - cnt_h["opens0"][first].astype(np.int64)).sum())
-    alu_flops = 12 * lane_steps + int(cnt_h["opens0"][first].astype(np.int64).sum())
+    evals = int(cnt_h["entries0"][first].astype(np.int64).sum())
+    ops = sweep_alu_ops(cnt_h, off_h)
     Bs = sweep_bytes(cnt_h, off_h)
     sweep_s = float(np.mean(times["sweep"])) / 1e3
     draw_s = float(np.mean(times["draw"])) / 1e3
-    achieved = Bs / sweep_s
+    walk_bytes = WALK_REC_BYTES * wave_steps + WALK_SRC_BYTES * int(first.size)
     traffic = measured_traffic(w.name)
-    roof = dict(bound="hbm", achieved=achieved / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
-                frac=achieved / HBM_PEAK, traffic=traffic,
+    issue = measured_counters(w.name)
+    roof = dict(bound="alu", achieved=ops / sweep_s / 1e12, peak=VALU_OPS_PEAK / 1e12,
+                unit="Tops/s", frac=ops / sweep_s / VALU_OPS_PEAK, traffic=traffic,
                 kernel="search_sweep_k", kernel_ms=sweep_s * 1e3,
-                algorithmic_bytes_per_launch=Bs,
-                search_total=dict(kernels="search_sweep_k+search_draw_k",
-                                  ms=(sweep_s + draw_s) * 1e3, algorithmic_bytes=B,
-                                  node_visits=visits,
-                                  achieved=B / (sweep_s + draw_s) / 1e9,
-                                  frac=B / (sweep_s + draw_s) / HBM_PEAK),
+                ops_per_launch=ops,
+                basis=(f"vector operations the method needs per source and level-0 record: "
+                       f"{OPS_VISIT} per record with vacancy (squared distance, acceptance), "
+                       f"{OPS_ENTRY} more per accepted entry (exp2, times v, running sum), "
+                       f"{OPS_EMPTY} per record without; exact per-search counts of a counting "
+                       f"launch; peak = 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz"),
                 sweep_wave_steps=wave_steps, sweep_lane_visits=lane_steps,
                 sweep_lane_utilisation=union_eff,
-                # kernel evaluations the method needs at level 0 (accepted entries: visits
-                # that are not opened), per second of the sweep, against the float32 exp2
-                # rate (quarter rate: 256 CU x 64 lanes x 2.4 GHz / 4)
+                timed_equals_counting_launch=counting_equal,
+                # measured instruction issue of the sweep (committed rocprofv3 counters of
+                # the same kernel sources, or null): vector-issue busy share and the share
+                # of vector issue slots that do a lane's own work
+                issue=None if issue is None else dict(
+                    valu_insts=issue["SQ_INSTS_VALU"], salu_insts=issue["SQ_INSTS_SALU"],
+                    kernel_ms=issue["kernel_ms"],
+                    valu_busy=issue["SQ_INSTS_VALU"] * 4 / (1024 * 2.4e9 * issue["kernel_ms"] / 1e3),
+                    useful_lane_issue=issue["SQ_INSTS_VALU"] * 4 / (1024 * 2.4e9 * issue["kernel_ms"] / 1e3)
+                    * union_eff,
+                    valu_per_wave_step=issue["SQ_INSTS_VALU"] / wave_steps,
+                    salu_per_wave_step=issue["SQ_INSTS_SALU"] / wave_steps),
+                # HBM views: the bytes the shared walk needs (one 32-byte record per wave
+                # step, the sources' data and outputs), and the survey's logical bytes
+                # (16 B per lane visit, 8 B per open, 16 B per source: every lane charged
+                # separately, so it exceeds 1 when the 64 lanes share a record load)
+                hbm_shared_walk=dict(bytes=walk_bytes, achieved=walk_bytes / sweep_s / 1e9,
+                                     unit="GB/s", frac=walk_bytes / sweep_s / HBM_PEAK),
+                hbm_measured=None if traffic is None else dict(
+                    bytes=traffic, achieved=traffic / sweep_s / 1e9, unit="GB/s",
+                    frac=traffic / sweep_s / HBM_PEAK),
+                logical_traversal=dict(bytes=Bs, achieved=Bs / sweep_s / 1e9, unit="GB/s",
+                                       logical_traversal_frac=Bs / sweep_s / HBM_PEAK),
+                search_total=dict(kernels="search_sweep_k+search_draw_k",
+                                  ms=(sweep_s + draw_s) * 1e3, logical_bytes=B,
+                                  node_visits=visits,
+                                  logical_traversal_frac=B / (sweep_s + draw_s) / HBM_PEAK),
+                # kernel evaluations at level 0 (entries of the accepted lists) per second
+                # of the sweep, against the float32 exp2 rate (quarter rate)
                 kernel_evals_per_s=evals / sweep_s, exp2_peak_per_s=EXP2_PEAK,
-                exp2_frac=evals / sweep_s / EXP2_PEAK,
-                # the vector-ALU view of the same launch: fp64 operations the method needs
-                # per source and visited record (squared distance 8; weight 4: d2 k2, the
-                # exponential, times v, the running sum) plus the acceptance product of
-                # every opened node, against the fp64 vector peak
-                alu=dict(bound="alu", achieved=alu_flops / sweep_s / 1e12,
-                         peak=FP64_VECTOR_PEAK / 1e12, unit="TFLOP/s",
-                         frac=alu_flops / sweep_s / FP64_VECTOR_PEAK, flops_per_launch=alu_flops,
-                         basis="12 fp64 operations per source and visited record + 1 per "
-                               "opened node; level-0 counts of the launch"))
-    log(f"step {sec * 1e3:.1f} ms; sweep {sweep_s * 1e3:.2f} ms ({achieved / 1e9:.0f} GB/s "
-        f"algorithmic, {roof['frac']:.3f} of HBM peak); draw {draw_s * 1e3:.2f} ms; "
-        f"{wave_steps} wave steps, lane utilisation {union_eff:.3f}")
+                exp2_frac=evals / sweep_s / EXP2_PEAK)
+    log(f"step {sec * 1e3:.1f} ms; sweep {sweep_s * 1e3:.2f} ms ({roof['frac']:.3f} of the "
+        f"vector-op peak, shared-walk HBM {roof['hbm_shared_walk']['frac']:.3f}); draw "
+        f"{draw_s * 1e3:.2f} ms; {wave_steps} wave steps, lane utilisation {union_eff:.3f}; "
+        f"timed targets equal the counting launch's: {counting_equal}")
 
     out = {
         "metric": "axon target searches/sec",
@@ -720,7 +816,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "fp64 (fp32 exp2 mantissa)",
         "data": "synthetic",
         "config": {"workload": w.name, "neurons": w.n, "searches_per_step": S,
                    "sigma_um": w.sigma, "theta": w.theta,
@@ -729,6 +825,7 @@ def main():
         "breakdown_ms": {k: float(np.mean(v)) for k, v in times.items()},
         "search_kernels_searches_per_s": S / (sweep_s + draw_s),
         "roofline": roof,
+        "paper_context": PAPER_CONTEXT,
     }
     if not args.no_also:
         from synth_inputs import config_clusters
@@ -738,7 +835,7 @@ def main():
         also["plain_1M_clusters"] = bench_plain_update(msp, torch, wc, steps=5, warmup=1)
         del wc
         log("also: two-phase search")
-        also["two_phase_8M"] = bench_two_phase(msp, torch, w, B)
+        also["two_phase_8M"] = bench_two_phase(msp, torch, w, B, ops)
         log("also: electrical activity")
         also["activity"] = bench_activity(msp, torch, w)
         log("also: batched")

@@ -50,7 +50,7 @@ extern "C" {
 
 typedef int32_t msp_status;
 #define MSP_OK                 0
-#define MSP_ERR_INVALID       (-1)  /* bad argument, freed or foreign handle          */
+#define MSP_ERR_INVALID       (-1)  /* bad argument; a handle that is not live        */
 #define MSP_ERR_OOM           (-2)  /* device allocation failed                       */
 #define MSP_ERR_HIP           (-3)  /* a HIP runtime call failed                      */
 #define MSP_ERR_CAPACITY      (-4)  /* an output buffer is too small; nothing written */
@@ -117,15 +117,25 @@ msp_status msp_update_vacant_counts(msp_octree t, const int32_t* vac_dend_exc,
  * Working memory: about 200 B per neuron plus the search checkpoints, up to 3 KB per
  * neuron but never more than an eighth of the device's memory. The library keeps it
  * per device between calls and grows it when a larger search needs more (it is held
- * until the process ends; MSP_ERR_OOM if it cannot be had). Searches on one device
- * take turns with it: a call holds it from entry to return, and the kernels of a call
- * on another stream wait for those of the previous call. The call waits on `s` once,
- * after the worklist is built, to read the status.
+ * until msp_release_workspace or the end of the process; MSP_ERR_OOM if it cannot be
+ * had). Searches on one device take turns with it: a call holds it from entry to
+ * return, and the kernels of a call on another stream wait for those of the previous
+ * call. The call waits on `s` once, after the worklist is built, to read the status.
  */
 msp_status msp_find_targets(msp_octree t, const uint8_t* neuron_type, const int32_t* vac_axon,
                             double sigma_um, double theta, uint64_t seed, uint64_t step,
                             int32_t* target_out, int64_t* elem_offset_out, int64_t capacity_S,
                             hipStream_t s);
+
+/*
+ * The searches msp_find_targets will run, so that a caller can size target_out:
+ * elem_offset_out [n+1] int64 = exclusive prefix sum of vac_axon [n] int32 (CSR by
+ * source, as msp_find_targets writes it) and *S_out (host) = elem_offset_out[n].
+ * MSP_ERR_INVALID for n < 1 or n > MSP_MAX_NEURONS, a null pointer, or a negative
+ * count (found on the device; it counts as 0 in the offsets). Waits on `s`.
+ */
+msp_status msp_search_offsets(const int32_t* vac_axon, int64_t n, int64_t* elem_offset_out,
+                              int64_t* S_out, hipStream_t s);
 
 /*
  * Diagnostics of one msp_find_targets call. Every pointer is nullable.
@@ -157,6 +167,8 @@ msp_status msp_find_targets(msp_octree t, const uint8_t* neuron_type, const int3
  *           level-0 walk is cut into this many parts (see msp_find_targets); other
  *           values are MSP_ERR_INVALID. Visits and opens do not depend on it; z0 does
  *           in its last bits only.
+ *   entries0 [S] int32: the number of entries of the level-0 accepted list (cells
+ *           accepted and neurons listed: the kernel evaluations of the level-0 sum).
  */
 typedef struct msp_search_diag {
   double* z0;
@@ -170,6 +182,7 @@ typedef struct msp_search_diag {
   int32_t branch_level;
   int64_t* phase2_requests;
   int32_t parts_per_tile;
+  int32_t* entries0;
 } msp_search_diag;
 
 /* msp_find_targets with diagnostics (diag may be null). */
@@ -266,8 +279,9 @@ msp_status msp_attraction_bwd(msp_octree t, const uint8_t* neuron_type, const in
  *   accepted_out [S] uint8 (nullable in msp_commit_synapses_ex): 1 if the request in
  *   that slot was accepted.
  * Errors: MSP_ERR_CAPACITY if more than syn_capacity synapses would form (then no
- * count is modified and nothing is written). After a commit the octree is stale
- * until the next msp_update_vacant_counts.
+ * count is modified and nothing is written); MSP_ERR_INVALID if S = elem_offset[n]
+ * is negative or not below 2^31 - 1 (requests are indexed with int32). After a commit
+ * the octree is stale until the next msp_update_vacant_counts.
  */
 msp_status msp_commit_synapses(const int32_t* target, const int64_t* elem_offset,
                                const uint8_t* neuron_type, int64_t n, int32_t* vac_axon,
@@ -282,9 +296,23 @@ msp_status msp_commit_synapses_ex(const int32_t* target, const int64_t* elem_off
                                   uint8_t* syn_type, int64_t syn_capacity, int64_t* n_formed,
                                   uint8_t* accepted_out, hipStream_t s);
 
-/* Release the octree (waits for the device to finish using it). A freed or foreign
- * handle is rejected with MSP_ERR_INVALID by every call (magic-number check). */
+/* Release the octree (waits for the device to finish using it). The library keeps a
+ * registry of the handles it has handed out and never reads through a handle that is
+ * not in it: every call rejects a freed or foreign handle with MSP_ERR_INVALID, and a
+ * second free of the same handle does nothing. */
 void msp_free_octree(msp_octree t);
+
+/* Stream-ordered release: the octree's memory returns to the library's pool after the
+ * work queued on `s` so far; the handle is invalid at once. The caller orders every
+ * other use of the octree (on other streams) before that point. MSP_ERR_INVALID for
+ * a handle that is not live. */
+msp_status msp_free_octree_async(msp_octree t, hipStream_t s);
+
+/* Free the search working memory the library keeps on `device` (see msp_find_targets),
+ * after the last search that used it has finished (waits for it). The next search
+ * on that device allocates it again. MSP_ERR_INVALID for a device that does not
+ * exist. */
+msp_status msp_release_workspace(int32_t device);
 
 /* Wait for stream s; MSP_ERR_HIP if the stream reported an error. */
 msp_status msp_sync(hipStream_t s);
@@ -397,6 +425,19 @@ typedef struct msp_activity_params {
   double ca_beta, ca_tau;
   int32_t epoch;
 } msp_activity_params;
+
+/*
+ * Initial state of the activity (Sec. II: the neuron model's state before the first
+ * step): v = c and u = b c of the neuron's type (its reset potential and the resting
+ * relation of the recovery variable), calcium = 0, spiked = 0, epoch_count = 0,
+ * freq = 0, written to the caller's device arrays [n] (the same arrays as
+ * msp_activity_run's). MSP_ERR_INVALID for n < 1, a null pointer, or a type > 1
+ * (found on the device; such a neuron is initialised as inhibitory). Waits on `s`.
+ */
+msp_status msp_activity_init(int64_t n, const uint8_t* neuron_type,
+                             const msp_activity_params* params, double* v, double* u,
+                             double* calcium, uint8_t* spiked, int32_t* epoch_count, double* freq,
+                             hipStream_t s);
 
 /*
  * Runs steps t0 .. t0 + steps - 1 (1 ms each). Per step t:

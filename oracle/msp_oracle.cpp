@@ -323,6 +323,7 @@ struct SearchResult {
   double z0 = 0.0;          // normaliser of the level-0 list
   double window = 1.0;      // min over levels of |u - P/Z| at the chosen entry's bounds
   int32_t levels = 0;       // number of lists drawn from
+  int64_t entries0 = 0;     // length of the level-0 list (its kernel evaluations)
   SearchCounters cnt;
 };
 
@@ -336,7 +337,10 @@ SearchResult search_one(const OracleTree& t, int type, int64_t i, int64_t j, dou
     expand(t, type, i, S, sigma, theta, g, g, list, res.cnt);
     double Z = 0.0;
     for (const Entry& e : list) Z = Z + e.w;
-    if (level == 0) res.z0 = Z;
+    if (level == 0) {
+      res.z0 = Z;
+      res.entries0 = (int64_t)list.size();
+    }
     res.levels += 1;
     if (list.empty() || Z == 0.0) { res.target = -1; return res; }
     double u = draw_u(seed, 0, (uint64_t)i, (uint64_t)j, step, level);
@@ -440,12 +444,12 @@ void oracle_get_aggregates(const OracleTree* t, int type, int64_t* v, double* c)
 // Run the searches (src[q], elem[q]) for q < n_sel. neuron_type selects the
 // dendrite type searched (0 = excitatory, 1 = inhibitory).
 // Outputs per search: target id or -1, level-0 normaliser, window distance, number
-// of levels, node records read and nodes opened.
+// of levels, node records read and nodes opened, and the length of the level-0 list.
 int oracle_find_targets(const OracleTree* t, const uint8_t* neuron_type, double sigma,
                         double theta, uint64_t seed, uint64_t step, const int64_t* src,
                         const int64_t* elem, int64_t n_sel, int64_t* target, double* z0,
                         double* window, int32_t* levels, int64_t* visits, int64_t* opens,
-                        int nthreads) {
+                        int64_t* entries0, int nthreads) {
   if (!t->counted || !(sigma > 0.0) || !(theta >= 0.0)) return -1;
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -460,6 +464,7 @@ int oracle_find_targets(const OracleTree* t, const uint8_t* neuron_type, double 
     if (levels) levels[q] = r.levels;
     if (visits) visits[q] = r.cnt.visits;
     if (opens) opens[q] = r.cnt.opens;
+    if (entries0) entries0[q] = r.entries0;
   }
   return 0;
 }

@@ -42,10 +42,12 @@ _lib = None
 
 
 def lib():
+    """The oracle library: built here on first use, or, when MSP_ORACLE_LIB names a
+    prebuilt one (the sanitizer test's instrumented build of the same source), that."""
     global _lib
     if _lib is None:
-        build_oracle()
-        L = ctypes.CDLL(_LIB_PATH)
+        path = os.environ.get("MSP_ORACLE_LIB") or build_oracle()
+        L = ctypes.CDLL(path)
         L.oracle_build.restype = _ptr
         L.oracle_build.argtypes = [_ptr, _i64, _ptr, _dbl]
         L.oracle_free.argtypes = [_ptr]
@@ -58,7 +60,7 @@ def lib():
         L.oracle_get_aggregates.argtypes = [_ptr, ctypes.c_int, _ptr, _ptr]
         L.oracle_find_targets.restype = ctypes.c_int
         L.oracle_find_targets.argtypes = [_ptr, _ptr, _dbl, _dbl, _u64, _u64, _ptr, _ptr, _i64,
-                                          _ptr, _ptr, _ptr, _ptr, _ptr, _ptr, ctypes.c_int]
+                                          _ptr, _ptr, _ptr, _ptr, _ptr, _ptr, _ptr, ctypes.c_int]
         L.oracle_commit.restype = _i64
         L.oracle_commit.argtypes = [_i64, _ptr, _ptr, _ptr, _ptr, _ptr, _ptr, _u64, _u64,
                                     _ptr, _ptr, _ptr, _ptr]
@@ -168,11 +170,13 @@ class OracleTree:
         m = src.size
         out = dict(target=np.zeros(m, np.int64), z0=np.zeros(m, np.float64),
                    window=np.zeros(m, np.float64), levels=np.zeros(m, np.int32),
-                   visits=np.zeros(m, np.int64), opens=np.zeros(m, np.int64))
+                   visits=np.zeros(m, np.int64), opens=np.zeros(m, np.int64),
+                   entries0=np.zeros(m, np.int64))
         rc = lib().oracle_find_targets(self._h, _p(t), float(sigma), float(theta), int(seed),
                                        int(step), _p(src), _p(elem), m, _p(out["target"]),
                                        _p(out["z0"]), _p(out["window"]), _p(out["levels"]),
-                                       _p(out["visits"]), _p(out["opens"]), int(nthreads))
+                                       _p(out["visits"]), _p(out["opens"]),
+                                       _p(out["entries0"]), int(nthreads))
         if rc != 0:
             raise ValueError("oracle_find_targets rejected the input")
         return out

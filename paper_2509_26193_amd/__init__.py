@@ -7,9 +7,10 @@ commit_synapses.
 """
 from ._lib import (ACTIVITY, PLASTICITY, Activity, AttractionFn, Batch, MspError, Network, Octree, attraction,
                    attraction_bwd, attraction_fwd, build_octree, commit_synapses, find_targets,
-                   header_functions, lib, status_string, sync, update_vacant_counts)
+                   header_functions, lib, release_workspace, search_offsets, status_string, sync,
+                   update_vacant_counts)
 
 __all__ = ["AttractionFn", "attraction", "attraction_fwd", "attraction_bwd", "Batch", "MspError",
            "Octree", "build_octree", "update_vacant_counts", "find_targets",
            "commit_synapses", "Network", "PLASTICITY", "Activity", "ACTIVITY", "sync", "status_string",
-           "header_functions", "lib"]
+           "header_functions", "lib", "search_offsets", "release_workspace"]

@@ -41,7 +41,8 @@ class SearchDiag(ctypes.Structure):
     _fields_ = [("z0", _vp), ("levels", _vp), ("visits", _vp), ("opens", _vp),
                 ("visits0", _vp), ("opens0", _vp), ("kernel_ms", ctypes.POINTER(ctypes.c_float)),
                 ("wave_steps", _vp), ("branch_level", ctypes.c_int32),
-                ("phase2_requests", _vp), ("parts_per_tile", ctypes.c_int32)]
+                ("phase2_requests", _vp), ("parts_per_tile", ctypes.c_int32),
+                ("entries0", _vp)]
 
 
 class SimSpec(ctypes.Structure):
@@ -76,6 +77,9 @@ _SIGS = {
     "msp_commit_synapses_ex": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _u64, _u64, _vp, _vp,
                                       _vp, _i64, _vp, _vp, _vp]),
     "msp_free_octree": (None, [_vp]),
+    "msp_free_octree_async": (_i32, [_vp, _vp]),
+    "msp_release_workspace": (_i32, [_i32]),
+    "msp_search_offsets": (_i32, [_vp, _i64, _vp, ctypes.POINTER(_i64), _vp]),
     "msp_last_device_error": (_i32, [_vp]),
     "msp_octree_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "msp_octree_export_topology": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -90,6 +94,8 @@ _SIGS = {
                                      _vp]),
     "msp_plasticity_step": (_i32, [_i64, ctypes.POINTER(PlasticityParams), _u64, _u64, _vp, _vp,
                                    _vp, _vp, _vp, _i64, ctypes.POINTER(_i64), _vp, _vp, _vp, _vp]),
+    "msp_activity_init": (_i32, [_i64, _vp, ctypes.POINTER(ActivityParams), _vp, _vp, _vp, _vp,
+                                 _vp, _vp, _vp]),
     "msp_activity_run": (_i32, [_i64, _vp, _vp, _i64, _vp, _vp, _vp, _i32,
                                 ctypes.POINTER(ActivityParams), _u64, _u64, _i32, _vp, _vp, _vp,
                                 _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -175,14 +181,20 @@ class Octree:
         _check(lib().msp_octree_info(self.handle, ctypes.byref(nn), ctypes.byref(nN)), "octree_info")
         return int(nN.value)
 
-    def free(self) -> None:
+    def free(self, stream=None) -> None:
+        """Stream-ordered release: the memory returns to the library's pool after the
+        work queued so far on `stream` (default: the current stream). Uses of the
+        octree on other streams must be ordered before that point by the caller."""
         if self._h:
-            lib().msp_free_octree(self._h)
-            self._h = None
+            h, self._h = self._h, None
+            _check(lib().msp_free_octree_async(h, _stream(stream)), "free_octree")
 
     def __del__(self):
+        # at collection time the caller's stream order is unknown: wait for the device
         try:
-            self.free()
+            if self._h:
+                h, self._h = self._h, None
+                lib().msp_free_octree(h)
         except Exception:
             pass
 
@@ -225,6 +237,27 @@ def build_octree(pos: torch.Tensor, box_min, box_edge: float, leaf_size: int = 1
     return Octree(h.value, n, pos.device)
 
 
+def search_offsets(vac_axon: torch.Tensor, elem_offset_out: torch.Tensor | None = None,
+                   stream=None):
+    """(elem_offset[n+1], S): the CSR offsets of the searches (exclusive prefix sum of
+    vac_axon) and their number, computed by the library (waits on the stream)."""
+    n = vac_axon.numel()
+    if elem_offset_out is None:
+        elem_offset_out = torch.empty(n + 1, dtype=torch.int64, device=vac_axon.device)
+    S = _i64(0)
+    _check(lib().msp_search_offsets(_dev(vac_axon, torch.int32, "vac_axon", n), n,
+                                    _dev(elem_offset_out, torch.int64, "elem_offset_out", n + 1),
+                                    ctypes.byref(S), _stream(stream)), "search_offsets")
+    return elem_offset_out, int(S.value)
+
+
+def release_workspace(device=None) -> None:
+    """Free the search working memory the library keeps on `device` (default: the
+    current device); the next search allocates it again."""
+    d = torch.cuda.current_device() if device is None else torch.device(device).index
+    _check(lib().msp_release_workspace(int(d if d is not None else 0)), "release_workspace")
+
+
 def update_vacant_counts(tree: Octree, vac_exc: torch.Tensor, vac_inh: torch.Tensor,
                          stream=None) -> None:
     _check(lib().msp_update_vacant_counts(tree.handle, _dev(vac_exc, torch.int32, "vac_exc", tree.n),
@@ -238,7 +271,7 @@ def find_targets(tree: Octree, neuron_type: torch.Tensor, vac_axon: torch.Tensor
                  counters: bool = False, timing: dict | None = None, stream=None,
                  branch_level: int = 0, phase2: dict | None = None, parts: int = 0):
     """Returns (target[S], elem_offset[n+1]); with diag also (z0[S], levels[S]); with
-    counters also a dict of visits/opens/visits0/opens0 [S]. target_out may be a
+    counters also a dict of visits/opens/visits0/opens0/entries0 [S] and wave_steps. target_out may be a
     preallocated int32 buffer of any capacity >= S. If `timing` is a dict, the kernel
     durations (HIP events on the launch stream) are stored under "sweep_ms" (level-0
     sweep), "draw_ms" (draws and restarts, both phases), "phase2_ms" (the second phase)
@@ -258,7 +291,7 @@ def find_targets(tree: Octree, neuron_type: torch.Tensor, vac_axon: torch.Tensor
     ms = (ctypes.c_float * 3)(0.0, 0.0, 0.0)
     extra = {}
     if target_out is None:                  # size the output once instead of retrying
-        S0 = int(torch.clamp(vac_axon, min=0).sum().item())
+        _, S0 = search_offsets(vac_axon, elem_offset_out, stream)
         target_out = torch.empty(max(S0, 1), dtype=torch.int32, device=dev)
     for attempt in range(2):
         cap = 0 if target_out is None else target_out.numel()
@@ -267,7 +300,7 @@ def find_targets(tree: Octree, neuron_type: torch.Tensor, vac_axon: torch.Tensor
             extra["z0"] = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
             extra["levels"] = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
         if counters:
-            for k in ("visits", "opens", "visits0", "opens0"):
+            for k in ("visits", "opens", "visits0", "opens0", "entries0"):
                 extra[k] = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
             extra["wave_steps"] = torch.zeros(1, dtype=torch.int64, device=dev)
         for k, v in extra.items():
@@ -302,7 +335,7 @@ def find_targets(tree: Octree, neuron_type: torch.Tensor, vac_axon: torch.Tensor
     if diag:
         out += [extra["z0"][:S], extra["levels"][:S]]
     if counters:
-        c = {k: extra[k][:S] for k in ("visits", "opens", "visits0", "opens0")}
+        c = {k: extra[k][:S] for k in ("visits", "opens", "visits0", "opens0", "entries0")}
         c["wave_steps"] = extra["wave_steps"]
         out.append(c)
     return tuple(out)
@@ -362,7 +395,7 @@ class Batch:
             if d.get("elem_offset_out") is None:
                 d["elem_offset_out"] = torch.empty(n + 1, dtype=torch.int64, device=dev)
             if d.get("target_out") is None:
-                S = int(torch.clamp(d["vac_axon"], min=0).sum().item())
+                _, S = search_offsets(d["vac_axon"], d["elem_offset_out"])
                 d["target_out"] = torch.empty(max(S, 1), dtype=torch.int32, device=dev)
         arr = self._specs()
         flags = (MSP_BATCH_GRAPH if graph else 0) | (MSP_BATCH_AUTOTUNE if autotune else 0)
@@ -535,17 +568,18 @@ class Activity:
         self.n = neuron_type.numel()
         self.p = dict(ACTIVITY, **(params or {}))
         dev = neuron_type.device
-        inh = neuron_type != 0
-        c = torch.where(inh, torch.tensor(self.p["c_inh"], dtype=torch.float64, device=dev),
-                        torch.tensor(self.p["c_exc"], dtype=torch.float64, device=dev))
-        b = torch.where(inh, torch.tensor(self.p["b_inh"], dtype=torch.float64, device=dev),
-                        torch.tensor(self.p["b_exc"], dtype=torch.float64, device=dev))
-        self.v = c.contiguous()
-        self.u = (b * c).contiguous()
-        self.calcium = torch.zeros(self.n, dtype=torch.float64, device=dev)
-        self.spiked = torch.zeros(self.n, dtype=torch.uint8, device=dev)
-        self.count = torch.zeros(self.n, dtype=torch.int32, device=dev)
-        self.freq = torch.zeros(self.n, dtype=torch.float64, device=dev)
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.v = torch.empty(self.n, **f64)
+        self.u = torch.empty(self.n, **f64)
+        self.calcium = torch.empty(self.n, **f64)
+        self.spiked = torch.empty(self.n, dtype=torch.uint8, device=dev)
+        self.count = torch.empty(self.n, dtype=torch.int32, device=dev)
+        self.freq = torch.empty(self.n, **f64)
+        P = ActivityParams(*[self.p[f] for f, _ in ActivityParams._fields_])
+        _check(lib().msp_activity_init(
+            self.n, _dev(self.type, torch.uint8, "neuron_type", self.n), ctypes.byref(P),
+            self.v.data_ptr(), self.u.data_ptr(), self.calcium.data_ptr(), self.spiked.data_ptr(),
+            self.count.data_ptr(), self.freq.data_ptr(), _stream(None)), "activity_init")
 
     def run(self, syn_src: torch.Tensor, syn_tgt: torch.Tensor, syn_type: torch.Tensor,
             seed: int, t0: int, steps: int, approx: int = 0, rank: torch.Tensor | None = None,

@@ -34,6 +34,26 @@ struct ActParams {
   int32_t delta;
 };
 
+// Start of the activity (one thread per neuron): the membrane potential at the reset
+// value c of the neuron's type, the recovery variable at its resting relation u = b c,
+// no calcium, no spike, an empty epoch and no frequency yet.
+__global__ void __launch_bounds__(kActBlock) act_init_k(
+    int64_t n, const uint8_t* __restrict__ type, ActParams P, double* __restrict__ v,
+    double* __restrict__ u, double* __restrict__ calcium, uint8_t* __restrict__ spiked,
+    int32_t* __restrict__ count, double* __restrict__ freq, int32_t* err) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const uint8_t t8 = type[g];
+  if (t8 > 1) atomicOr(err, 1);
+  const int t = t8 ? 1 : 0;
+  v[g] = P.c[t];
+  u[g] = P.b[t] * P.c[t];
+  calcium[g] = 0.0;
+  spiked[g] = 0;
+  count[g] = 0;
+  freq[g] = 0.0;
+}
+
 // Run setup, one thread per synapse: a synapse with an endpoint outside [0, n) or a
 // type > 1 sets *err and takes no part in the run. Exact synapses are counted per
 // source (cnt); with approx 1, remote[s] = 1 marks the approximated ones (neurons of

@@ -162,6 +162,7 @@ __global__ void __launch_bounds__(256) search_draw_k(BatchDev B, SweepOut W) {
     D.opens = d->diag.opens;
     D.visits0 = d->diag.visits0;
     D.opens0 = d->diag.opens0;
+    D.entries0 = d->diag.entries0;
   }
   draw_slot<DIAG, SLOTS, DEFER>(A, D, W, slot, u0, plog, *W.unit_count <= W.ck_units);
 }
@@ -482,7 +483,7 @@ inline ScratchSizes scratch_sizes(int64_t total_n, int nsims, int slots, int for
   z.hval = align_up(sizeof(int32_t) * total_n);
   z.hsort = align_up(radix_sort_ws_bytes(total_n));
   z.total = z.ea + 2 * z.p + z.tile_base + z.unit_base + z.plog + z.status + z.work + z.Z +
-            2 * z.v + z.nck + z.ckx +
+            3 * z.v + z.nck + z.ckx +
             z.ckP + z.ckme + z.counters + z.scan + z.srct + 2 * z.hkey + 2 * z.hval + z.hsort;
   return z;
 }
@@ -513,6 +514,7 @@ inline SearchScratch carve(void* base, int64_t total_n, int nsims, int slots,
   S.W.Z = reinterpret_cast<double*>(take(z.Z));
   S.W.v0 = reinterpret_cast<int32_t*>(take(z.v));
   S.W.o0 = reinterpret_cast<int32_t*>(take(z.v));
+  S.W.e0 = reinterpret_cast<int32_t*>(take(z.v));
   S.W.nck = reinterpret_cast<int32_t*>(take(z.nck));
   S.W.ck_x = reinterpret_cast<int32_t*>(take(z.ckx));
   S.W.ck_P = reinterpret_cast<double*>(take(z.ckP));

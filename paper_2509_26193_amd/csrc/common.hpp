@@ -8,13 +8,12 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <unordered_map>
 
 #include "msp.h"
 
 namespace msp {
 
-constexpr uint32_t kMagic = 0x3150534Du;   // "MSP1"
-constexpr uint32_t kDead = 0xDEADBEEFu;
 constexpr int kMaxDepth = 21;              // 21 bits per axis, 63-bit Morton keys
 constexpr int kWave = 64;
 
@@ -48,7 +47,6 @@ constexpr int32_t kErrArgs = 8;
 }  // namespace msp
 
 struct msp_octree_s {
-  uint32_t magic;
   int device;
   int64_t n;             // neurons
   int64_t N;             // nodes
@@ -88,7 +86,47 @@ struct msp_octree_s {
 
 namespace msp {
 
-inline bool handle_ok(const msp_octree_s* t) { return t != nullptr && t->magic == kMagic; }
+// Registry of the live handles the library has handed out (octrees and batch plans).
+// A handle is valid exactly while it is registered: every entry point looks the
+// pointer up here instead of reading through it, so a freed, foreign or doubly freed
+// handle is rejected without touching freed memory. (A handle whose address a later
+// build or plan has reused names that new object.)
+enum class HandleKind : int { kOctree = 1, kBatch = 2 };
+
+inline std::mutex& handle_mutex() {
+  static std::mutex m;
+  return m;
+}
+
+inline std::unordered_map<const void*, HandleKind>& live_handles() {
+  static std::unordered_map<const void*, HandleKind> h;
+  return h;
+}
+
+inline void handle_register(const void* p, HandleKind k) {
+  std::lock_guard<std::mutex> g(handle_mutex());
+  live_handles()[p] = k;
+}
+
+inline bool handle_live(const void* p, HandleKind k) {
+  if (!p) return false;
+  std::lock_guard<std::mutex> g(handle_mutex());
+  const auto it = live_handles().find(p);
+  return it != live_handles().end() && it->second == k;
+}
+
+// Unregister p if it is a live handle of kind k; true if it was (exactly one of two
+// concurrent frees of one handle gets true).
+inline bool handle_take(const void* p, HandleKind k) {
+  if (!p) return false;
+  std::lock_guard<std::mutex> g(handle_mutex());
+  const auto it = live_handles().find(p);
+  if (it == live_handles().end() || it->second != k) return false;
+  live_handles().erase(it);
+  return true;
+}
+
+inline bool handle_ok(const msp_octree_s* t) { return handle_live(t, HandleKind::kOctree); }
 
 // The library's own stream-ordered memory pool on `device`: memory freed to it stays
 // mapped for the next allocation (release threshold = unlimited), so the per-call

@@ -61,20 +61,29 @@ void carve_nodes(msp_octree_s* t, char* base, size_t* bytes) {
   *bytes = c.off;
 }
 
-void release(msp_octree_s* t) {
+// Return the octree's memory to the library pool, ordered on `fs` (null: the library's
+// own stream, for callers that have waited for every use), and delete the struct. The
+// handle must already be unregistered (or never have been registered).
+void release(msp_octree_s* t, hipStream_t fs = nullptr, bool on_caller_stream = false) {
   if (!t) return;
-  // the callers have waited for every use: the memory returns to the library pool
-  hipStream_t fs = nullptr;
-  if (lib_stream(t->device, &fs) != hipSuccess) fs = nullptr;
+  if (!on_caller_stream && lib_stream(t->device, &fs) != hipSuccess) fs = nullptr;
   if (t->slab_n) (void)hipFreeAsync(t->slab_n, fs);
   if (t->slab_N) (void)hipFreeAsync(t->slab_N, fs);
-  t->magic = kDead;
   delete t;
 }
 
 struct AccFlag {
   __device__ int64_t operator()(uint8_t a, int64_t) const { return (int64_t)a; }
 };
+
+struct NonNeg {                 // a count, negative ones taken as 0 (they are reported)
+  __device__ int64_t operator()(int32_t a, int64_t) const { return a > 0 ? (int64_t)a : 0; }
+};
+
+__global__ void negative_k(const int32_t* __restrict__ a, int64_t n, int32_t* err) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n && a[k] < 0) atomicOr(err, 1);
+}
 
 // Fill the device descriptor of one simulation.
 SimDesc make_desc(const msp_octree_s* t, const uint8_t* neuron_type, const int32_t* vac_axon,
@@ -245,6 +254,27 @@ msp_status msp_sync(hipStream_t s) {
   return MSP_OK;
 }
 
+msp_status msp_release_workspace(int32_t device) {
+  int ndev = 0;
+  MSP_HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev || device >= 64) return MSP_ERR_INVALID;
+  Workspace& w = workspace(device);
+  std::lock_guard<std::mutex> g(w.m);
+  if (!w.p) return MSP_OK;
+  int cur = -1;
+  MSP_HIP_TRY(hipGetDevice(&cur));
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess && w.done) e = hipEventSynchronize(w.done);
+  if (e == hipSuccess) e = hipFree(w.p);
+  if (e == hipSuccess) {
+    w.p = nullptr;
+    w.bytes = 0;
+  }
+  (void)hipSetDevice(cur);
+  MSP_HIP_TRY(e);
+  return MSP_OK;
+}
+
 msp_status msp_build_octree(const double* pos, int64_t n, const double box_min[3],
                             double box_edge, int32_t leaf_size, hipStream_t s, msp_octree* out) {
   if (!out) return MSP_ERR_INVALID;
@@ -257,7 +287,6 @@ msp_status msp_build_octree(const double* pos, int64_t n, const double box_min[3
   msp_octree_s* t = new (std::nothrow) msp_octree_s();
   if (!t) return MSP_ERR_OOM;
   std::memset(t, 0, sizeof(*t));
-  t->magic = kMagic;
   t->n = n;
   t->box_edge = box_edge;
   for (int a = 0; a < 3; ++a) t->box_min[a] = box_min[a];
@@ -357,18 +386,29 @@ msp_status msp_build_octree(const double* pos, int64_t n, const double box_min[3
     TRY(hipGetLastError());
   }
 #undef TRY
+  handle_register(t, HandleKind::kOctree);
   *out = t;
   return MSP_OK;
 }
 
 void msp_free_octree(msp_octree t) {
-  if (!handle_ok(t)) return;
+  if (!handle_take(t, HandleKind::kOctree)) return;
   int dev = -1;
   (void)hipGetDevice(&dev);
   (void)hipSetDevice(t->device);
   (void)hipDeviceSynchronize();
   release(t);
   if (dev >= 0) (void)hipSetDevice(dev);
+}
+
+msp_status msp_free_octree_async(msp_octree t, hipStream_t s) {
+  if (!handle_take(t, HandleKind::kOctree)) return MSP_ERR_INVALID;
+  int dev = -1;
+  (void)hipGetDevice(&dev);
+  (void)hipSetDevice(t->device);
+  release(t, s, true);
+  if (dev >= 0) (void)hipSetDevice(dev);
+  return MSP_OK;
 }
 
 msp_status msp_octree_info(msp_octree t, int64_t* n_neurons, int64_t* n_nodes) {
@@ -421,9 +461,9 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
   bool any = false;
   if (diag) {
     h.diag = DiagOut{diag->z0, diag->levels, diag->visits, diag->opens, diag->visits0,
-                     diag->opens0};
+                     diag->opens0, diag->entries0};
     any = h.diag.z0 || h.diag.levels || h.diag.visits || h.diag.opens || h.diag.visits0 ||
-          h.diag.opens0;
+          h.diag.opens0 || h.diag.entries0;
   }
   const int64_t hbase[2] = {0, n};
   int force = -1;                       // parts per tile: automatic
@@ -537,6 +577,27 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
   return MSP_OK;
 }
 
+msp_status msp_search_offsets(const int32_t* vac_axon, int64_t n, int64_t* elem_offset_out,
+                              int64_t* S_out, hipStream_t s) {
+  if (!vac_axon || !elem_offset_out || !S_out || n < 1 || n > MSP_MAX_NEURONS)
+    return MSP_ERR_INVALID;
+  Temp err(s);
+  MSP_HIP_TRY(err.alloc(sizeof(int32_t)));
+  fill_i32_k<<<1, 64, 0, s>>>(err.as<int32_t>(), 1, 0);
+  negative_k<<<grid_for(n, 256), 256, 0, s>>>(vac_axon, n, err.as<int32_t>());
+  MSP_HIP_TRY(hipGetLastError());
+  MSP_HIP_TRY((exclusive_scan<int64_t, int32_t, NonNeg>(vac_axon, elem_offset_out, n, NonNeg(),
+                                                       true, s)));
+  int64_t S = 0;
+  int32_t bad = 0;
+  MSP_HIP_TRY(hipMemcpyAsync(&S, elem_offset_out + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MSP_HIP_TRY(hipMemcpyAsync(&bad, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MSP_HIP_TRY(hipStreamSynchronize(s));
+  if (bad) return MSP_ERR_INVALID;
+  *S_out = S;
+  return MSP_OK;
+}
+
 msp_status msp_find_targets(msp_octree t, const uint8_t* neuron_type, const int32_t* vac_axon,
                             double sigma_um, double theta, uint64_t seed, uint64_t step,
                             int32_t* target_out, int64_t* elem_offset_out, int64_t capacity_S,
@@ -557,7 +618,8 @@ msp_status msp_commit_synapses_ex(const int32_t* target, const int64_t* elem_off
   int64_t S = 0;
   MSP_HIP_TRY(hipMemcpyAsync(&S, elem_offset + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   MSP_HIP_TRY(hipStreamSynchronize(s));
-  if (S < 0) return MSP_ERR_INVALID;
+  // group offsets, cursors and request indices are int32
+  if (S < 0 || S >= (int64_t)INT32_MAX) return MSP_ERR_INVALID;
   if (S == 0) {
     MSP_HIP_TRY(hipMemsetAsync(n_formed, 0, sizeof(int64_t), s));
     return MSP_OK;
@@ -688,7 +750,6 @@ msp_status msp_octree_export_aggregates(msp_octree t, int32_t type, int64_t* cou
 
 // ---------------------------------------------------------------------------- batched
 struct msp_batch_s {
-  uint32_t magic;
   int device;
   int32_t nsims;
   int32_t flags;
@@ -724,7 +785,6 @@ void batch_release(msp_batch_s* b) {
   if (b->d_sims) (void)hipFree(b->d_sims);
   if (b->d_nbase) (void)hipFree(b->d_nbase);
   if (b->scratch) (void)hipFree(b->scratch);
-  b->magic = kDead;
   delete b;
 }
 
@@ -787,12 +847,14 @@ msp_status msp_batch_create(const msp_sim* sims, int32_t n_sims, int32_t flags, 
   if (!out) return MSP_ERR_INVALID;
   *out = nullptr;
   if (!sims || n_sims < 1) return MSP_ERR_INVALID;
+  for (int k = 0; k < n_sims; ++k)
+    if (!sim_ok(sims[k])) return MSP_ERR_INVALID;
   int dev = -1;
   MSP_HIP_TRY(hipGetDevice(&dev));
   int64_t total = 0;
   std::vector<int64_t> base(n_sims + 1, 0);
   for (int k = 0; k < n_sims; ++k) {
-    if (!sim_ok(sims[k]) || sims[k].tree->device != dev) return MSP_ERR_INVALID;
+    if (sims[k].tree->device != dev) return MSP_ERR_INVALID;
     base[k] = total;
     total += sims[k].tree->n;
   }
@@ -800,7 +862,6 @@ msp_status msp_batch_create(const msp_sim* sims, int32_t n_sims, int32_t flags, 
   if (total >= ((int64_t)1 << 31) - 4096) return MSP_ERR_INVALID;
   msp_batch_s* b = new (std::nothrow) msp_batch_s();
   if (!b) return MSP_ERR_OOM;
-  b->magic = kMagic;
   b->device = dev;
   b->nsims = n_sims;
   b->flags = flags;
@@ -839,13 +900,14 @@ msp_status msp_batch_create(const msp_sim* sims, int32_t n_sims, int32_t flags, 
     return e == hipErrorOutOfMemory ? MSP_ERR_OOM : MSP_ERR_HIP;
   }
   b->S = carve(b->scratch, total, n_sims, b->ck_slots, b->d_sims, b->d_nbase, -1, b->ck_regions);
+  handle_register(b, HandleKind::kBatch);
   *out = b;
   return MSP_OK;
 }
 
 msp_status msp_find_targets_batched(msp_batch b, const msp_sim* sims, double theta,
                                     uint64_t step, hipStream_t s) {
-  if (!b || b->magic != kMagic) return MSP_ERR_INVALID;
+  if (!handle_live(b, HandleKind::kBatch)) return MSP_ERR_INVALID;
   if (!std::isfinite(theta) || !(theta >= 0.0)) return MSP_ERR_INVALID;
   if (sims) {
     for (int k = 0; k < b->nsims; ++k)
@@ -899,7 +961,7 @@ msp_status msp_find_targets_batched(msp_batch b, const msp_sim* sims, double the
 }
 
 msp_status msp_batch_status(msp_batch b, hipStream_t s, int32_t* status_out) {
-  if (!b || b->magic != kMagic) return MSP_ERR_INVALID;
+  if (!handle_live(b, HandleKind::kBatch)) return MSP_ERR_INVALID;
   std::vector<int32_t> st(b->nsims, 0);
   MSP_HIP_TRY(hipMemcpyAsync(st.data(), b->S.B.status, sizeof(int32_t) * b->nsims,
                              hipMemcpyDeviceToHost, s));
@@ -915,7 +977,7 @@ msp_status msp_batch_status(msp_batch b, hipStream_t s, int32_t* status_out) {
 }
 
 void msp_batch_free(msp_batch b) {
-  if (!b || b->magic != kMagic) return;
+  if (!handle_take(b, HandleKind::kBatch)) return;
   (void)hipSetDevice(b->device);
   (void)hipDeviceSynchronize();
   batch_release(b);
@@ -1013,6 +1075,27 @@ msp_status msp_attraction_bwd(msp_octree t, const uint8_t* neuron_type, const in
 // ---------------------------------------------------------------------------
 // Plasticity between updates
 // ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+ActParams act_params(const msp_activity_params& q) {
+  ActParams P;
+  P.a[0] = q.a_exc; P.b[0] = q.b_exc; P.c[0] = q.c_exc; P.d[0] = q.d_exc;
+  P.a[1] = q.a_inh; P.b[1] = q.b_inh; P.c[1] = q.c_inh; P.d[1] = q.d_inh;
+  P.w_e = q.w_exc;
+  P.w_i = q.w_inh;
+  P.mu = q.bg_mean;
+  P.width = q.bg_width;
+  P.beta = q.ca_beta;
+  P.inv_tau = 1.0 / q.ca_tau;
+  P.inv_delta = 1.0 / (double)q.epoch;
+  P.delta = q.epoch;
+  return P;
+}
+}  // namespace
+
+extern "C" {
+
 msp_status msp_plasticity_record(int64_t n, const int32_t* new_src, const int32_t* new_tgt,
                                  const uint8_t* new_type, int64_t m_new, int32_t* syn_src,
                                  int32_t* syn_tgt, uint8_t* syn_type, int64_t m, int64_t capacity,
@@ -1157,6 +1240,26 @@ msp_status msp_plasticity_step(int64_t n, const msp_plasticity_params* params, u
 }
 
 
+msp_status msp_activity_init(int64_t n, const uint8_t* neuron_type,
+                             const msp_activity_params* params, double* v, double* u,
+                             double* calcium, uint8_t* spiked, int32_t* epoch_count, double* freq,
+                             hipStream_t s) {
+  if (n < 1 || !params || !neuron_type || !v || !u || !calcium || !spiked || !epoch_count ||
+      !freq)
+    return MSP_ERR_INVALID;
+  Temp err(s);
+  MSP_HIP_TRY(err.alloc(sizeof(int32_t)));
+  fill_i32_k<<<1, 64, 0, s>>>(err.as<int32_t>(), 1, 0);
+  act_init_k<<<grid_for(n, kActBlock), kActBlock, 0, s>>>(n, neuron_type, act_params(*params), v,
+                                                          u, calcium, spiked, epoch_count, freq,
+                                                          err.as<int32_t>());
+  MSP_HIP_TRY(hipGetLastError());
+  int32_t bad = 0;
+  MSP_HIP_TRY(hipMemcpyAsync(&bad, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MSP_HIP_TRY(hipStreamSynchronize(s));
+  return bad ? MSP_ERR_INVALID : MSP_OK;
+}
+
 msp_status msp_activity_run(int64_t n, const uint8_t* neuron_type, const int32_t* rank,
                             int64_t m, const int32_t* syn_src, const int32_t* syn_tgt,
                             const uint8_t* syn_type, int32_t approx,
@@ -1172,17 +1275,7 @@ msp_status msp_activity_run(int64_t n, const uint8_t* neuron_type, const int32_t
   const msp_activity_params& q = *params;
   if (q.epoch < 1 || !(q.ca_tau > 0.0)) return MSP_ERR_INVALID;
   if (steps == 0) return MSP_OK;
-  ActParams P;
-  P.a[0] = q.a_exc; P.b[0] = q.b_exc; P.c[0] = q.c_exc; P.d[0] = q.d_exc;
-  P.a[1] = q.a_inh; P.b[1] = q.b_inh; P.c[1] = q.c_inh; P.d[1] = q.d_inh;
-  P.w_e = q.w_exc;
-  P.w_i = q.w_inh;
-  P.mu = q.bg_mean;
-  P.width = q.bg_width;
-  P.beta = q.ca_beta;
-  P.inv_tau = 1.0 / q.ca_tau;
-  P.inv_delta = 1.0 / (double)q.epoch;
-  P.delta = q.epoch;
+  const ActParams P = act_params(q);
   Temp arr(s), err(s), part(s), grp(s);
   const int64_t nblocks = (int64_t)grid_for(n, kActBlock);
   // arrival counts (e, h) of two consecutive steps: step k consumes buffer k % 2 and its

@@ -142,6 +142,7 @@ __device__ __forceinline__ bool leaf_entries(const SearchArgs& A, const int32_t*
 // Node records examined and nodes opened (the algorithmic work of one expansion).
 struct Count {
   int32_t visits = 0, opens = 0;
+  int32_t entries = 0;             // level-0 sweep only: entries of the accepted list
 };
 
 // The source's own walk over pre-order positions [x, end) of a start cell's
@@ -248,6 +249,7 @@ struct DiagOut {
   int32_t* opens;
   int32_t* visits0;
   int32_t* opens0;
+  int32_t* entries0;
 };
 
 }  // namespace msp

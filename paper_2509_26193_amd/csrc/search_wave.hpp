@@ -57,6 +57,7 @@ struct SweepOut {
   double* Z;                       // [units][64] level-0 sum of the unit's part
   int32_t* v0;                     // [units][64] level-0 visits (counting launches only)
   int32_t* o0;                     // [units][64] level-0 opens
+  int32_t* e0;                     // [units][64] level-0 accepted entries
   int32_t* nck;                    // [units] checkpoints written
   int32_t* ck_x;                   // [ck_units][ck_slots] wave position
   double* ck_P;                    // [ck_units][ck_slots][64] running sum
@@ -290,6 +291,7 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
           if (cur.v != 0) {
             if (!(meta & kBucketBit)) {
               const int32_t id = (int32_t)(meta & kIdMask);
+              if (DIAG && active && id != i) c0.entries += 1;
               sum.Z = sum.Z + kernel_weight_if(active && id != i, cur.v,
                                                dist2(xi, yi, zi, cur.x, cur.y, cur.z), A.k2);
             } else {                            // several neurons at one finest cell
@@ -301,6 +303,7 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
                 const int32_t id = order[p];
                 const int32_t v = vs[p];
                 if (v == 0) continue;
+                if (DIAG && active && id != i) c0.entries += 1;
                 sum.Z = sum.Z + kernel_weight_if(
                     active && id != i, v,
                     dist2(xi, yi, zi, pos[3 * (int64_t)id], pos[3 * (int64_t)id + 1],
@@ -323,6 +326,7 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
             sum.Z = sum.Z + kernel_weight_if(take, cur.v, d2, A.k2);
             me = take ? sk : me;
             if (DIAG && open) c0.opens += 1;
+            if (DIAG && take) c0.entries += 1;
             // a lane opened x iff it is still active at x (taking moves me past x;
             // inactive and padding lanes have me > x): one compare feeds the ballot
             if (__builtin_amdgcn_ballot_w64(me <= x)) next = x + 1;
@@ -344,6 +348,7 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
   if (DIAG) {
     W.v0[us] = c0.visits;
     W.o0[us] = c0.opens;
+    W.e0[us] = c0.entries;
     if (W.wave_steps && lane == 0) atomicAdd(W.wave_steps, (unsigned long long)steps);
   }
   return steps;
@@ -378,6 +383,7 @@ __device__ __forceinline__ void draw_slot(const SearchArgs& A, const DiagOut& D,
     for (int q = 0; q < np; ++q) {
       c0.visits += W.v0[(u0 + q) * kWave + lane];
       c0.opens += W.o0[(u0 + q) * kWave + lane];
+      c0.entries += W.e0[(u0 + q) * kWave + lane];
     }
   }
   for (int32_t j = 0; j < a; ++j) {
@@ -454,6 +460,7 @@ __device__ __forceinline__ void draw_slot(const SearchArgs& A, const DiagOut& D,
       if (D.opens) D.opens[off + j] = c.opens;
       if (D.visits0) D.visits0[off + j] = c0.visits;
       if (D.opens0) D.opens0[off + j] = c0.opens;
+      if (D.entries0) D.entries0[off + j] = c0.entries;
     }
   }
 }

@@ -281,8 +281,9 @@ class InsertTree:
 
     def search_full(self, agg, vac, i, j, sigma, theta, seed, step):
         """One search with every per-search output of the method's checker: target,
-        level-0 normaliser, the levels drawn, the node records examined and the nodes
-        opened over all levels, and the boundary distance of the draw: at each level
+        level-0 normaliser and the length of the level-0 list, the levels drawn, the node
+        records examined and the nodes opened over all levels, and the boundary
+        distance of the draw: at each level
         the chosen entry covers [P_prev / Z, P / Z) of the cumulative distribution
         (running sums in list order), its distance is min(u - P_prev / Z, P / Z - u),
         and the search's is the smallest over its levels (1 if it never draws).
@@ -290,7 +291,7 @@ class InsertTree:
         entry (Fractions of the same float weights) so that callers can check the
         float distance against exact arithmetic."""
         S = self.root
-        res = dict(target=-1, z0=None, window=1.0, levels=0, visits=0, opens=0)
+        res = dict(target=-1, z0=None, window=1.0, levels=0, visits=0, opens=0, entries0=0)
         exact = []
         for level in range(64):
             lst, nv, no = self.bh_list_counted(agg, vac, i, S, sigma, theta)
@@ -302,6 +303,7 @@ class InsertTree:
                 Z = Z + e[2]
             if res["z0"] is None:
                 res["z0"] = Z
+                res["entries0"] = len(lst)
             if not lst or Z == 0.0:
                 res["target"] = -1
                 return res, exact

@@ -8,7 +8,7 @@ import torch
 import paper_2509_26193_amd as msp
 from oracle import oracle as orc
 from synth_inputs import config_batched
-from gpu_util import T, compare_search, say
+from gpu_util import T, compare_search, compare_targets, say
 
 pytestmark = pytest.mark.gpu
 
@@ -112,3 +112,44 @@ def test_batched_capacity_error_is_per_simulation():
         tgt, off = b.results(k)
         assert np.array_equal(tgt.cpu().numpy(), ref[k][0])
     b.free()
+
+
+def test_config4_64_simulations_against_oracle():
+    """The 64-simulation workload (2^12..2^18 neurons each, 4.0M in all) as the benchmark
+    runs it (one autotuned, graph-captured batch): every search of the simulations with
+    at most 2^14 neurons and 20,000 sampled searches of each larger one against the
+    oracle."""
+    ws = config_batched()
+    sims = []
+    for k, w in enumerate(ws):
+        tree = msp.build_octree(T(w.pos, torch.float64), w.box_min, w.box_edge)
+        msp.update_vacant_counts(tree, T(w.vac_exc, torch.int32), T(w.vac_inh, torch.int32))
+        sims.append(dict(tree=tree, neuron_type=T(w.neuron_type, torch.uint8),
+                         vac_axon=T(w.vac_axon, torch.int32), sigma=w.sigma, seed=w.seed + k))
+    b = msp.Batch(sims, graph=True, autotune=True)
+    b.run(0.3, 0)
+    b.run(0.3, 0)                       # the replay of the captured graph
+    torch.cuda.synchronize()
+    assert b.status() == [0] * len(ws)
+    rng = np.random.default_rng(404)
+    checked = small = 0
+    for k, w in enumerate(ws):
+        tgt, off = b.results(k)
+        g = tgt.cpu().numpy().astype(np.int64)
+        t = orc.OracleTree(w.pos, w.box_min, w.box_edge)
+        t.update_counts(w.vac_exc, w.vac_inh)
+        ooff, src, elem = orc.search_list(w.vac_axon)
+        assert np.array_equal(off.cpu().numpy(), ooff), k
+        if w.n <= (1 << 14):
+            q = np.arange(src.size)
+            small += 1
+        else:
+            q = np.sort(rng.choice(src.size, size=min(20000, src.size), replace=False))
+        o = t.find_targets(w.neuron_type, w.sigma, 0.3, w.seed + k, 0, src[q], elem[q])
+        compare_targets(g[q], o, f"sim {k} n={w.n}")
+        checked += q.size
+        del t
+    say(f"64 simulations: {small} checked in full, {checked} searches against the oracle")
+    b.free()
+    for d in sims:
+        d["tree"].free()

@@ -107,6 +107,7 @@ def test_search_small(theta):
     # the kernel examines exactly the oracle's node records (same acceptance decisions)
     assert np.array_equal(g["visits"][same], o["visits"][same])
     assert np.array_equal(g["opens"][same], o["opens"][same])
+    assert np.array_equal(g["entries0"], o["entries0"])      # level 0: independent of the draw
     g["tree"].free()
 
 

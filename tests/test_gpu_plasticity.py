@@ -164,8 +164,11 @@ def _sync_oracle(onet, dnet):
 
 def test_device_loop_8388608_matches_oracle():
     """Three updates of the 8M workload entirely on the device (search, commit, record,
-    plasticity step). Per update the oracle starts from the device's state, samples the
-    searches, and replays the commit of the device's proposals and the step."""
+    plasticity step), the search being the benchmark's plain call (no diagnostics). Per
+    update a counting call gives the same targets bitwise and the normalisers, the
+    oracle starts from the device's state, checks 65,536 sampled searches, and replays
+    the commit of the device's proposals and the step: every update's network must
+    equal the oracle's bitwise."""
     w = config_large()
     tree = msp.build_octree(T(w.pos, torch.float64), w.box_min, w.box_edge)
     ty = T(w.neuron_type, torch.uint8)
@@ -180,7 +183,9 @@ def test_device_loop_8388608_matches_oracle():
         _sync_oracle(onet, dnet)
         a, e, i = (v.cpu().numpy() for v in (ga, ge, gi))
         msp.update_vacant_counts(tree, ge, gi)
-        tgt, off, z0, _ = msp.find_targets(tree, ty, ga, w.sigma, w.theta, w.seed, step, diag=True)
+        tgt, off = msp.find_targets(tree, ty, ga, w.sigma, w.theta, w.seed, step)
+        tgt_c, _, z0, _ = msp.find_targets(tree, ty, ga, w.sigma, w.theta, w.seed, step, diag=True)
+        assert torch.equal(tgt, tgt_c), step
         res = msp.commit_synapses(tgt, off, ty, ga, ge, gi, w.seed, step)
         dnet.record(res["syn_src"], res["syn_tgt"], res["syn_type"])
         ga, ge, gi = dnet.step(w.seed, step)
@@ -188,7 +193,7 @@ def test_device_loop_8388608_matches_oracle():
         gt = tgt.cpu().numpy().astype(np.int64)
         otree.update_counts(e, i)
         ooff, src, elem = orc.search_list(a)
-        pick = np.sort(rng.choice(src.size, size=min(32768, src.size), replace=False))
+        pick = np.sort(rng.choice(src.size, size=min(65536, src.size), replace=False))
         o = otree.find_targets(w.neuron_type, w.sigma, w.theta, w.seed, step, src[pick], elem[pick])
         diff = gt[pick] != o["target"]
         pos = o["z0"] > 0
@@ -203,5 +208,5 @@ def test_device_loop_8388608_matches_oracle():
         onet.record(oc["syn_src"], oc["syn_tgt"], oc["syn_type"])
         ovac = onet.step(w.seed, step)
         agreed += _compare_networks(dnet, onet, (ga, ge, gi), ovac, f"8M update {step}")
-    assert agreed >= 2
+    assert agreed == 3
     tree.free()

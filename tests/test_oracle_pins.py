@@ -233,8 +233,8 @@ def _counted_cases():
 @pytest.mark.parametrize("theta", [0.0, 0.2, 0.3, 0.5, 0.9])
 def test_window_and_work_counters_match_independent_search(theta):
     """The oracle's boundary distance of the draw (the only quantity that excuses a
-    differing choice) and its visit/open counters (the numerator of the roofline) per
-    search, against an independent Barnes-Hut written from Sec. III-B ("Division of
+    differing choice) and its visit/open/entry counters (the numerator of the roofline)
+    per search, against an independent Barnes-Hut written from Sec. III-B ("Division of
     work": the list, the draw by probability, the restart): bitwise equal, and the
     distance equal to exact rational arithmetic on the same weights to 1e-12."""
     for label, pos in _counted_cases():
@@ -262,6 +262,7 @@ def test_window_and_work_counters_match_independent_search(theta):
             assert r["visits"][q] == b["visits"], (label, q, r["visits"][q], b["visits"])
             assert r["opens"][q] == b["opens"], (label, q, r["opens"][q], b["opens"])
             assert r["window"][q] == b["window"], (label, q, r["window"][q], b["window"])
+            assert r["entries0"][q] == b["entries0"], (label, q)
             # the chosen entry's exact interval holds u, and the float distance is the
             # exact one up to the rounding of the running sums
             we = 1.0
