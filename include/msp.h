@@ -65,16 +65,17 @@ typedef struct msp_octree_s* msp_octree;
  * Build the octree over n neurons (Sec. III-B, "Spatial octree"; "Division of the
  * simulation domain" for the Morton-indexed cells).
  *   pos       [n][3] float64, row-major (x, y, z) per neuron, micrometres.
- *   box_min   (host) [3] minimum corner of the cubic domain; box_edge (host) > 0 its
- *             edge. Each axis is quantised to 21 bits, q = floor((x - min) / edge * 2^21),
- *             clamped into [0, 2^21 - 1] (positions outside the cube fall in edge cells).
+ *   box_min   (host) [3] minimum corner of the cubic domain; box_edge (host) its edge,
+ *             in [2^-480, 2^480]. Each axis is quantised to 21 bits,
+ *             q = floor((x - min) / edge * 2^21), clamped into [0, 2^21 - 1] (positions
+ *             outside the cube fall in edge cells).
  *   leaf_size must be 1: a leaf holds one neuron, except that neurons whose quantised
  *             positions coincide share one depth-21 leaf.
  *   out       (host) receives the handle. The library owns every node array.
- * Errors: MSP_ERR_INVALID for n < 1 or n > MSP_MAX_NEURONS, non-finite or non-positive
- * box, leaf_size != 1, null pointers; MSP_ERR_OOM. A non-finite position sets the
- * device error flag. The build waits on `s` twice (to size the node arrays and the
- * per-depth lists); its last kernels may still run when it returns.
+ * Errors: MSP_ERR_INVALID for n < 1 or n > MSP_MAX_NEURONS, a non-finite box corner, an
+ * edge outside that range, leaf_size != 1, null pointers; MSP_ERR_OOM. A non-finite
+ * position sets the device error flag. The build waits on `s` twice (to size the node
+ * arrays and the per-depth lists); its last kernels may still run when it returns.
  */
 msp_status msp_build_octree(const double* pos, int64_t n, const double box_min[3],
                             double box_edge, int32_t leaf_size, hipStream_t s,

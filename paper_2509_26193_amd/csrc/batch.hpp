@@ -102,7 +102,8 @@ __device__ __forceinline__ SearchArgs args_of(const SimDesc* sims, int s, const 
 // that die's L2), then from the other dies' ranges. A unit's simulation is found from
 // the unit bases.
 template <bool DIAG, int SLOTS, bool OWN>
-__global__ void __launch_bounds__(kWaveBlock) search_sweep_k(BatchDev B, SweepOut W) {
+__global__ void __launch_bounds__(kWaveBlock) __attribute__((amdgpu_num_sgpr(94)))
+search_sweep_k(BatchDev B, SweepOut W) {
   const int lane = threadIdx.x & (kWave - 1);
   const int home = blockIdx.x % kXcd;
   const int nunits = *W.unit_count;

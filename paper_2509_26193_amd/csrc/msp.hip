@@ -280,7 +280,10 @@ msp_status msp_build_octree(const double* pos, int64_t n, const double box_min[3
   if (!out) return MSP_ERR_INVALID;
   *out = nullptr;
   if (!pos || !box_min || n < 1 || n > MSP_MAX_NEURONS || leaf_size != 1) return MSP_ERR_INVALID;
-  if (!std::isfinite(box_edge) || !(box_edge > 0.0)) return MSP_ERR_INVALID;
+  // the cube edge's square lowered by 4^21 (the finest cell's) must stay a normal double
+  if (!std::isfinite(box_edge) || !(box_edge >= std::ldexp(1.0, -480)) ||
+      !(box_edge <= std::ldexp(1.0, 480)))
+    return MSP_ERR_INVALID;
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(box_min[a])) return MSP_ERR_INVALID;
 

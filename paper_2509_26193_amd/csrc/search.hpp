@@ -53,24 +53,47 @@ struct SearchArgs {
 constexpr double kMaxY = kUnderflowX * kLog2e;   // exp(-x) == 0 in float64 beyond this
 
 // Barnes-Hut acceptance of an inner node at depth dep (edge L 2^-dep) seen from
-// squared distance d2: (L 2^-dep)^2 < theta^2 d2, evaluated as L^2 < theta^2 d2 4^dep
-// (scaling by a power of two is exact, so both forms decide identically).
-// `meta_hi` = meta >> (kSkipBits - 1): its bits 1..5 are 2*dep for an inner node.
-__device__ __forceinline__ bool bh_accept(double L2, double theta2, double d2, uint32_t meta_hi) {
-  return L2 < ldexp(theta2 * d2, (int)(meta_hi & 62u));
+// squared distance d2: (L 2^-dep)^2 < theta^2 d2 (scalings by powers of two are exact,
+// so the forms below decide identically). `meta` is the node's record meta word.
+//   bh_accept:   L^2 < theta^2 d2 4^dep (one ldexp of the lane's product);
+//   bh_accept_u: L^2 4^-dep < theta^2 d2, the squared edge made from L^2 by lowering its
+//                exponent by 2 dep: for a wave-uniform meta that is scalar integer work.
+//                Exact because the build accepts only cubes whose L^2 4^-21 is a
+//                normal double.
+__device__ __forceinline__ bool bh_accept(double L2, double theta2, double d2, uint32_t meta) {
+  return L2 < ldexp(theta2 * d2, (int)((meta >> (kSkipBits - 1)) & 62u));
+}
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double edge2_at(double L2, uint32_t meta) {
+  u32x2 w = __builtin_bit_cast(u32x2, L2);
+  w.y -= ((meta >> kSkipBits) & 31u) << 21;
+  return __builtin_bit_cast(double, w);
+}
+
+__device__ __forceinline__ bool bh_accept_u(double L2, double theta2, double d2, uint32_t meta) {
+  return edge2_at(L2, meta) < theta2 * d2;
 }
 
 // v * 2^-y with y = d2 * k2 (= v exp(-d2 / sigma^2)), or exactly 0 where `keep` is
 // false or exp(-d2 / sigma^2) underflows in float64. Branch-free: the walks evaluate
 // it on every lane. A dropped entry gets the exponent -2048, which takes any
 // v * mant < 2^31 to 0, so the mask costs one 32-bit select instead of a 64-bit one.
-__device__ __forceinline__ double kernel_weight_if(bool keep, int32_t v, double d2, double k2) {
-  const double y = fmin(d2 * k2, 2048.0);         // keeps the integer part in range
+// -floor(y) is the hardware's truncating conversion of -y (y >= 0), which saturates
+// out of range; it is used only where y <= kMaxY.
+__device__ __forceinline__ double kernel_weight_vd(bool keep, double vd, double d2, double k2) {
+  const double y = d2 * k2;
   const double fr = __builtin_amdgcn_fract(y);
-  const int nfl = (int)(-y);                      // -floor(y): truncation, as y >= 0
+  int nfl;
+  asm("v_cvt_i32_f64_e64 %0, -%1" : "=v"(nfl) : "v"(y));
   const int e = (keep && y <= kMaxY) ? nfl : -2048;
   const double mant = (double)__builtin_amdgcn_exp2f(-(float)fr);
-  return ldexp((double)v * mant, e);
+  return ldexp(vd * mant, e);
+}
+
+__device__ __forceinline__ double kernel_weight_if(bool keep, int32_t v, double d2, double k2) {
+  return kernel_weight_vd(keep, (double)v, d2, k2);
 }
 
 __device__ __forceinline__ double kernel_weight(int32_t v, double d2, double k2) {
@@ -171,7 +194,7 @@ __device__ void expand_range(const SearchArgs& A, const NodeRec* __restrict__ R,
       continue;
     }
     const double d2 = dist2(xi, yi, zi, r.x, r.y, r.z);
-    if (bh_accept(A.L2, A.theta2, d2, r.meta >> (kSkipBits - 1))) {
+    if (bh_accept(A.L2, A.theta2, d2, r.meta)) {
       if (f(x, false, r.v, d2)) return;
       x = sk;
     } else {

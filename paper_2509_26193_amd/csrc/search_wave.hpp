@@ -186,7 +186,7 @@ __device__ __forceinline__ int32_t mask_at(const SearchArgs& A, cptr<NodeRec> R,
       if (r.v != 0) {
         const double d2 = dist2(xi, yi, zi, r.x, r.y, r.z);
         const bool contains = OWN && (uint32_t)(li - y) < (uint32_t)(sk - y);
-        out = !contains && bh_accept(A.L2, A.theta2, d2, r.meta >> (kSkipBits - 1));
+        out = !contains && bh_accept_u(A.L2, A.theta2, d2, r.meta);
       }
       if (me <= y && out) me = sk;
       y = y + 1;
@@ -282,58 +282,78 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
       int left = chunk;
       do {
         // one node: uniform branches on its kind, per-lane decisions as lane masks, the
-        // weight evaluated on every lane and added where the lane takes the entry
+        // weight evaluated on every lane and added where the lane takes the entry. The
+        // next record's load is issued as soon as the next node is known (a leaf's at
+        // once, an inner node's after the ballot), so it is in flight while this node's
+        // weights are computed.
+        // Lane decisions are lane masks: a ballot of each compare (its mask itself),
+        // combined on the scalar unit, and turned back into a lane condition where a
+        // select needs one (inverse ballot: the same mask).
         const uint32_t meta = cur.meta;
-        const bool active = x >= me;
+        const uint64_t m_act = __builtin_amdgcn_ballot_w64(x >= me);
+        const bool active = __builtin_amdgcn_inverse_ballot_w64(m_act);
         if (DIAG && active) c0.visits += 1;
-        int32_t next = x + 1;
+        int32_t next;
+        NodeRec nxt;
         if ((int32_t)meta < 0) {                               // leaf
-          if (cur.v != 0) {
-            if (!(meta & kBucketBit)) {
-              const int32_t id = (int32_t)(meta & kIdMask);
+          next = x + 1;                                        // index N: the sentinel
+          if (cur.v == 0) {
+            nxt = load_rec_u(R, (uint32_t)next);
+          } else if (!(meta & kBucketBit)) {
+            const int32_t id = (int32_t)(meta & kIdMask);
+            const bool keep = active && id != i;
+            if (DIAG && keep) c0.entries += 1;
+            const double d2 = dist2(xi, yi, zi, cur.x, cur.y, cur.z);
+            const double vd = (double)cur.v;
+            // the record is no longer needed: its registers take the next one; the
+            // weight is computed while the load is in flight (no instruction of it may
+            // be scheduled above the load)
+            nxt = load_rec_u(R, (uint32_t)next);
+            __builtin_amdgcn_sched_barrier(0);
+            sum.Z = sum.Z + kernel_weight_vd(keep, vd, d2, A.k2);
+          } else {                              // several neurons at one finest cell
+            nxt = load_rec_u(R, (uint32_t)next);
+            const cptr<int32_t> vs = as_const(A.vs[t]);
+            const cptr<int32_t> order = as_const(A.order);
+            const cptr<double> pos = as_const(A.pos);
+            const int32_t pe = as_const(A.nend)[x];
+            for (int32_t p = as_const(A.nbeg)[x]; p < pe; ++p) {
+              const int32_t id = order[p];
+              const int32_t v = vs[p];
+              if (v == 0) continue;
               if (DIAG && active && id != i) c0.entries += 1;
-              sum.Z = sum.Z + kernel_weight_if(active && id != i, cur.v,
-                                               dist2(xi, yi, zi, cur.x, cur.y, cur.z), A.k2);
-            } else {                            // several neurons at one finest cell
-              const cptr<int32_t> vs = as_const(A.vs[t]);
-              const cptr<int32_t> order = as_const(A.order);
-              const cptr<double> pos = as_const(A.pos);
-              const int32_t pe = as_const(A.nend)[x];
-              for (int32_t p = as_const(A.nbeg)[x]; p < pe; ++p) {
-                const int32_t id = order[p];
-                const int32_t v = vs[p];
-                if (v == 0) continue;
-                if (DIAG && active && id != i) c0.entries += 1;
-                sum.Z = sum.Z + kernel_weight_if(
-                    active && id != i, v,
-                    dist2(xi, yi, zi, pos[3 * (int64_t)id], pos[3 * (int64_t)id + 1],
-                          pos[3 * (int64_t)id + 2]),
-                    A.k2);
-              }
+              sum.Z = sum.Z + kernel_weight_if(
+                  active && id != i, v,
+                  dist2(xi, yi, zi, pos[3 * (int64_t)id], pos[3 * (int64_t)id + 1],
+                        pos[3 * (int64_t)id + 2]),
+                  A.k2);
             }
           }
-        } else {
-          int32_t sk = (int32_t)(meta & kSkipMask);
-          sk = sk > x ? sk : x + 1;
-          next = sk;
-          if (cur.v != 0) {
-            const double d2 = dist2(xi, yi, zi, cur.x, cur.y, cur.z);
-            // li in [x, sk) (padding lanes have li = -1, far above sk - x unsigned)
-            const bool contains = OWN && (uint32_t)(li - x) < (uint32_t)(sk - x);
-            const bool far = !contains && bh_accept(A.L2, A.theta2, d2, meta >> (kSkipBits - 1));
-            const bool take = active && far;
-            const bool open = active && !far;
-            sum.Z = sum.Z + kernel_weight_if(take, cur.v, d2, A.k2);
-            me = take ? sk : me;
-            if (DIAG && open) c0.opens += 1;
-            if (DIAG && take) c0.entries += 1;
-            // a lane opened x iff it is still active at x (taking moves me past x;
-            // inactive and padding lanes have me > x): one compare feeds the ballot
-            if (__builtin_amdgcn_ballot_w64(me <= x)) next = x + 1;
-          }
+        } else if (cur.v == 0) {                // no vacancy below: over the subtree
+          next = (int32_t)(meta & kSkipMask);
+          nxt = load_rec_u(R, (uint32_t)next);
+        } else {                                               // inner node
+          const int32_t sk = (int32_t)(meta & kSkipMask);     // > x
+          const double d2 = dist2(xi, yi, zi, cur.x, cur.y, cur.z);
+          uint64_t m_far = __builtin_amdgcn_ballot_w64(bh_accept_u(A.L2, A.theta2, d2, meta));
+          // li in [x, sk) (padding lanes have li = -1, far above sk - x unsigned)
+          if (OWN) m_far &= ~__builtin_amdgcn_ballot_w64((uint32_t)(li - x) < (uint32_t)(sk - x));
+          const uint64_t m_take = m_act & m_far;
+          const uint64_t m_open = m_act & ~m_far;
+          const double vd = (double)cur.v;
+          // the wave descends iff a lane opens x; the record is no longer needed: its
+          // registers take the next one
+          next = m_open ? x + 1 : sk;
+          nxt = load_rec_u(R, (uint32_t)next);
+          __builtin_amdgcn_sched_barrier(0);
+          const bool take = __builtin_amdgcn_inverse_ballot_w64(m_take);
+          sum.Z = sum.Z + kernel_weight_vd(take, vd, d2, A.k2);
+          me = take ? sk : me;
+          if (DIAG && __builtin_amdgcn_inverse_ballot_w64(m_open)) c0.opens += 1;
+          if (DIAG && take) c0.entries += 1;
         }
-        x = next < end ? next : end;
-        cur = load_rec_u(R, (uint32_t)x);     // index N: the sentinel record
+        x = next;
+        cur = nxt;
         if (x >= end) {
           --left;
           break;

@@ -73,6 +73,41 @@ def test_backward_matches_central_differences():
     g["tree"].free()
 
 
+def _golden_fd():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "attraction_262144_fd.txt")
+    coords, ds = [], None
+    with open(path) as f:
+        for ln in f:
+            if ln.startswith("#") or not ln.strip():
+                continue
+            a, b, v = ln.split()
+            if a == "sigma":
+                ds = float(v)
+            else:
+                coords.append((int(a), int(b), float(v)))
+    return coords, ds
+
+
+def test_backward_matches_central_differences_262144():
+    """The 262,144-neuron workload itself: the adjoint at 64 seeded coordinates and in
+    sigma against central differences (h = 1e-3 um) of the oracle's frozen-set forward,
+    written to tests/golden by tests/golden/make_attraction_fd.py (oracle only)."""
+    w = config_attraction()
+    coords, fd_s = _golden_fd()
+    assert len(coords) == 64 and fd_s is not None
+    g = _gpu(w, w.theta)
+    worst = 0.0
+    for i, a, fd in coords:
+        tol = 1e-4 * abs(fd) + 1e-9
+        worst = max(worst, abs(g["dpos"][i, a] - fd) / tol)
+        assert abs(g["dpos"][i, a] - fd) <= tol, (i, a, fd, g["dpos"][i, a])
+    say(f"64 coordinates: worst error / tolerance {worst:.3f}; sigma: fd {fd_s:.8e} "
+        f"gpu {g['ds']:.8e}")
+    assert g["ds"] == pytest.approx(fd_s, rel=1e-5)
+    g["tree"].free()
+
+
 def test_theta0_direct_gradient_on_4096_subset():
     full = config_attraction()
     n = 4096
