@@ -56,6 +56,8 @@ typedef int32_t msp_status;
 #define MSP_ERR_CAPACITY      (-4)  /* an output buffer is too small; nothing written */
 #define MSP_ERR_DEVICE        (-5)  /* data error detected on the device              */
 #define MSP_ERR_UNIMPLEMENTED (-6)
+#define MSP_ERR_TOO_LARGE     (-7)  /* beyond the fixed working memory of an
+                                       allocation-free entry point                   */
 
 #define MSP_MAX_NEURONS (1LL << 25)
 
@@ -127,6 +129,25 @@ msp_status msp_find_targets(msp_octree t, const uint8_t* neuron_type, const int3
                             double sigma_um, double theta, uint64_t seed, uint64_t step,
                             int32_t* target_out, int64_t* elem_offset_out, int64_t capacity_S,
                             hipStream_t s);
+
+/*
+ * msp_find_targets without any memory allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid device
+ * allocation). Same arguments, results and errors as msp_find_targets (targets
+ * bitwise equal), one phase, no diagnostics. Its working memory is one fixed array
+ * per device inside the library's code object (40 MiB, held by every device the
+ * library runs on until the process ends), enough for n <= MSP_NOALLOC_MAX_NEURONS;
+ * a larger octree returns MSP_ERR_TOO_LARGE before anything is queued, and a call
+ * while another device than the octree's is current MSP_ERR_INVALID. Every call on
+ * one device shares that array: calls that overlap on a device (on different
+ * streams, or from different host threads) race and must be ordered by the caller.
+ * The call waits on `s` once, after the worklist is built, to read the status.
+ */
+#define MSP_NOALLOC_MAX_NEURONS (1LL << 16)
+msp_status msp_find_targets_noalloc(msp_octree t, const uint8_t* neuron_type,
+                                    const int32_t* vac_axon, double sigma_um, double theta,
+                                    uint64_t seed, uint64_t step, int32_t* target_out,
+                                    int64_t* elem_offset_out, int64_t capacity_S, hipStream_t s);
 
 /*
  * The searches msp_find_targets will run, so that a caller can size target_out:

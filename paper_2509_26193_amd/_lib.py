@@ -23,6 +23,8 @@ MSP_ERR_HIP = -3
 MSP_ERR_CAPACITY = -4
 MSP_ERR_DEVICE = -5
 MSP_ERR_UNIMPLEMENTED = -6
+MSP_ERR_TOO_LARGE = -7
+MSP_NOALLOC_MAX_NEURONS = 1 << 16
 
 
 class MspError(RuntimeError):
@@ -70,6 +72,8 @@ _SIGS = {
     "msp_build_octree": (_i32, [_vp, _i64, _vp, _dbl, _i32, _vp, ctypes.POINTER(_vp)]),
     "msp_update_vacant_counts": (_i32, [_vp, _vp, _vp, _vp]),
     "msp_find_targets": (_i32, [_vp, _vp, _vp, _dbl, _dbl, _u64, _u64, _vp, _vp, _i64, _vp]),
+    "msp_find_targets_noalloc": (_i32, [_vp, _vp, _vp, _dbl, _dbl, _u64, _u64, _vp, _vp, _i64,
+                                        _vp]),
     "msp_find_targets_diag": (_i32, [_vp, _vp, _vp, _dbl, _dbl, _u64, _u64, _vp, _vp, _i64,
                                      ctypes.POINTER(SearchDiag), _vp]),
     "msp_commit_synapses": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _u64, _u64, _vp, _vp, _vp,

@@ -232,6 +232,39 @@ class WorkspaceLease {
   bool leased_ = false;
 };
 
+// Working memory of msp_find_targets_noalloc: one fixed array per device, part of the
+// code object (no allocation call). Sized for a search over MSP_NOALLOC_MAX_NEURONS
+// neurons with kCkptMin checkpoint slots per tile, plus its descriptor and bases.
+constexpr size_t kNoAllocBytes = (size_t)40 << 20;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+// Device address of `scratch` on `device` (the array's name is a host-side stand-in,
+// not a device address): resolved once per device with that device current.
+hipError_t noalloc_scratch(int device, void** out) {
+  static std::mutex m;
+  static void* addr[64] = {};
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(m);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *out = addr[device];
+  return hipSuccess;
+}
+
+// The search's descriptor and neuron bases written by a kernel (arguments by value):
+// no host-to-device copy.
+__global__ void put_desc_k(SimDesc h, SimDesc* d, int64_t* base, int64_t n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *d = h;
+    base[0] = 0;
+    base[1] = n;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -245,6 +278,8 @@ const char* msp_status_string(msp_status st) {
     case MSP_ERR_CAPACITY: return "output capacity exceeded";
     case MSP_ERR_DEVICE: return "data error detected on the device";
     case MSP_ERR_UNIMPLEMENTED: return "not implemented";
+    case MSP_ERR_TOO_LARGE:
+      return "problem larger than the fixed working memory of the allocation-free entry point";
     default: return "unknown status";
   }
 }
@@ -607,6 +642,51 @@ msp_status msp_find_targets(msp_octree t, const uint8_t* neuron_type, const int3
                             hipStream_t s) {
   return msp_find_targets_diag(t, neuron_type, vac_axon, sigma_um, theta, seed, step, target_out,
                                elem_offset_out, capacity_S, nullptr, s);
+}
+
+msp_status msp_find_targets_noalloc(msp_octree t, const uint8_t* neuron_type,
+                                    const int32_t* vac_axon, double sigma_um, double theta,
+                                    uint64_t seed, uint64_t step, int32_t* target_out,
+                                    int64_t* elem_offset_out, int64_t capacity_S, hipStream_t s) {
+  if (!handle_ok(t) || !neuron_type || !vac_axon || !elem_offset_out) return MSP_ERR_INVALID;
+  if (!t->refreshed) return MSP_ERR_INVALID;
+  if (!std::isfinite(sigma_um) || !(sigma_um > 0.0) || !std::isfinite(theta) || !(theta >= 0.0))
+    return MSP_ERR_INVALID;
+  if (capacity_S < 0) return MSP_ERR_INVALID;
+  const int64_t n = t->n;
+  if (n > MSP_NOALLOC_MAX_NEURONS) return MSP_ERR_TOO_LARGE;
+  int cur = -1;
+  MSP_HIP_TRY(hipGetDevice(&cur));
+  if (cur != t->device) return MSP_ERR_INVALID;   // the array of the tree's device
+  // the same layout as msp_find_targets' workspace, with kCkptMin slots and one
+  // checkpoint region per tile; the descriptor and the neuron bases follow it
+  const size_t body = scratch_sizes(n, 1, kCkptMin).total;
+  const size_t need = body + align_up(sizeof(SimDesc)) + align_up(2 * sizeof(int64_t));
+  if (need > kNoAllocBytes) return MSP_ERR_TOO_LARGE;
+  void* base = nullptr;
+  MSP_HIP_TRY(noalloc_scratch(t->device, &base));
+  char* p = static_cast<char*>(base);
+  SimDesc* dsim = reinterpret_cast<SimDesc*>(p + body);
+  int64_t* dbase = reinterpret_cast<int64_t*>(p + body + align_up(sizeof(SimDesc)));
+  const SimDesc h = make_desc(t, neuron_type, vac_axon, sigma_um, theta, seed, step, target_out,
+                              elem_offset_out, capacity_S);
+  put_desc_k<<<1, 64, 0, s>>>(h, dsim, dbase, n);
+  MSP_HIP_TRY(hipGetLastError());
+  SearchScratch S = carve(base, n, 1, kCkptMin, dsim, dbase);
+  S.own_cell = own_cell_needed(t, theta);
+  MSP_HIP_TRY(enqueue_prep(S, n, s));
+  int32_t status = 0, ntiles = 0, nunits = 0;
+  MSP_HIP_TRY(hipMemcpyAsync(&status, S.B.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MSP_HIP_TRY(hipMemcpyAsync(&ntiles, S.counters, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MSP_HIP_TRY(hipMemcpyAsync(&nunits, S.W.unit_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MSP_HIP_TRY(hipStreamSynchronize(s));
+  if (status & kSimInvalid) return MSP_ERR_INVALID;
+  if (status & kSimCapacity) return MSP_ERR_CAPACITY;
+  if (ntiles == 0) return MSP_OK;
+  unsigned blocks = 0;
+  MSP_HIP_TRY(sweep_blocks_for(t->device, false, nunits, 1.0, &blocks));
+  MSP_HIP_TRY(enqueue_search(S, false, blocks, 256, s));
+  return MSP_OK;
 }
 
 msp_status msp_commit_synapses_ex(const int32_t* target, const int64_t* elem_offset,
