@@ -241,7 +241,9 @@ typedef struct msp_batch_s* msp_batch;
 #define MSP_BATCH_GRAPH    1    /* capture the launches in a HIP graph on the first run,
                                    replay it afterwards */
 #define MSP_BATCH_AUTOTUNE 2    /* on the first run, time several launch shapes (sweep
-                                   occupancy, draw block size) and keep the fastest */
+                                   occupancy, draw block size, checkpoint slots per
+                                   region; each the median of 3 timed runs) and keep
+                                   the fastest (the targets do not depend on them) */
 
 /* Create a plan over n_sims >= 1 simulations on the current device (host array sims,
  * copied). Errors: MSP_ERR_INVALID (bad handle, unrefreshed octree, bad sigma,

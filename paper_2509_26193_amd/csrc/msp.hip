@@ -882,41 +882,63 @@ hipError_t batch_enqueue(msp_batch_s* b, hipStream_t s) {
   return enqueue_search(b->S, false, b->sweep_blocks, b->draw_block, s);
 }
 
-// Time launch shapes on the current descriptors and keep the fastest.
+// Time launch shapes on the current descriptors and keep the fastest: the sweep's
+// occupancy, the draw's block size and the checkpoint depth (slots per region: the
+// plan's own, and kCkptMin where the plan holds more; the scratch carved for more
+// slots holds fewer). Each shape is timed kTuneReps times after one untimed run, and
+// its median counts. The targets do not depend on the shape.
+constexpr int kTuneReps = 3;
+
 hipError_t batch_autotune(msp_batch_s* b, hipStream_t s) {
   const double fracs[] = {1.0, 0.75, 0.5};
   const int draws[] = {256, 128, 64};
+  const int slots_opts[] = {b->ck_slots, kCkptMin};
+  const int n_slots = b->ck_slots == kCkptMin ? 1 : 2;
   const int64_t max_units = max_units_for(b->total_n, b->nsims);
   hipEvent_t e0, e1;
   hipError_t e = hipEventCreate(&e0);
   if (e != hipSuccess) return e;
   e = hipEventCreate(&e1);
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return e;
+  }
   float best = 1e30f;
   unsigned best_blocks = b->sweep_blocks;
   int best_draw = b->draw_block;
-  for (double f : fracs) {
-    for (int d : draws) {
-      unsigned blocks = 0;
-      if ((e = sweep_blocks_for(b->device, false, max_units, f, &blocks)) != hipSuccess) break;
-      b->sweep_blocks = blocks;
-      b->draw_block = d;
-      float ms = 0.0f;
-      if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
-      if ((e = batch_enqueue(b, s)) != hipSuccess) break;
-      if ((e = hipEventRecord(e1, s)) != hipSuccess) break;
-      if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best) {
-        best = ms;
-        best_blocks = blocks;
-        best_draw = d;
+  int best_slots = b->S.W.ck_slots;
+  for (int si = 0; si < n_slots && e == hipSuccess; ++si) {
+    for (double f : fracs) {
+      for (int d : draws) {
+        unsigned blocks = 0;
+        if ((e = sweep_blocks_for(b->device, false, max_units, f, &blocks)) != hipSuccess) break;
+        b->sweep_blocks = blocks;
+        b->draw_block = d;
+        b->S.W.ck_slots = slots_opts[si];
+        float t[kTuneReps + 1];
+        for (int r = 0; r <= kTuneReps && e == hipSuccess; ++r) {
+          if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
+          if ((e = batch_enqueue(b, s)) != hipSuccess) break;
+          if ((e = hipEventRecord(e1, s)) != hipSuccess) break;
+          if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+          (void)hipEventElapsedTime(&t[r], e0, e1);
+        }
+        if (e != hipSuccess) break;
+        std::sort(t + 1, t + kTuneReps + 1);       // run 0 is the untimed warm-up
+        const float ms = t[1 + kTuneReps / 2];
+        if (ms < best) {
+          best = ms;
+          best_blocks = blocks;
+          best_draw = d;
+          best_slots = slots_opts[si];
+        }
       }
+      if (e != hipSuccess) break;
     }
-    if (e != hipSuccess) break;
   }
   b->sweep_blocks = best_blocks;
   b->draw_block = best_draw;
+  b->S.W.ck_slots = best_slots;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return e;
