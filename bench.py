@@ -466,11 +466,14 @@ def bench_batched(msp, torch, reps=5):
 
 
 def bench_plasticity(msp, torch, updates=3):
-    """The first updates of the 100-update workload (2^23 neurons uniform in a 20,000 um
-    cube), entirely on the device: the octree is built once (positions are fixed); each
-    update refreshes the vacancies, searches and commits, then records the new synapses
-    and runs the plasticity step (growth, deletion, retraction) that gives the next
-    update's vacancies."""
+    """The 100-update workload (2^23 neurons uniform in a 20,000 um cube), entirely on
+    the device, run twice from the same start: (1) made of the separate calls, which
+    read counts back between phases; (2) as update cycles (msp_cycle) replayed from a
+    captured HIP graph, the host reading one status word per update. Each update
+    refreshes the vacancies, searches and commits, then records the new synapses and
+    runs the plasticity step (growth, deletion, retraction) that gives the next
+    update's vacancies. The octree is built once (positions are fixed). Both runs must
+    end in the same network."""
     from synth_inputs import config_large
     dev = torch.device("cuda:0")
     T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
@@ -481,18 +484,18 @@ def bench_plasticity(msp, torch, updates=3):
     net = msp.Network(ga, ge, gi, capacity=4 * w.n)
     per = []
     for step in range(updates):
-        S = int(ga.sum().item())
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         msp.update_vacant_counts(tree, ge, gi)
         tgt, off = msp.find_targets(tree, ty, ga, w.sigma, w.theta, w.seed, step)
-        res = msp.commit_synapses(tgt, off, ty, ga, ge, gi, w.seed, step, syn_capacity=S)
+        res = msp.commit_synapses(tgt, off, ty, ga, ge, gi, w.seed, step)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         net.record(res["syn_src"], res["syn_tgt"], res["syn_type"])
         ga, ge, gi = net.step(w.seed, step)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        S = int(off[-1].item())
         m = int(res["n_formed"])
         per.append(dict(update=step, searches=S, formed=m, synapses=net.m,
                         connectivity_ms=(t1 - t0) * 1e3, plasticity_ms=(t2 - t1) * 1e3,
@@ -501,16 +504,40 @@ def bench_plasticity(msp, torch, updates=3):
             log(f"plasticity update {step}: {S} searches, {m} formed, {net.m} synapses; "
                 f"connectivity {(t1 - t0) * 1e3:.1f} ms, plasticity step "
                 f"{(t2 - t1) * 1e3:.1f} ms")
-    tree.free()
     tot_s = sum(u["connectivity_ms"] + u["plasticity_ms"] for u in per) / 1e3
     searches = sum(u["searches"] for u in per)
+    end_a = (net.m, int(net.bound.sum().item()), float(net.z.sum().item()))
+    del net, res, tgt, off
+    # the same updates as cycles replayed from one captured graph
+    msp.release_workspace(0)
+    va, ve, vi = (T(v, torch.int32) for v in (w.vac_axon, w.vac_exc, w.vac_inh))
+    net = msp.Network(va, ve, vi, capacity=4 * w.n)
+    cyc = msp.Cycle(tree, ty, net, va, ve, vi, w.sigma, w.theta, w.seed, step=0, graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bad = 0
+    for step in range(updates):
+        cyc.run(1)
+        bad |= cyc.status()              # the one host read of an update
+    torch.cuda.synchronize()
+    cyc_s = time.perf_counter() - t0
+    c = cyc.counts()
+    end_b = (c["m"], int(net.bound.sum().item()), float(net.z.sum().item()))
+    log(f"plasticity: {updates} updates made of separate calls {tot_s:.3f} s, as replayed "
+        f"update cycles {cyc_s:.3f} s; same network: {end_a == end_b}")
+    cyc.free()
+    tree.free()
     return dict(workload=f"plasticity_{w.n}_uniform_20000um", n_updates=len(per),
                 total_s=tot_s, searches=searches, searches_per_s=searches / tot_s,
-                synapses_formed=sum(u["formed"] for u in per), synapses_at_end=net.m,
+                cycle_graph_total_s=cyc_s, cycle_graph_searches_per_s=searches / cyc_s,
+                cycle_status=bad, same_network=end_a == end_b,
+                synapses_formed=sum(u["formed"] for u in per), synapses_at_end=end_a[0],
                 first_updates=per[:3], last_update=per[-1],
                 note="per update: refresh + search + commit, then record + growth/deletion/"
                      "retraction (the plasticity step), all on the device; octree built "
-                     "once (positions fixed)")
+                     "once (positions fixed). total_s: the separate calls; "
+                     "cycle_graph_total_s: the same updates replayed from a captured graph, "
+                     "one status read per update")
 
 
 def study_complexity(msp, torch, log2_ns=(12, 14, 16, 18, 20, 22, 23),

@@ -302,10 +302,12 @@ msp_status msp_attraction_bwd(msp_octree t, const uint8_t* neuron_type, const in
  *   synapses, ordered by (source, element). n_formed: device int64 scalar.
  *   accepted_out [S] uint8 (nullable in msp_commit_synapses_ex): 1 if the request in
  *   that slot was accepted.
- * Errors: MSP_ERR_CAPACITY if more than syn_capacity synapses would form (then no
- * count is modified and nothing is written); MSP_ERR_INVALID if S = elem_offset[n]
- * is negative or not below 2^31 - 1 (requests are indexed with int32). After a commit
- * the octree is stale until the next msp_update_vacant_counts.
+ * Errors: MSP_ERR_CAPACITY if more than syn_capacity synapses would form, and
+ * MSP_ERR_INVALID if a target is >= n (then no vacancy count is modified, no synapse is
+ * written and *n_formed = 0); MSP_ERR_INVALID if S = elem_offset[n] is negative or
+ * not below 2^31 - 1 (requests are indexed with int32). Waits on `s` (to size its
+ * working memory by S and to report the status). After a commit the octree is stale
+ * until the next msp_update_vacant_counts.
  */
 msp_status msp_commit_synapses(const int32_t* target, const int64_t* elem_offset,
                                const uint8_t* neuron_type, int64_t n, int32_t* vac_axon,
@@ -430,6 +432,73 @@ msp_status msp_plasticity_step(int64_t n, const msp_plasticity_params* params, u
                                int32_t* syn_tgt, uint8_t* syn_type, int64_t m, int64_t* m_out,
                                int32_t* vac_axon, int32_t* vac_exc, int32_t* vac_inh,
                                hipStream_t s);
+
+/* ------------------------------------------------------------------------------------
+ * The update cycle (Sec. III-A: every connectivity update refreshes the octree's
+ * vacancy counts, searches a target for every vacant axonal element, accepts or
+ * declines the requests, records the new synapses, and the elements then grow,
+ * retract and are deleted until the next update). msp_cycle_run enqueues whole
+ * updates with every count kept on the device: nothing is read back and nothing is
+ * allocated, so the host never waits inside an update and, with MSP_CYCLE_GRAPH, one
+ * update is captured as a HIP graph and replayed. An update does exactly what
+ *   msp_update_vacant_counts(t, vac_exc, vac_inh),
+ *   msp_find_targets(t, neuron_type, vac_axon, sigma, theta, seed, step, ...),
+ *   msp_commit_synapses(..., seed, step, ...), msp_plasticity_record(...),
+ *   msp_plasticity_step(n, params, seed, step, ...)
+ * do in turn with step = *state.step, then increments *state.step: the network state
+ * it leaves is bitwise the same.
+ * ------------------------------------------------------------------------------------ */
+typedef struct msp_cycle_s* msp_cycle;
+
+/* The network state an update cycle reads and advances: device memory owned by the
+ * caller, which must stay valid until msp_cycle_free. */
+typedef struct msp_cycle_state {
+  double* z;             /* [3][n] element counts (kinds as in msp_plasticity_step) */
+  int32_t* bound;        /* [3][n] bound elements */
+  int32_t* syn_src;      /* [syn_capacity] the synapse list */
+  int32_t* syn_tgt;
+  uint8_t* syn_type;
+  int64_t* m;            /* [1] synapses in the list */
+  int32_t* vac_axon;     /* [n] vacant elements: the update's input, rewritten by its */
+  int32_t* vac_exc;      /*     plasticity step for the next update */
+  int32_t* vac_inh;
+  uint64_t* step;        /* [1] step of the next update; incremented by every update */
+  int32_t* status;       /* [1] MSP_CYCLE_* bits, OR-ed in by every update (the caller
+                            clears it) */
+  int64_t* searches;     /* [1] nullable: searches of the last update */
+  int64_t* formed;       /* [1] nullable: synapses formed by the last update */
+} msp_cycle_state;
+
+#define MSP_CYCLE_GRAPH 1       /* capture one update on the first run, replay it after */
+
+/* status bits of an update (device) */
+#define MSP_CYCLE_SEARCH_INVALID  1   /* a negative vac_axon or a neuron type > 1: the
+                                         update searched nothing and formed nothing */
+#define MSP_CYCLE_SEARCH_CAPACITY 2   /* more searches than search_capacity: likewise */
+#define MSP_CYCLE_SYN_CAPACITY    4   /* the list could not hold the new synapses: none
+                                         was recorded (their elements stay unbound) */
+#define MSP_CYCLE_DEVICE          8   /* the octree's device error flag is set (e.g. a
+                                         negative vacant dendritic count) */
+
+/* Plan update cycles of the network on octree t (built; its positions are the
+ * neurons'), neuron_type [n], on the current device (t's). search_capacity: most
+ * searches one update may run (the sum of vac_axon); syn_capacity: the list's length.
+ * The plan holds its own working memory (search, acceptance and plasticity scratch,
+ * sized by n, search_capacity and syn_capacity). Errors: MSP_ERR_INVALID (bad handle,
+ * null state pointer, sigma or theta, parameters as msp_plasticity_step checks them,
+ * search_capacity < 1 or not below 2^31 - 1, syn_capacity < 1 or not below 2^31),
+ * MSP_ERR_OOM. */
+msp_status msp_cycle_create(msp_octree t, const uint8_t* neuron_type, double sigma_um,
+                            double theta, uint64_t seed, const msp_plasticity_params* params,
+                            int64_t search_capacity, int64_t syn_capacity,
+                            const msp_cycle_state* state, int32_t flags, msp_cycle* out);
+
+/* Enqueue `updates` >= 0 consecutive updates on stream s. Does not wait: read
+ * *state.status (and the state) after the stream has reached them. */
+msp_status msp_cycle_run(msp_cycle c, int32_t updates, hipStream_t s);
+
+/* Release the plan (waits for the device). */
+void msp_cycle_free(msp_cycle c);
 
 /*
  * Electrical activity between connectivity updates (Sec. II, "Update of electrical

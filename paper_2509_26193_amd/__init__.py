@@ -3,14 +3,16 @@
 The computation lives in libmsp.so (hand-written HIP kernels behind the C ABI of
 include/msp.h); this package is its thin Python binding. Entry points follow the
 four steps of one update: build_octree, update_vacant_counts, find_targets,
-commit_synapses.
+commit_synapses; Network holds the plasticity between updates and Cycle runs whole
+updates without host waits.
 """
-from ._lib import (ACTIVITY, PLASTICITY, Activity, AttractionFn, Batch, MspError, Network, Octree, attraction,
+from ._lib import (ACTIVITY, PLASTICITY, Activity, AttractionFn, Batch, Cycle, MspError, Network, Octree,
+                   attraction,
                    attraction_bwd, attraction_fwd, build_octree, commit_synapses, find_targets,
                    header_functions, lib, release_workspace, search_offsets, status_string, sync,
                    update_vacant_counts)
 
 __all__ = ["AttractionFn", "attraction", "attraction_fwd", "attraction_bwd", "Batch", "MspError",
            "Octree", "build_octree", "update_vacant_counts", "find_targets",
-           "commit_synapses", "Network", "PLASTICITY", "Activity", "ACTIVITY", "sync", "status_string",
+           "commit_synapses", "Network", "Cycle", "PLASTICITY", "Activity", "ACTIVITY", "sync", "status_string",
            "header_functions", "lib", "search_offsets", "release_workspace"]

@@ -59,6 +59,13 @@ class PlasticityParams(ctypes.Structure):
                 ("steps_per_update", _i32)]
 
 
+class CycleState(ctypes.Structure):
+    _fields_ = [("z", _vp), ("bound", _vp), ("syn_src", _vp), ("syn_tgt", _vp),
+                ("syn_type", _vp), ("m", _vp), ("vac_axon", _vp), ("vac_exc", _vp),
+                ("vac_inh", _vp), ("step", _vp), ("status", _vp), ("searches", _vp),
+                ("formed", _vp)]
+
+
 class ActivityParams(ctypes.Structure):
     _fields_ = [("a_exc", _dbl), ("b_exc", _dbl), ("c_exc", _dbl), ("d_exc", _dbl),
                 ("a_inh", _dbl), ("b_inh", _dbl), ("c_inh", _dbl), ("d_inh", _dbl),
@@ -98,6 +105,11 @@ _SIGS = {
                                      _vp]),
     "msp_plasticity_step": (_i32, [_i64, ctypes.POINTER(PlasticityParams), _u64, _u64, _vp, _vp,
                                    _vp, _vp, _vp, _i64, ctypes.POINTER(_i64), _vp, _vp, _vp, _vp]),
+    "msp_cycle_create": (_i32, [_vp, _vp, _dbl, _dbl, _u64, ctypes.POINTER(PlasticityParams),
+                                _i64, _i64, ctypes.POINTER(CycleState), _i32,
+                                ctypes.POINTER(_vp)]),
+    "msp_cycle_run": (_i32, [_vp, _i32, _vp]),
+    "msp_cycle_free": (None, [_vp]),
     "msp_activity_init": (_i32, [_i64, _vp, ctypes.POINTER(ActivityParams), _vp, _vp, _vp, _vp,
                                  _vp, _vp, _vp]),
     "msp_activity_run": (_i32, [_i64, _vp, _vp, _i64, _vp, _vp, _vp, _i32,
@@ -107,6 +119,11 @@ _SIGS = {
 
 MSP_BATCH_GRAPH = 1
 MSP_BATCH_AUTOTUNE = 2
+MSP_CYCLE_GRAPH = 1
+MSP_CYCLE_SEARCH_INVALID = 1
+MSP_CYCLE_SEARCH_CAPACITY = 2
+MSP_CYCLE_SYN_CAPACITY = 4
+MSP_CYCLE_DEVICE = 8
 
 _lib = None
 
@@ -555,6 +572,77 @@ class Network:
 
     def synapses(self):
         return self.src[:self.m], self.tgt[:self.m], self.type[:self.m]
+
+
+class Cycle:
+    """Update cycles of a Network on a fixed octree (msp_cycle_*): each update refreshes
+    the octree's vacancies, searches, commits, records and runs the plasticity step,
+    exactly as the separate calls do, with every count on the device and no host wait;
+    graph=True replays one captured update. The cycle takes over the network's
+    synapse count and the vacancy tensors (updated in place); `step` is the first
+    update's step."""
+
+    def __init__(self, tree: Octree, neuron_type: torch.Tensor, net: "Network",
+                 vac_axon: torch.Tensor, vac_exc: torch.Tensor, vac_inh: torch.Tensor,
+                 sigma_um: float, theta: float, seed: int, step: int = 0,
+                 params: dict | None = None, search_capacity: int | None = None,
+                 graph: bool = True):
+        n = net.n
+        dev = net.z.device
+        self.net = net
+        for t, name in ((vac_axon, "vac_axon"), (vac_exc, "vac_exc"), (vac_inh, "vac_inh")):
+            _dev(t, torch.int32, name, n)
+        self.va, self.ve, self.vi = vac_axon, vac_exc, vac_inh
+        # device scalars: m, step, searches, formed (int64) and the status word
+        self.i64 = torch.tensor([net.m, int(step), 0, 0], dtype=torch.int64, device=dev)
+        self.status_word = torch.zeros(1, dtype=torch.int32, device=dev)
+        p = PlasticityParams(**dict(PLASTICITY, **(params or {})))
+        ptr = self.i64.data_ptr()
+        self._state = CycleState(net.z.data_ptr(), net.bound.data_ptr(), net.src.data_ptr(),
+                                 net.tgt.data_ptr(), net.type.data_ptr(), ptr,
+                                 self.va.data_ptr(), self.ve.data_ptr(), self.vi.data_ptr(),
+                                 ptr + 8, self.status_word.data_ptr(), ptr + 16, ptr + 24)
+        cap = int(search_capacity) if search_capacity else max(1, 3 * n)
+        _dev(neuron_type, torch.uint8, "neuron_type", n)
+        self._type = neuron_type
+        self._tree = tree
+        h = _vp()
+        _check(lib().msp_cycle_create(tree.handle, neuron_type.data_ptr(), float(sigma_um),
+                                      float(theta), int(seed), ctypes.byref(p), cap,
+                                      net.src.numel(), ctypes.byref(self._state),
+                                      MSP_CYCLE_GRAPH if graph else 0, ctypes.byref(h)),
+               "cycle_create")
+        self.handle = h.value
+
+    def run(self, updates: int = 1, stream=None) -> None:
+        """Enqueue `updates` updates (no host wait)."""
+        _check(lib().msp_cycle_run(self.handle, int(updates), _stream(stream)), "cycle_run")
+
+    def va_ve_vi(self):
+        """The vacancy tensors the cycle reads and rewrites (axon, exc, inh)."""
+        return self.va, self.ve, self.vi
+
+    def status(self) -> int:
+        """The OR of the status bits of the updates run so far (waits for them)."""
+        return int(self.status_word.item())
+
+    def counts(self) -> dict:
+        """m, the next step, and the last update's searches and synapses formed (waits);
+        also sets the network's host-side synapse count."""
+        m, step, searches, formed = (int(v) for v in self.i64.cpu())
+        self.net.m = m
+        return dict(m=m, step=step, searches=searches, formed=formed)
+
+    def free(self) -> None:
+        if self.handle:
+            lib().msp_cycle_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 ACTIVITY = dict(a_exc=0.02, b_exc=0.2, c_exc=-65.0, d_exc=8.0, a_inh=0.1, b_inh=0.2,

@@ -218,11 +218,6 @@ __global__ void phase2_count_k(SweepOut W, int64_t nreq, int64_t* out) {
   *out = lo;
 }
 
-__global__ void fill_i32_k(int32_t* p, int64_t n, int32_t v) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) p[k] = v;
-}
-
 // Validity of vac_axon and types; per-simulation status starts at 0 (fill before).
 __global__ void b_check_k(BatchDev B, int64_t total) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -432,8 +427,6 @@ struct SearchScratch {
   void* hsort;                  // radix sort workspace
   bool own_cell;                // the sweep tests for the source's own cell (see sweep_tile)
 };
-
-inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 inline int64_t max_tiles_for(int64_t total_n, int nsims) { return total_n / kWave + 2 * nsims + 1; }
 

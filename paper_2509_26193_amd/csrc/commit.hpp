@@ -10,67 +10,70 @@
 namespace msp {
 
 constexpr int kCommitBlock = 256;
+constexpr int32_t kCommitCapacity = 1;      // more accepted requests than list capacity
 
+// Source of every request slot below S.
 __global__ void __launch_bounds__(kCommitBlock) src_of_k(const int64_t* __restrict__ off, int64_t n,
-                                                        int32_t* __restrict__ src_of) {
+                                                        DevCount S, int32_t* __restrict__ src_of) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  for (int64_t s = off[i]; s < off[i + 1]; ++s) src_of[s] = (int32_t)i;
+  const int64_t S_ = S.get();
+  const int64_t e = off[i + 1] < S_ ? off[i + 1] : S_;
+  for (int64_t s = off[i]; s < e; ++s) src_of[s] = (int32_t)i;
 }
+
+// The launches over the S requests below are sized by grid_cap and stride over them.
 
 // Group key 2g + type, priority, and the per-group request count.
 __global__ void __launch_bounds__(kCommitBlock) req_key_k(
     const int32_t* __restrict__ target, const int64_t* __restrict__ off,
-    const int32_t* __restrict__ src_of, const uint8_t* __restrict__ type, int64_t S, int64_t n,
-    uint64_t seed, uint64_t step, int64_t* __restrict__ key, uint64_t* __restrict__ prio,
+    const int32_t* __restrict__ src_of, const uint8_t* __restrict__ type, DevCount S, int64_t n,
+    uint64_t seed, DevStep step, int64_t* __restrict__ key, uint64_t* __restrict__ prio,
     int32_t* __restrict__ cnt, int32_t* err) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  const int32_t g = target[s];
-  const int32_t i = src_of[s];
-  if (g < 0 || g >= n) {
-    if (g >= n) atomicOr(err, kErrArgs);
-    key[s] = -1;
-    return;
+  const int64_t S_ = S.get();
+  const uint64_t st = step.get();
+  for (int64_t s = gtid(); s < S_; s += gstride()) {
+    const int32_t g = target[s];
+    const int32_t i = src_of[s];
+    if (g < 0 || g >= n) {
+      if (g >= n) atomicOr(err, kErrArgs);
+      key[s] = -1;
+      continue;
+    }
+    const int64_t k = 2 * (int64_t)g + (type[i] ? 1 : 0);
+    key[s] = k;
+    prio[s] = philox_word0(seed, 1, (uint64_t)i, (uint64_t)(s - off[i]), st, 0);
+    atomicAdd(&cnt[k], 1);
   }
-  const int64_t k = 2 * (int64_t)g + (type[i] ? 1 : 0);
-  key[s] = k;
-  prio[s] = philox_word0(seed, 1, (uint64_t)i, (uint64_t)(s - off[i]), step, 0);
-  atomicAdd(&cnt[k], 1);
 }
 
 __global__ void __launch_bounds__(kCommitBlock) req_scatter_k(const int64_t* __restrict__ key,
-                                                             int64_t S, int32_t* __restrict__ cursor,
+                                                             DevCount S, int32_t* __restrict__ cursor,
                                                              int32_t* __restrict__ seg) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  const int64_t k = key[s];
-  if (k < 0) return;
-  const int32_t p = atomicAdd(&cursor[k], 1);
-  seg[p] = (int32_t)s;
+  const int64_t S_ = S.get();
+  for (int64_t s = gtid(); s < S_; s += gstride()) {
+    const int64_t k = key[s];
+    if (k < 0) continue;
+    const int32_t p = atomicAdd(&cursor[k], 1);
+    seg[p] = (int32_t)s;
+  }
 }
 
 // Accept iff fewer than v requests of the group precede this one in (prio, i, j) order.
 // Slots s are in (i, j) order, so (i, j) ties compare as slot indices.
-__global__ void __launch_bounds__(kCommitBlock) req_rank_k(
-    const int64_t* __restrict__ key, const uint64_t* __restrict__ prio,
-    const int32_t* __restrict__ seg_off, const int32_t* __restrict__ seg, int64_t S,
-    const int32_t* __restrict__ vexc, const int32_t* __restrict__ vinh, uint8_t* __restrict__ acc) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S) return;
+__device__ __forceinline__ uint8_t rank_accept(const int64_t* __restrict__ key,
+                                               const uint64_t* __restrict__ prio,
+                                               const int32_t* __restrict__ seg_off,
+                                               const int32_t* __restrict__ seg,
+                                               const int32_t* __restrict__ vexc,
+                                               const int32_t* __restrict__ vinh, int64_t s) {
   const int64_t k = key[s];
-  if (k < 0) {
-    acc[s] = 0;
-    return;
-  }
+  if (k < 0) return 0;
   const int32_t g = (int32_t)(k >> 1);
   int32_t v = (k & 1) ? vinh[g] : vexc[g];
   v = v < 0 ? 0 : v;
   const int32_t lo = seg_off[k], hi = seg_off[k + 1];
-  if (hi - lo <= v) {
-    acc[s] = 1;
-    return;
-  }
+  if (hi - lo <= v) return 1;
   const uint64_t ps = prio[s];
   int32_t rank = 0;
   for (int32_t q = lo; q < hi && rank < v; ++q) {
@@ -78,28 +81,61 @@ __global__ void __launch_bounds__(kCommitBlock) req_rank_k(
     const uint64_t po = prio[o];
     rank += (po < ps || (po == ps && o < s)) ? 1 : 0;
   }
-  acc[s] = rank < v ? 1 : 0;
+  return rank < v ? 1 : 0;
 }
 
+__global__ void __launch_bounds__(kCommitBlock) req_rank_k(
+    const int64_t* __restrict__ key, const uint64_t* __restrict__ prio,
+    const int32_t* __restrict__ seg_off, const int32_t* __restrict__ seg, DevCount S,
+    const int32_t* __restrict__ vexc, const int32_t* __restrict__ vinh, uint8_t* __restrict__ acc) {
+  const int64_t S_ = S.get();
+  for (int64_t s = gtid(); s < S_; s += gstride())
+    acc[s] = rank_accept(key, prio, seg_off, seg, vexc, vinh, s);
+}
+
+// Writes the accepted requests' synapses at their places in the output list, unless
+// the list (capacity `cap`) cannot hold them all or a target was out of range
+// (kErrArgs in *flags): then it writes nothing (and sets kCommitCapacity for the
+// former).
 __global__ void __launch_bounds__(kCommitBlock) commit_write_k(
     const uint8_t* __restrict__ acc, const int64_t* __restrict__ dst, const int64_t* __restrict__ key,
-    const int32_t* __restrict__ src_of, int64_t S, int32_t* vac_axon, int32_t* vexc, int32_t* vinh,
-    int32_t* syn_src, int32_t* syn_tgt, uint8_t* syn_type, uint8_t* acc_out) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  const uint8_t a = acc[s];
-  if (acc_out) acc_out[s] = a;
-  if (!a) return;
-  const int64_t k = key[s];
-  const int32_t g = (int32_t)(k >> 1);
-  const int ty = (int)(k & 1);
-  const int32_t i = src_of[s];
-  const int64_t p = dst[s];
-  syn_src[p] = i;
-  syn_tgt[p] = g;
-  syn_type[p] = (uint8_t)ty;
-  atomicSub(&vac_axon[i], 1);
-  atomicSub(ty ? &vinh[g] : &vexc[g], 1);
+    const int32_t* __restrict__ src_of, DevCount S, int64_t cap, int32_t* vac_axon, int32_t* vexc,
+    int32_t* vinh, int32_t* syn_src, int32_t* syn_tgt, uint8_t* syn_type, uint8_t* acc_out,
+    int32_t* flags) {
+  const int64_t S_ = S.get();
+  if (S_ == 0 || (*flags & kErrArgs)) return;
+  if (dst[S_] > cap) {
+    if (gtid() == 0) atomicOr(flags, kCommitCapacity);
+    return;
+  }
+  for (int64_t s = gtid(); s < S_; s += gstride()) {
+    const uint8_t a = acc[s];
+    if (acc_out) acc_out[s] = a;
+    if (!a) continue;
+    const int64_t k = key[s];
+    const int32_t g = (int32_t)(k >> 1);
+    const int ty = (int)(k & 1);
+    const int32_t i = src_of[s];
+    const int64_t p = dst[s];
+    syn_src[p] = i;
+    syn_tgt[p] = g;
+    syn_type[p] = (uint8_t)ty;
+    atomicSub(&vac_axon[i], 1);
+    atomicSub(ty ? &vinh[g] : &vexc[g], 1);
+  }
+}
+
+struct AccFlag {
+  __device__ int64_t operator()(uint8_t a, int64_t) const { return (int64_t)a; }
+};
+
+// Synapses formed: the accepted requests, or 0 where commit_write_k wrote nothing.
+__global__ void formed_k(const int64_t* __restrict__ dst, DevCount S, int64_t cap,
+                         const int32_t* __restrict__ flags, int64_t* __restrict__ n_formed) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int64_t S_ = S.get();
+  const int64_t f = S_ == 0 ? 0 : dst[S_];
+  *n_formed = ((*flags & kErrArgs) || f > cap) ? 0 : f;
 }
 
 __global__ void copy_scalar_k(const int64_t* __restrict__ src, int64_t* __restrict__ dst) {

@@ -86,12 +86,13 @@ struct msp_octree_s {
 
 namespace msp {
 
-// Registry of the live handles the library has handed out (octrees and batch plans).
+// Registry of the live handles the library has handed out (octrees, batch plans and
+// update cycles).
 // A handle is valid exactly while it is registered: every entry point looks the
 // pointer up here instead of reading through it, so a freed, foreign or doubly freed
 // handle is rejected without touching freed memory. (A handle whose address a later
 // build or plan has reused names that new object.)
-enum class HandleKind : int { kOctree = 1, kBatch = 2 };
+enum class HandleKind : int { kOctree = 1, kBatch = 2, kCycle = 3 };
 
 inline std::mutex& handle_mutex() {
   static std::mutex m;
@@ -202,6 +203,81 @@ inline unsigned grid_for(int64_t n, int block) {
   if (g < 1) g = 1;
   return (unsigned)g;
 }
+
+inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Carves 256-byte aligned arrays out of one allocation (base null: only sizes it).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(int64_t count) {
+    T* q = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += align_up(sizeof(T) * (size_t)(count > 0 ? count : 1));
+    return q;
+  }
+  void* take_bytes(size_t bytes) {
+    void* q = base ? base + off : nullptr;
+    off += align_up(bytes);
+    return q;
+  }
+};
+
+__global__ void fill_i32_k(int32_t* p, int64_t n, int32_t v) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+
+__global__ void fill_i64_k(int64_t* p, int64_t n, int64_t v) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+
+__global__ void copy_i32_k(const int32_t* __restrict__ from, int32_t* __restrict__ to, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) to[k] = from[k];
+}
+
+// An item count known on the host (p null: v) or only on the device (*p, clamped to
+// [0, v]: the launch is sized for the bound v and threads past the count return).
+// Device counts let a sequence of launches run without reading anything back, so that
+// it can be enqueued ahead and captured in a graph.
+struct DevCount {
+  int64_t v;
+  const int64_t* p;
+  __device__ __forceinline__ int64_t get() const {
+    if (!p) return v;
+    const int64_t c = *p;
+    return c < 0 ? 0 : (c < v ? c : v);
+  }
+};
+
+inline DevCount host_count(int64_t n) { return DevCount{n, nullptr}; }
+
+// Launches over a device count are sized for its bound but hold at most kStrideGrid
+// blocks (one full residency of the chip at 256 threads); their threads stride over
+// the items.
+constexpr unsigned kStrideGrid = 2048;
+
+inline unsigned grid_cap(int64_t n, int block) {
+  const unsigned g = grid_for(n, block);
+  return g < kStrideGrid ? g : kStrideGrid;
+}
+
+__device__ __forceinline__ int64_t gtid() {
+  return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+}
+
+__device__ __forceinline__ int64_t gstride() { return (int64_t)gridDim.x * blockDim.x; }
+
+// A step number given by value, or read on the device (p non-null).
+struct DevStep {
+  uint64_t v;
+  const uint64_t* p;
+  __device__ __forceinline__ uint64_t get() const { return p ? *p : v; }
+};
+
+inline DevStep host_step(uint64_t step) { return DevStep{step, nullptr}; }
 
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two

@@ -16,23 +16,12 @@
 #include "attraction.hpp"
 #include "commit.hpp"
 #include "plasticity.hpp"
+#include "update.hpp"
 #include "activity.hpp"
 
 using namespace msp;
 
 namespace {
-
-// Carves 256-byte aligned arrays out of one allocation (base null: only sizes it).
-struct Carver {
-  char* base;
-  size_t off = 0;
-  template <class T>
-  T* take(int64_t count) {
-    T* q = base ? reinterpret_cast<T*>(base + off) : nullptr;
-    off += (sizeof(T) * (size_t)(count > 0 ? count : 1) + 255) & ~(size_t)255;
-    return q;
-  }
-};
 
 void carve_neurons(msp_octree_s* t, char* base, size_t* bytes) {
   Carver c{base};
@@ -71,10 +60,6 @@ void release(msp_octree_s* t, hipStream_t fs = nullptr, bool on_caller_stream = 
   if (t->slab_N) (void)hipFreeAsync(t->slab_N, fs);
   delete t;
 }
-
-struct AccFlag {
-  __device__ int64_t operator()(uint8_t a, int64_t) const { return (int64_t)a; }
-};
 
 struct NonNeg {                 // a count, negative ones taken as 0 (they are reported)
   __device__ int64_t operator()(int32_t a, int64_t) const { return a > 0 ? (int64_t)a : 0; }
@@ -253,6 +238,24 @@ hipError_t noalloc_scratch(int device, void** out) {
   }
   *out = addr[device];
   return hipSuccess;
+}
+
+// The octree's per-type vacancy counts and centroids from the vacant dendritic
+// elements: leaves first, then the inner nodes level by level, deepest first.
+hipError_t enqueue_refresh(msp_octree_s* t, const int32_t* vac_exc, const int32_t* vac_inh,
+                           hipStream_t s) {
+  refresh_leaves_k<<<grid_for(t->n, kRefreshBlock), kRefreshBlock, 0, s>>>(
+      t->n, t->rec[0], t->rec[1], t->leaf_at, t->nbeg, t->nend, t->order, t->pos, vac_exc,
+      vac_inh, t->vs[0], t->vs[1], t->err);
+  hipError_t e = hipGetLastError();
+  for (int k = kMaxDepth; k >= 0 && e == hipSuccess; --k) {
+    const int64_t cnt = t->level_off[k + 1] - t->level_off[k];
+    if (cnt == 0) continue;
+    refresh_level_k<<<grid_for(cnt, kRefreshBlock), kRefreshBlock, 0, s>>>(
+        t->level_nodes + t->level_off[k], cnt, t->rec[0], t->rec[1], t->err);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 // The search's descriptor and neuron bases written by a kernel (arguments by value):
@@ -466,17 +469,7 @@ msp_status msp_last_device_error(msp_octree t) {
 msp_status msp_update_vacant_counts(msp_octree t, const int32_t* vac_dend_exc,
                                     const int32_t* vac_dend_inh, hipStream_t s) {
   if (!handle_ok(t) || !vac_dend_exc || !vac_dend_inh) return MSP_ERR_INVALID;
-  refresh_leaves_k<<<grid_for(t->n, kRefreshBlock), kRefreshBlock, 0, s>>>(
-      t->n, t->rec[0], t->rec[1], t->leaf_at, t->nbeg, t->nend, t->order, t->pos, vac_dend_exc,
-      vac_dend_inh, t->vs[0], t->vs[1], t->err);
-  MSP_HIP_TRY(hipGetLastError());
-  for (int k = kMaxDepth; k >= 0; --k) {
-    const int64_t cnt = t->level_off[k + 1] - t->level_off[k];
-    if (cnt == 0) continue;
-    refresh_level_k<<<grid_for(cnt, kRefreshBlock), kRefreshBlock, 0, s>>>(
-        t->level_nodes + t->level_off[k], cnt, t->rec[0], t->rec[1], t->err);
-    MSP_HIP_TRY(hipGetLastError());
-  }
+  MSP_HIP_TRY(enqueue_refresh(t, vac_dend_exc, vac_dend_inh, s));
   t->refreshed = true;
   return MSP_OK;
 }
@@ -704,66 +697,26 @@ msp_status msp_commit_synapses_ex(const int32_t* target, const int64_t* elem_off
   // group offsets, cursors and request indices are int32
   if (S < 0 || S >= (int64_t)INT32_MAX) return MSP_ERR_INVALID;
   if (S == 0) {
-    MSP_HIP_TRY(hipMemsetAsync(n_formed, 0, sizeof(int64_t), s));
+    fill_i64_k<<<1, 64, 0, s>>>(n_formed, 1, 0);
+    MSP_HIP_TRY(hipGetLastError());
     return MSP_OK;
   }
   if (!target) return MSP_ERR_INVALID;
+  if (syn_capacity > 0 && (!syn_src || !syn_tgt || !syn_type)) return MSP_ERR_INVALID;
   // every temporary of the commit in one pool block (one allocation, one free)
-  const size_t z_src = align_up(sizeof(int32_t) * S), z_key = align_up(sizeof(int64_t) * S),
-               z_prio = align_up(sizeof(uint64_t) * S), z_cnt = align_up(sizeof(int32_t) * 2 * n),
-               z_off = align_up(sizeof(int32_t) * (2 * n + 1)), z_seg = align_up(sizeof(int32_t) * S),
-               z_acc = align_up(sizeof(uint8_t) * S), z_dst = align_up(sizeof(int64_t) * (S + 1)),
-               z_err = align_up(sizeof(int32_t)),
-               z_scan = align_up(std::max(scan_tmp_bytes<int32_t>(2 * n), scan_tmp_bytes<int64_t>(S)));
+  size_t bytes = 0;
+  (void)commit_ws(nullptr, n, S, &bytes);
   Temp tmp(s);
-  MSP_HIP_TRY(tmp.alloc(z_src + z_key + z_prio + z_cnt + z_off + z_seg + z_acc + z_dst + z_err +
-                        z_scan));
-  char* q = tmp.as<char>();
-  auto take = [&](size_t bytes) {
-    char* r = q;
-    q += bytes;
-    return r;
-  };
-  int32_t* src_of = reinterpret_cast<int32_t*>(take(z_src));
-  int64_t* key = reinterpret_cast<int64_t*>(take(z_key));
-  uint64_t* prio = reinterpret_cast<uint64_t*>(take(z_prio));
-  int32_t* cnt = reinterpret_cast<int32_t*>(take(z_cnt));
-  int32_t* seg_off = reinterpret_cast<int32_t*>(take(z_off));
-  int32_t* seg = reinterpret_cast<int32_t*>(take(z_seg));
-  uint8_t* acc = reinterpret_cast<uint8_t*>(take(z_acc));
-  int64_t* dst = reinterpret_cast<int64_t*>(take(z_dst));
-  int32_t* err = reinterpret_cast<int32_t*>(take(z_err));
-  void* scan_ws = take(z_scan);
-  MSP_HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int32_t) * 2 * n, s));
-  MSP_HIP_TRY(hipMemsetAsync(err, 0, sizeof(int32_t), s));
-  src_of_k<<<grid_for(n, kCommitBlock), kCommitBlock, 0, s>>>(elem_offset, n, src_of);
-  req_key_k<<<grid_for(S, kCommitBlock), kCommitBlock, 0, s>>>(
-      target, elem_offset, src_of, neuron_type, S, n, seed, step, key, prio, cnt, err);
-  MSP_HIP_TRY(hipGetLastError());
-  MSP_HIP_TRY((exclusive_scan<int32_t, int32_t, Ident<int32_t>>(cnt, seg_off, 2 * n,
-                                                                Ident<int32_t>(), true, s,
-                                                                scan_ws)));
-  // cursor = copy of the group offsets
-  MSP_HIP_TRY(hipMemcpyAsync(cnt, seg_off, sizeof(int32_t) * 2 * n, hipMemcpyDeviceToDevice, s));
-  req_scatter_k<<<grid_for(S, kCommitBlock), kCommitBlock, 0, s>>>(key, S, cnt, seg);
-  req_rank_k<<<grid_for(S, kCommitBlock), kCommitBlock, 0, s>>>(key, prio, seg_off, seg, S,
-                                                                 vac_exc, vac_inh, acc);
-  MSP_HIP_TRY(hipGetLastError());
-  MSP_HIP_TRY((exclusive_scan<int64_t, uint8_t, AccFlag>(acc, dst, S, AccFlag(), true, s,
-                                                         scan_ws)));
-  int64_t formed = 0;
-  int32_t bad = 0;
-  MSP_HIP_TRY(hipMemcpyAsync(&formed, dst + S, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  MSP_HIP_TRY(hipMemcpyAsync(&bad, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MSP_HIP_TRY(tmp.alloc(bytes));
+  const CommitWs w = commit_ws(tmp.p, n, S, &bytes);
+  MSP_HIP_TRY(enqueue_commit(w, target, elem_offset, neuron_type, n, host_count(S), vac_axon,
+                             vac_exc, vac_inh, seed, host_step(step), syn_src, syn_tgt, syn_type,
+                             syn_capacity, n_formed, accepted_out, s));
+  int32_t flags = 0;
+  MSP_HIP_TRY(hipMemcpyAsync(&flags, w.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   MSP_HIP_TRY(hipStreamSynchronize(s));
-  if (bad) return MSP_ERR_INVALID;
-  if (formed > syn_capacity) return MSP_ERR_CAPACITY;
-  if (formed > 0 && (!syn_src || !syn_tgt || !syn_type)) return MSP_ERR_INVALID;
-  commit_write_k<<<grid_for(S, kCommitBlock), kCommitBlock, 0, s>>>(
-      acc, dst, key, src_of, S, vac_axon, vac_exc, vac_inh, syn_src, syn_tgt, syn_type,
-      accepted_out);
-  copy_scalar_k<<<1, 64, 0, s>>>(dst + S, n_formed);
-  MSP_HIP_TRY(hipGetLastError());
+  if (flags & kErrArgs) return MSP_ERR_INVALID;
+  if (flags & kCommitCapacity) return MSP_ERR_CAPACITY;
   return MSP_OK;
 }
 
@@ -1183,6 +1136,29 @@ msp_status msp_attraction_bwd(msp_octree t, const uint8_t* neuron_type, const in
 }  // extern "C"
 
 namespace {
+// The growth rule's constants from the parameters (the same double expressions as the
+// definition, evaluated once).
+PlastConst plast_const(const msp_plasticity_params& p) {
+  PlastConst c;
+  c.scale = (double)p.steps_per_update * p.growth_rate;
+  c.xi = 0.5 * (p.growth_onset + p.target_calcium);
+  c.zeta = (p.target_calcium - p.growth_onset) / (2.0 * std::sqrt(std::log(2.0)));
+  c.ca_mean = p.calcium_mean;
+  c.ca_sd = p.calcium_sd;
+  c.delete_fraction = p.delete_fraction;
+  return c;
+}
+
+// Parameters a plasticity step accepts.
+bool plast_params_ok(const msp_plasticity_params& p) {
+  const double vals[] = {p.growth_rate, p.target_calcium, p.growth_onset, p.calcium_mean,
+                         p.calcium_sd, p.delete_fraction};
+  for (double v : vals)
+    if (!std::isfinite(v)) return false;
+  return p.growth_onset < p.target_calcium && p.delete_fraction >= 0.0 &&
+         p.delete_fraction <= 1.0 && p.steps_per_update >= 0;
+}
+
 ActParams act_params(const msp_activity_params& q) {
   ActParams P;
   P.a[0] = q.a_exc; P.b[0] = q.b_exc; P.c[0] = q.c_exc; P.d[0] = q.d_exc;
@@ -1219,8 +1195,9 @@ msp_status msp_plasticity_record(int64_t n, const int32_t* new_src, const int32_
   Temp err(s);
   MSP_HIP_TRY(err.alloc(sizeof(int32_t)));
   fill_i32_k<<<1, 64, 0, s>>>(err.as<int32_t>(), 1, 0);
-  bind_k<<<grid_for(m_new, kPlastBlock), kPlastBlock, 0, s>>>(new_src, new_tgt, new_type, m_new,
-                                                            n, bound, err.as<int32_t>());
+  bind_k<<<grid_cap(m_new, kPlastBlock), kPlastBlock, 0, s>>>(new_src, new_tgt, new_type,
+                                                            host_count(m_new), n, bound,
+                                                            err.as<int32_t>());
   MSP_HIP_TRY(hipGetLastError());
   int32_t bad = 0;
   MSP_HIP_TRY(hipMemcpyAsync(&bad, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -1238,112 +1215,258 @@ msp_status msp_plasticity_step(int64_t n, const msp_plasticity_params* params, u
     return MSP_ERR_INVALID;
   if (m > 0 && (!syn_src || !syn_tgt || !syn_type)) return MSP_ERR_INVALID;
   const msp_plasticity_params& p = *params;
-  const double vals[] = {p.growth_rate, p.target_calcium, p.growth_onset, p.calcium_mean,
-                         p.calcium_sd, p.delete_fraction};
-  for (double v : vals)
-    if (!std::isfinite(v)) return MSP_ERR_INVALID;
-  if (!(p.growth_onset < p.target_calcium) || p.delete_fraction < 0.0 || p.delete_fraction > 1.0 ||
-      p.steps_per_update < 0)
-    return MSP_ERR_INVALID;
-  // the same double expressions as the definition, evaluated once
-  const double scale = (double)p.steps_per_update * p.growth_rate;
-  const double xi = 0.5 * (p.growth_onset + p.target_calcium);
-  const double zeta = (p.target_calcium - p.growth_onset) / (2.0 * std::sqrt(std::log(2.0)));
-  growth_k<<<grid_for(3 * n, kPlastBlock), kPlastBlock, 0, s>>>(
-      z, n, seed, step, p.calcium_mean, p.calcium_sd, xi, zeta, scale);
-  MSP_HIP_TRY(hipGetLastError());
-  int64_t M = m;
-  if (m > 0) {
-    const SynList L{syn_src, syn_tgt, syn_type};
-    // every temporary of the step in one pool block (one allocation, one free)
-    const size_t z_dead = align_up(sizeof(uint8_t) * m), z_k = align_up(sizeof(uint64_t) * m),
-                 z_v = align_up(sizeof(int32_t) * m), z_pos = align_up(sizeof(int32_t) * (m + 1)),
-                 z_exc = align_up(sizeof(int32_t) * n), z_sort = align_up(radix_sort_ws_bytes(m)),
-                 z_scan = align_up(scan_tmp_bytes<int32_t>(m)),
-                 z_ty = align_up(sizeof(uint8_t) * m),
-                 z_sel = align_up(sizeof(DelSelect)) + align_up(sizeof(uint32_t) * 256);
-    Temp tmp(s);
-    MSP_HIP_TRY(tmp.alloc(z_dead + 2 * z_k + 4 * z_v + z_pos + z_exc + z_sort + z_scan + z_ty +
-                          z_sel));
-    char* q = tmp.as<char>();
-    auto take = [&](size_t bytes) {
-      char* r = q;
-      q += bytes;
-      return r;
-    };
-    uint8_t* dd = reinterpret_cast<uint8_t*>(take(z_dead));
-    uint64_t* k0 = reinterpret_cast<uint64_t*>(take(z_k));
-    uint64_t* k1 = reinterpret_cast<uint64_t*>(take(z_k));
-    int32_t* v0 = reinterpret_cast<int32_t*>(take(z_v));
-    int32_t* v1 = reinterpret_cast<int32_t*>(take(z_v));
-    int32_t* pos = reinterpret_cast<int32_t*>(take(z_pos));
-    int32_t* exc = reinterpret_cast<int32_t*>(take(z_exc));
-    void* sort_ws = take(z_sort);
-    void* scan_ws = take(z_scan);
-    const SynList O{reinterpret_cast<int32_t*>(take(z_v)), reinterpret_cast<int32_t*>(take(z_v)),
-                    reinterpret_cast<uint8_t*>(take(z_ty))};
-    char* sel = take(z_sel);
-    DelSelect* st = reinterpret_cast<DelSelect*>(sel);
-    uint32_t* hist = reinterpret_cast<uint32_t*>(sel + align_up(sizeof(DelSelect)));
-    MSP_HIP_TRY(hipMemsetAsync(dd, 0, sizeof(uint8_t) * m, s));
-    const int64_t n_del = (int64_t)std::floor(p.delete_fraction * (double)m + 0.5);
-    if (n_del > 0) {
-      // the n_del synapses of smallest (priority, index): a radix selection of the
-      // threshold key, most significant digit first, then one marking pass
-      del_keys_k<<<grid_for(m, kPlastBlock), kPlastBlock, 0, s>>>(k0, v0, m, seed, step);
-      del_select_init_k<<<1, 256, 0, s>>>(st, n_del < m ? n_del : m, hist);
-      const unsigned hg = std::min(grid_for(m, kPlastBlock), 2048u);
-      for (int shift = 56; shift >= 0; shift -= 8) {
-        del_select_hist_k<<<hg, kPlastBlock, 0, s>>>(k0, m, st, shift, hist);
-        del_select_pick_k<<<1, 256, 0, s>>>(st, hist, shift);
-      }
-      MSP_HIP_TRY((exclusive_scan<int32_t, uint64_t, DelTie>(k0, pos, m, DelTie{st}, false, s,
-                                                             scan_ws)));
-      del_select_mark_k<<<grid_for(m, kPlastBlock), kPlastBlock, 0, s>>>(k0, m, st, pos, L, n, dd,
-                                                                        bound);
-      MSP_HIP_TRY(hipGetLastError());
-    }
-    int owner_bits = 1;
-    while (owner_bits < 31 && ((int64_t)1 << owner_bits) < n) ++owner_bits;
-    const int key_bits = (32 + owner_bits + 7) / 8 * 8;
-    for (int k = 0; k < 3; ++k) {
-      excess_k<<<grid_for(n, kPlastBlock), kPlastBlock, 0, s>>>(bound + k * n, z + k * n, n, exc);
-      const RetractFlag F{L, dd, exc, k};
-      MSP_HIP_TRY((exclusive_scan<int32_t, int32_t, RetractFlag>(nullptr, pos, m, F, true, s,
-                                                                scan_ws)));
-      int32_t C = 0;
-      MSP_HIP_TRY(hipMemcpyAsync(&C, pos + m, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      MSP_HIP_TRY(hipStreamSynchronize(s));
-      if (C == 0) continue;
-      cand_write_k<<<grid_for(m, kPlastBlock), kPlastBlock, 0, s>>>(F, pos, m, seed, step, k0, v0);
-      MSP_HIP_TRY(radix_sort_pairs_ws(k0, v0, k1, v1, C, key_bits, s, sort_ws));
-      retract_k<<<grid_for(C, kPlastBlock), kPlastBlock, 0, s>>>(k0, v0, C, exc, L, n, dd, bound);
-      MSP_HIP_TRY(hipGetLastError());
-    }
-    MSP_HIP_TRY((exclusive_scan<int32_t, int32_t, LiveFlag>(nullptr, pos, m, LiveFlag{dd}, true, s,
-                                                           scan_ws)));
-    int32_t M32 = 0;
-    MSP_HIP_TRY(hipMemcpyAsync(&M32, pos + m, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    MSP_HIP_TRY(hipStreamSynchronize(s));
-    M = M32;
-    if (M < m) {
-      compact_k<<<grid_for(m, kPlastBlock), kPlastBlock, 0, s>>>(L, dd, pos, m, O);
-      MSP_HIP_TRY(hipGetLastError());
-      if (M > 0) {
-        MSP_HIP_TRY(hipMemcpyAsync(syn_src, O.src, sizeof(int32_t) * M, hipMemcpyDeviceToDevice, s));
-        MSP_HIP_TRY(hipMemcpyAsync(syn_tgt, O.tgt, sizeof(int32_t) * M, hipMemcpyDeviceToDevice, s));
-        MSP_HIP_TRY(hipMemcpyAsync(syn_type, O.type, sizeof(uint8_t) * M, hipMemcpyDeviceToDevice, s));
-      }
-    }
-  }
-  vacancy_k<<<grid_for(3 * n, kPlastBlock), kPlastBlock, 0, s>>>(z, bound, n, vac_axon, vac_exc,
-                                                                vac_inh);
-  MSP_HIP_TRY(hipGetLastError());
+  if (!plast_params_ok(p)) return MSP_ERR_INVALID;
+  const PlastConst c = plast_const(p);
+  int64_t* m_dev = nullptr;
+  Temp tmp(s);
+  size_t bytes = 0;
+  (void)plast_ws(nullptr, n, m, &bytes);
+  MSP_HIP_TRY(tmp.alloc(bytes + align_up(sizeof(int64_t))));
+  const PlastWs w = plast_ws(tmp.p, n, m, &bytes);
+  m_dev = reinterpret_cast<int64_t*>(static_cast<char*>(tmp.p) + bytes);
+  MSP_HIP_TRY(enqueue_plasticity(w, n, c, seed, host_step(step), z, bound,
+                                 SynList{syn_src, syn_tgt, syn_type}, host_count(m), m_dev,
+                                 vac_axon, vac_exc, vac_inh, s));
+  int64_t M = 0;
+  MSP_HIP_TRY(hipMemcpyAsync(&M, m_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   MSP_HIP_TRY(hipStreamSynchronize(s));
   *m_out = M;
   return MSP_OK;
 }
 
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------- update cycle
+struct msp_cycle_s {
+  int device;
+  int32_t flags;
+  msp_octree_s* t;
+  int64_t n;
+  const uint8_t* type;
+  uint64_t seed;
+  PlastConst pc;
+  int64_t cap_S, cap_syn;
+  msp_cycle_state st;
+  void* mem;                // one allocation: everything below
+  SimDesc* d_sim;
+  int64_t* d_nbase;
+  SearchScratch S;
+  unsigned sweep_blocks;
+  int64_t* elem_off;        // [n + 1]
+  int32_t* target;          // [cap_S]
+  CommitWs cw;
+  SynList fresh;            // [cap_S] the update's new synapses
+  int64_t* cnt;             // [2] searches, formed
+  int32_t* rec_flags;       // [1]
+  PlastWs pw;
+  hipGraphExec_t exec;
+  bool captured;
+  hipStream_t cap_stream;   // private stream for graph capture
+};
+
+namespace {
+
+// Start of an update: the step into the search descriptor, the record flags cleared.
+__global__ void cycle_begin_k(SimDesc* d, const uint64_t* step, int32_t* rec_flags) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  d->step = *step;
+  *rec_flags = 0;
+}
+
+// The searches the commit takes: none if the search reported an error (it then wrote
+// no targets).
+__global__ void cycle_searches_k(const int32_t* status, const int64_t* elem_off, int64_t n,
+                                 int64_t* searches) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  *searches = *status ? 0 : elem_off[n];
+}
+
+// End of an update: its status bits into the caller's word, the counts out, the step on.
+__global__ void cycle_end_k(const int32_t* search_status, const int32_t* commit_flags,
+                            const int32_t* rec_flags, const int32_t* tree_err,
+                            const int64_t* cnt, msp_cycle_state st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int32_t b = 0;
+  const int32_t ss = *search_status;
+  if (ss & kSimInvalid) b |= MSP_CYCLE_SEARCH_INVALID;
+  if (ss & kSimCapacity) b |= MSP_CYCLE_SEARCH_CAPACITY;
+  if (*rec_flags & kRecordCapacity) b |= MSP_CYCLE_SYN_CAPACITY;
+  if (*tree_err || (*commit_flags & kErrArgs)) b |= MSP_CYCLE_DEVICE;
+  if (b) *st.status |= b;
+  if (st.searches) *st.searches = cnt[0];
+  if (st.formed) *st.formed = cnt[1];
+  *st.step += 1;
+}
+
+void cycle_release(msp_cycle_s* c) {
+  if (!c) return;
+  if (c->captured) (void)hipGraphExecDestroy(c->exec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->mem) (void)hipFree(c->mem);
+  delete c;
+}
+
+// Carves the plan's memory (base null: sizes it).
+size_t cycle_carve(msp_cycle_s* c, char* base, int slots, int64_t regions) {
+  Carver cv{base};
+  const int64_t n = c->n;
+  void* search = cv.take_bytes(scratch_sizes(n, 1, slots, -1, regions).total);
+  c->d_sim = cv.take<SimDesc>(1);
+  c->d_nbase = cv.take<int64_t>(2);
+  c->elem_off = cv.take<int64_t>(n + 1);
+  c->target = cv.take<int32_t>(c->cap_S);
+  size_t bytes = 0;
+  (void)commit_ws(nullptr, n, c->cap_S, &bytes);
+  void* cw = cv.take_bytes(bytes);
+  c->fresh.src = cv.take<int32_t>(c->cap_S);
+  c->fresh.tgt = cv.take<int32_t>(c->cap_S);
+  c->fresh.type = cv.take<uint8_t>(c->cap_S);
+  c->cnt = cv.take<int64_t>(2);
+  c->rec_flags = cv.take<int32_t>(1);
+  (void)plast_ws(nullptr, n, c->cap_syn, &bytes);
+  void* pw = cv.take_bytes(bytes);
+  if (base) {
+    c->S = carve(search, n, 1, slots, c->d_sim, c->d_nbase, -1, regions);
+    c->cw = commit_ws(cw, n, c->cap_S, &bytes);
+    c->pw = plast_ws(pw, n, c->cap_syn, &bytes);
+  }
+  return cv.off;
+}
+
+// One update, kernels only (see msp_cycle_run).
+hipError_t cycle_enqueue(msp_cycle_s* c, hipStream_t s) {
+  const msp_cycle_state& st = c->st;
+  const DevStep step{0, st.step};
+  const int64_t n = c->n;
+  cycle_begin_k<<<1, 64, 0, s>>>(c->d_sim, st.step, c->rec_flags);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = enqueue_refresh(c->t, st.vac_exc, st.vac_inh, s);
+  if (e == hipSuccess) e = enqueue_prep(c->S, n, s);
+  if (e == hipSuccess) e = enqueue_search(c->S, false, c->sweep_blocks, 256, s);
+  if (e != hipSuccess) return e;
+  cycle_searches_k<<<1, 64, 0, s>>>(c->S.B.status, c->elem_off, n, c->cnt);
+  e = enqueue_commit(c->cw, c->target, c->elem_off, c->type, n, DevCount{c->cap_S, c->cnt},
+                     st.vac_axon, st.vac_exc, st.vac_inh, c->seed, step, c->fresh.src,
+                     c->fresh.tgt, c->fresh.type, c->cap_S, c->cnt + 1, nullptr, s);
+  if (e != hipSuccess) return e;
+  const SynList L{st.syn_src, st.syn_tgt, st.syn_type};
+  const DevCount formed{c->cap_S, c->cnt + 1};
+  record_k<<<grid_cap(c->cap_S, kPlastBlock), kPlastBlock, 0, s>>>(
+      c->fresh, formed, L, st.m, c->cap_syn, n, st.bound, c->rec_flags);
+  record_end_k<<<1, 64, 0, s>>>(formed, st.m, c->cap_syn);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  e = enqueue_plasticity(c->pw, n, c->pc, c->seed, step, st.z, st.bound, L,
+                         DevCount{c->cap_syn, st.m}, st.m, st.vac_axon, st.vac_exc, st.vac_inh, s);
+  if (e != hipSuccess) return e;
+  cycle_end_k<<<1, 64, 0, s>>>(c->S.B.status, c->cw.flags, c->rec_flags, c->t->err, c->cnt, st);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+msp_status msp_cycle_create(msp_octree t, const uint8_t* neuron_type, double sigma_um,
+                            double theta, uint64_t seed, const msp_plasticity_params* params,
+                            int64_t search_capacity, int64_t syn_capacity,
+                            const msp_cycle_state* state, int32_t flags, msp_cycle* out) {
+  if (!out) return MSP_ERR_INVALID;
+  *out = nullptr;
+  if (!handle_ok(t) || !neuron_type || !params || !state) return MSP_ERR_INVALID;
+  const msp_cycle_state& st = *state;
+  if (!st.z || !st.bound || !st.syn_src || !st.syn_tgt || !st.syn_type || !st.m ||
+      !st.vac_axon || !st.vac_exc || !st.vac_inh || !st.step || !st.status)
+    return MSP_ERR_INVALID;
+  if (!std::isfinite(sigma_um) || !(sigma_um > 0.0) || !std::isfinite(theta) || !(theta >= 0.0))
+    return MSP_ERR_INVALID;
+  if (!plast_params_ok(*params)) return MSP_ERR_INVALID;
+  if (search_capacity < 1 || search_capacity >= (int64_t)INT32_MAX || syn_capacity < 1 ||
+      syn_capacity >= ((int64_t)1 << 31))
+    return MSP_ERR_INVALID;
+  if ((flags & ~MSP_CYCLE_GRAPH) != 0) return MSP_ERR_INVALID;
+  int dev = -1;
+  MSP_HIP_TRY(hipGetDevice(&dev));
+  if (dev != t->device) return MSP_ERR_INVALID;
+  msp_cycle_s* c = new (std::nothrow) msp_cycle_s();
+  if (!c) return MSP_ERR_OOM;
+  c->device = dev;
+  c->flags = flags;
+  c->t = t;
+  c->n = t->n;
+  c->type = neuron_type;
+  c->seed = seed;
+  c->pc = plast_const(*params);
+  c->cap_S = search_capacity;
+  c->cap_syn = syn_capacity;
+  c->st = st;
+  c->mem = nullptr;
+  c->captured = false;
+  c->cap_stream = nullptr;
+  int slots = 0;
+  int64_t regions = 0;
+  hipError_t e = ck_slots_for(dev, c->n, 1, -1, &slots, &regions);
+  if (e == hipSuccess) e = hipMalloc(&c->mem, cycle_carve(c, nullptr, slots, regions));
+  if (e == hipSuccess) {
+    (void)cycle_carve(c, static_cast<char*>(c->mem), slots, regions);
+    e = sweep_blocks_for(dev, false, max_units_for(c->n, 1), 1.0, &c->sweep_blocks);
+  }
+  if (e == hipSuccess && (flags & MSP_CYCLE_GRAPH))
+    e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) {
+    const SimDesc h = make_desc(t, neuron_type, st.vac_axon, sigma_um, theta, seed, 0, c->target,
+                                c->elem_off, c->cap_S);
+    const int64_t hbase[2] = {0, c->n};
+    e = hipMemcpy(c->d_sim, &h, sizeof(SimDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(c->d_nbase, hbase, sizeof(hbase), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    cycle_release(c);
+    return e == hipErrorOutOfMemory ? MSP_ERR_OOM : MSP_ERR_HIP;
+  }
+  c->S.own_cell = own_cell_needed(t, theta);
+  handle_register(c, HandleKind::kCycle);
+  *out = c;
+  return MSP_OK;
+}
+
+msp_status msp_cycle_run(msp_cycle c, int32_t updates, hipStream_t s) {
+  if (!handle_live(c, HandleKind::kCycle) || updates < 0) return MSP_ERR_INVALID;
+  if (!handle_ok(c->t)) return MSP_ERR_INVALID;
+  if (updates == 0) return MSP_OK;
+  if (c->flags & MSP_CYCLE_GRAPH) {
+    if (!c->captured) {
+      hipGraph_t g;
+      MSP_HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t e = cycle_enqueue(c, c->cap_stream);
+      hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        (void)hipGetLastError();
+        return MSP_ERR_HIP;
+      }
+      e = hipGraphInstantiate(&c->exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return MSP_ERR_HIP;
+      c->captured = true;
+    }
+    for (int32_t k = 0; k < updates; ++k) MSP_HIP_TRY(hipGraphLaunch(c->exec, s));
+    return MSP_OK;
+  }
+  for (int32_t k = 0; k < updates; ++k) MSP_HIP_TRY(cycle_enqueue(c, s));
+  return MSP_OK;
+}
+
+void msp_cycle_free(msp_cycle c) {
+  if (!handle_take(c, HandleKind::kCycle)) return;
+  int dev = -1;
+  (void)hipGetDevice(&dev);
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  cycle_release(c);
+  if (dev >= 0) (void)hipSetDevice(dev);
+}
 
 msp_status msp_activity_init(int64_t n, const uint8_t* neuron_type,
                              const msp_activity_params* params, double* v, double* u,

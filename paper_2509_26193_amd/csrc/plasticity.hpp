@@ -32,13 +32,13 @@ struct SynList {
 };
 
 __global__ void __launch_bounds__(kPlastBlock) growth_k(double* __restrict__ z, int64_t n,
-                                                       uint64_t seed, uint64_t step,
+                                                       uint64_t seed, DevStep step,
                                                        double ca_mean, double ca_sd, double xi,
                                                        double zeta, double scale) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= 3 * n) return;
   const int64_t k = g / n, j = g - k * n;
-  uint64_t c0 = (uint64_t)j, c1 = (uint64_t)k, c2 = step, c3 = 0;
+  uint64_t c0 = (uint64_t)j, c1 = (uint64_t)k, c2 = step.get(), c3 = 0;
   philox4x64_10(c0, c1, c2, c3, seed, 2);
   const double u1 = (double)((c0 >> 11) + 1) * 0x1p-53;     // (0, 1]
   const double u2 = (double)(c1 >> 11) * 0x1p-53;           // [0, 1)
@@ -58,12 +58,14 @@ __device__ __forceinline__ void unbind(const SynList& L, int64_t s, int64_t n, i
 }
 
 __global__ void __launch_bounds__(kPlastBlock) del_keys_k(uint64_t* __restrict__ key,
-                                                         int32_t* __restrict__ val, int64_t m,
-                                                         uint64_t seed, uint64_t step) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= m) return;
-  key[s] = philox_word0(seed, 3, (uint64_t)s, step, 0, 0);
-  val[s] = (int32_t)s;
+                                                         int32_t* __restrict__ val, DevCount m,
+                                                         uint64_t seed, DevStep step) {
+  const int64_t m_ = m.get();
+  const uint64_t st = step.get();
+  for (int64_t s = gtid(); s < m_; s += gstride()) {
+    key[s] = philox_word0(seed, 3, (uint64_t)s, st, 0, 0);
+    val[s] = (int32_t)s;
+  }
 }
 
 // Deletion as a selection, not a sort: the `want` synapses of smallest (priority,
@@ -75,23 +77,33 @@ struct DelSelect {
   int64_t want;                 // synapses still to choose among the candidates
 };
 
-__global__ void del_select_init_k(DelSelect* st, int64_t want, uint32_t* hist) {
+// Synapses a deletion removes from a list of m: round(frac m), halves up, at most m
+// (the product and the sum rounded separately, as on the host).
+__host__ __device__ inline int64_t delete_count(double frac, int64_t m) {
+#pragma clang fp contract(off)
+  const double w = floor(frac * (double)m + 0.5);
+  const int64_t c = (int64_t)w;
+  return c < m ? c : m;
+}
+
+__global__ void del_select_init_k(DelSelect* st, double frac, DevCount m, uint32_t* hist) {
   if (threadIdx.x == 0) {
     st->prefix = 0;
     st->mask = 0;
-    st->want = want;
+    st->want = delete_count(frac, m.get());
   }
   hist[threadIdx.x] = 0;        // 256 threads
 }
 
 // Histogram of digit (key >> shift) & 255 over the keys that match the chosen digits.
 __global__ void __launch_bounds__(kPlastBlock) del_select_hist_k(const uint64_t* __restrict__ key,
-                                                                int64_t m, const DelSelect* st,
+                                                                DevCount mc, const DelSelect* st,
                                                                 int shift, uint32_t* hist) {
   __shared__ uint32_t h[256];
   for (int d = threadIdx.x; d < 256; d += blockDim.x) h[d] = 0;
   __syncthreads();
   const uint64_t prefix = st->prefix, mask = st->mask;
+  const int64_t m = st->want > 0 ? mc.get() : 0;
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < m;
        s += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t k = key[s];
@@ -137,15 +149,19 @@ struct DelTie {
 // Below the threshold key, or among its first `want` ties (tie_pos: exclusive scan of
 // the ties), a synapse goes.
 __global__ void __launch_bounds__(kPlastBlock) del_select_mark_k(
-    const uint64_t* __restrict__ key, int64_t m, const DelSelect* st,
+    const uint64_t* __restrict__ key, DevCount m, const DelSelect* st,
     const int32_t* __restrict__ tie_pos, SynList L, int64_t n, uint8_t* __restrict__ dead,
     int32_t* bound) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= m) return;
-  const uint64_t k = key[s], kt = st->prefix;
-  if (k < kt || (k == kt && tie_pos[s] < st->want)) {
-    dead[s] = 1;
-    unbind(L, s, n, bound);
+  const int64_t want = st->want;
+  if (want <= 0) return;
+  const int64_t m_ = m.get();
+  const uint64_t kt = st->prefix;
+  for (int64_t s = gtid(); s < m_; s += gstride()) {
+    const uint64_t k = key[s];
+    if (k < kt || (k == kt && tie_pos[s] < want)) {
+      dead[s] = 1;
+      unbind(L, s, n, bound);
+    }
   }
 }
 
@@ -176,36 +192,40 @@ struct RetractFlag {            // live synapse of a neuron with an excess of ki
 };
 
 __global__ void __launch_bounds__(kPlastBlock) cand_write_k(RetractFlag F, const int32_t* __restrict__ pos,
-                                                           int64_t m, uint64_t seed, uint64_t step,
+                                                           DevCount m, uint64_t seed, DevStep step,
                                                            uint64_t* __restrict__ key,
                                                            int32_t* __restrict__ val) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= m || !F(0, s)) return;
-  const int32_t o = owner_of(F.L, s, F.k);
-  const uint64_t q = philox_word0(seed, 4, (uint64_t)s, step, (uint64_t)F.k, 0) >> 32;
-  key[pos[s]] = ((uint64_t)(uint32_t)o << 32) | q;
-  val[pos[s]] = (int32_t)s;
+  const int64_t m_ = m.get();
+  const uint64_t st = step.get();
+  for (int64_t s = gtid(); s < m_; s += gstride()) {
+    if (!F(0, s)) continue;
+    const int32_t o = owner_of(F.L, s, F.k);
+    const uint64_t q = philox_word0(seed, 4, (uint64_t)s, st, (uint64_t)F.k, 0) >> 32;
+    key[pos[s]] = ((uint64_t)(uint32_t)o << 32) | q;
+    val[pos[s]] = (int32_t)s;
+  }
 }
 
 // Candidates sorted by (owner, priority, s): the first exc[owner] of each owner go.
 __global__ void __launch_bounds__(kPlastBlock) retract_k(const uint64_t* __restrict__ key,
                                                         const int32_t* __restrict__ val,
-                                                        int64_t cnt, const int32_t* __restrict__ exc,
+                                                        DevCount cnt, const int32_t* __restrict__ exc,
                                                         SynList L, int64_t n,
                                                         uint8_t* __restrict__ dead, int32_t* bound) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= cnt) return;
-  const uint64_t o = key[p] >> 32;
-  // first candidate of this owner
-  int64_t lo = 0, hi = p;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if ((key[mid] >> 32) < o) lo = mid + 1; else hi = mid;
-  }
-  if (p - lo < (int64_t)exc[o]) {
-    const int64_t s = val[p];
-    dead[s] = 1;
-    unbind(L, s, n, bound);
+  const int64_t c = cnt.get();
+  for (int64_t p = gtid(); p < c; p += gstride()) {
+    const uint64_t o = key[p] >> 32;
+    // first candidate of this owner
+    int64_t lo = 0, hi = p;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if ((key[mid] >> 32) < o) lo = mid + 1; else hi = mid;
+    }
+    if (p - lo < (int64_t)exc[o]) {
+      const int64_t s = val[p];
+      dead[s] = 1;
+      unbind(L, s, n, bound);
+    }
   }
 }
 
@@ -215,14 +235,36 @@ struct LiveFlag {
 };
 
 __global__ void __launch_bounds__(kPlastBlock) compact_k(SynList in, const uint8_t* __restrict__ dead,
-                                                        const int32_t* __restrict__ pos, int64_t m,
+                                                        const int32_t* __restrict__ pos, DevCount m,
                                                         SynList out) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= m || dead[s]) return;
-  const int64_t p = pos[s];
-  out.src[p] = in.src[s];
-  out.tgt[p] = in.tgt[s];
-  out.type[p] = in.type[s];
+  const int64_t m_ = m.get();
+  for (int64_t s = gtid(); s < m_; s += gstride()) {
+    if (dead[s]) continue;
+    const int64_t p = pos[s];
+    out.src[p] = in.src[s];
+    out.tgt[p] = in.tgt[s];
+    out.type[p] = in.type[s];
+  }
+}
+
+// The first `cnt` synapses of one list into another.
+__global__ void __launch_bounds__(kPlastBlock) copy_list_k(SynList from, DevCount cnt, SynList to) {
+  const int64_t c = cnt.get();
+  for (int64_t s = gtid(); s < c; s += gstride()) {
+    to.src[s] = from.src[s];
+    to.tgt[s] = from.tgt[s];
+    to.type[s] = from.type[s];
+  }
+}
+
+// A count the device found (a scan total at position *at of `pos`) as a 64-bit and a
+// 32-bit scalar.
+__global__ void take_count_k(const int32_t* __restrict__ pos, DevCount at, int64_t* c64,
+                             int32_t* c32) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int32_t c = pos[at.get()];
+  if (c64) *c64 = c;
+  if (c32) *c32 = c;
 }
 
 __global__ void __launch_bounds__(kPlastBlock) vacancy_k(const double* __restrict__ z,
@@ -240,18 +282,56 @@ __global__ void __launch_bounds__(kPlastBlock) vacancy_k(const double* __restric
 __global__ void __launch_bounds__(kPlastBlock) bind_k(const int32_t* __restrict__ src,
                                                      const int32_t* __restrict__ tgt,
                                                      const uint8_t* __restrict__ type,
-                                                     int64_t cnt, int64_t n, int32_t* bound,
+                                                     DevCount cnt, int64_t n, int32_t* bound,
                                                      int32_t* err) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= cnt) return;
-  const int32_t i = src[q], g = tgt[q];
-  const uint8_t ty = type[q];
-  if (i < 0 || i >= n || g < 0 || g >= n || ty > 1) {
-    atomicOr(err, 1);
+  const int64_t c = cnt.get();
+  for (int64_t q = gtid(); q < c; q += gstride()) {
+    const int32_t i = src[q], g = tgt[q];
+    const uint8_t ty = type[q];
+    if (i < 0 || i >= n || g < 0 || g >= n || ty > 1) {
+      atomicOr(err, 1);
+      continue;
+    }
+    atomicAdd(&bound[i], 1);
+    atomicAdd(&bound[(1 + (int64_t)ty) * n + g], 1);
+  }
+}
+
+// Appends the *cnt synapses of `from` to the list L after its *m entries and binds
+// their elements, if the list (capacity cap) holds them all; else appends nothing and
+// sets kRecordCapacity in *flags. record_end_k then advances *m.
+constexpr int32_t kRecordCapacity = 1;
+
+__global__ void __launch_bounds__(kPlastBlock) record_k(SynList from, DevCount cnt, SynList L,
+                                                       const int64_t* __restrict__ m, int64_t cap,
+                                                       int64_t n, int32_t* bound, int32_t* flags) {
+  const int64_t c = cnt.get();
+  const int64_t base = *m;
+  if (c == 0) return;
+  if (base + c > cap) {
+    if (gtid() == 0) atomicOr(flags, kRecordCapacity);
     return;
   }
-  atomicAdd(&bound[i], 1);
-  atomicAdd(&bound[(1 + (int64_t)ty) * n + g], 1);
+  for (int64_t q = gtid(); q < c; q += gstride()) {
+    const int32_t i = from.src[q], g = from.tgt[q];
+    const uint8_t ty = from.type[q];
+    L.src[base + q] = i;
+    L.tgt[base + q] = g;
+    L.type[base + q] = ty;
+    atomicAdd(&bound[i], 1);
+    atomicAdd(&bound[(1 + (int64_t)ty) * n + g], 1);
+  }
+}
+
+__global__ void record_end_k(DevCount cnt, int64_t* m, int64_t cap) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int64_t c = cnt.get();
+  if (*m + c <= cap) *m += c;
+}
+
+__global__ void __launch_bounds__(kPlastBlock) fill_u8_k(uint8_t* p, DevCount n, uint8_t v) {
+  const int64_t c = n.get();
+  for (int64_t i = gtid(); i < c; i += gstride()) p[i] = v;
 }
 
 }  // namespace msp

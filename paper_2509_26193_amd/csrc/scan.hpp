@@ -34,9 +34,20 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* lds4, T* total) {
   return off + x - v;
 }
 
+// Scans take an optional device count dn (nullable): the items are then the first
+// min(n, *dn) (a negative count is 0), the launches stay sized for n + 1 items and the
+// total goes to out[count].
+__device__ __forceinline__ int64_t scan_count(int64_t n, const int64_t* dn) {
+  if (!dn) return n;
+  const int64_t c = *dn;
+  return c < 0 ? 0 : (c < n ? c : n);
+}
+
 template <class T, class Tin, class F>
-__global__ void __launch_bounds__(kScanBlock) scan_reduce_k(const Tin* in, int64_t n, T* sums, F f) {
+__global__ void __launch_bounds__(kScanBlock) scan_reduce_k(const Tin* in, int64_t n, T* sums, F f,
+                                                           const int64_t* dn) {
   __shared__ T lds4[kScanBlock / kWave];
+  n = scan_count(n, dn);
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   T s = 0;
 #pragma unroll
@@ -52,8 +63,10 @@ __global__ void __launch_bounds__(kScanBlock) scan_reduce_k(const Tin* in, int64
 // out[i] = sum_{k<i} f(in[k]) + offsets[block]; if total_out, out[n] = grand total.
 template <class T, class Tin, class F>
 __global__ void __launch_bounds__(kScanBlock) scan_apply_k(const Tin* in, int64_t n, T* out,
-                                                          const T* offsets, F f, int write_total) {
+                                                          const T* offsets, F f, int write_total,
+                                                          const int64_t* dn) {
   __shared__ T lds4[kScanBlock / kWave];
+  n = scan_count(n, dn);
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   T v[kScanItems];
   T s = 0;
@@ -69,10 +82,11 @@ __global__ void __launch_bounds__(kScanBlock) scan_apply_k(const Tin* in, int64_
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     int64_t idx = base + k;
-    if (idx < n) out[idx] = pre;
+    if (idx < n || (dn && write_total && idx == n)) out[idx] = pre;
     pre += v[k];
   }
-  if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanBlock - 1) out[n] = pre;
+  if (!dn && write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanBlock - 1)
+    out[n] = pre;
 }
 
 template <class T>
@@ -99,10 +113,12 @@ size_t scan_tmp_bytes(int64_t n) {
 // Exclusive scan of f(in[i], i) into out[0..n) (and out[n] = total if write_total).
 // `in` may be null (f then sees a default value) and may alias `out` element for
 // element. Block sums go to `tmp` (scan_tmp_bytes<T>(n) bytes) or, if null, to
-// stream-ordered temporary memory.
+// stream-ordered temporary memory. With a device count dn (see scan_count) the scan
+// covers its first min(n, *dn) items, writes the total after them, and needs
+// scan_tmp_bytes<T>(n + 1) bytes of `tmp`.
 template <class T, class Tin, class F>
 hipError_t exclusive_scan(const Tin* in, T* out, int64_t n, F f, bool write_total, hipStream_t s,
-                          void* tmp = nullptr) {
+                          void* tmp = nullptr, const int64_t* dn = nullptr) {
   if (n <= 0) {
     if (write_total) {
       fill_scalar_k<T><<<1, 64, 0, s>>>(out, T(0));
@@ -110,9 +126,11 @@ hipError_t exclusive_scan(const Tin* in, T* out, int64_t n, F f, bool write_tota
     }
     return hipSuccess;
   }
-  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  // with a device count the launch also covers position n, where the total may go
+  const int64_t nb = (n + (dn ? 1 : 0) + kScanTile - 1) / kScanTile;
   if (nb == 1) {
-    scan_apply_k<T, Tin, F><<<1, kScanBlock, 0, s>>>(in, n, out, nullptr, f, write_total ? 1 : 0);
+    scan_apply_k<T, Tin, F><<<1, kScanBlock, 0, s>>>(in, n, out, nullptr, f, write_total ? 1 : 0,
+                                                     dn);
     return hipGetLastError();
   }
   Temp own(s);
@@ -126,13 +144,13 @@ hipError_t exclusive_scan(const Tin* in, T* out, int64_t n, F f, bool write_tota
     if (e != hipSuccess) return e;
     sums = own.as<T>();
   }
-  scan_reduce_k<T, Tin, F><<<(unsigned)nb, kScanBlock, 0, s>>>(in, n, sums, f);
+  scan_reduce_k<T, Tin, F><<<(unsigned)nb, kScanBlock, 0, s>>>(in, n, sums, f, dn);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = exclusive_scan<T, T, Ident<T>>(sums, sums, nb, Ident<T>(), false, s, rest);
   if (e != hipSuccess) return e;
   scan_apply_k<T, Tin, F><<<(unsigned)nb, kScanBlock, 0, s>>>(in, n, out, sums, f,
-                                                             write_total ? 1 : 0);
+                                                             write_total ? 1 : 0, dn);
   return hipGetLastError();
 }
 
@@ -251,6 +269,17 @@ __global__ void __launch_bounds__(kSortBlock) rs_scatter_k(const uint64_t* kin, 
   }
 }
 
+__global__ void __launch_bounds__(kSortBlock) rs_copy_k(const uint64_t* __restrict__ kin,
+                                                       const int32_t* __restrict__ vin,
+                                                       uint64_t* __restrict__ kout,
+                                                       int32_t* __restrict__ vout, int64_t n,
+                                                       const int32_t* dn) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= sort_count(n, dn)) return;
+  kout[i] = kin[i];
+  vout[i] = vin[i];
+}
+
 // Scratch bytes of radix_sort_pairs_ws for n items: the digit histograms, then the
 // block sums of their scan.
 inline size_t radix_sort_ws_bytes(int64_t n) {
@@ -263,11 +292,10 @@ inline size_t radix_sort_ws_bytes(int64_t n) {
 // Buffers k0/v0 hold the input and receive the output; k1/v1 are scratch of size n;
 // `ws` holds radix_sort_ws_bytes(n) bytes. Allocates nothing, so it can be captured.
 // dn (nullable, device): sort only the first min(n, *dn) items, a count known on the
-// device alone; the launches stay sized for n. Needs an even number of passes.
+// device alone; the launches stay sized for n.
 inline hipError_t radix_sort_pairs_ws(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1,
                                       int64_t n, int bits, hipStream_t s, void* ws,
                                       const int32_t* dn = nullptr) {
-  if (dn && ((bits + 7) / 8) % 2 != 0) return hipErrorInvalidValue;
   if (n <= 1) return hipSuccess;
   const int64_t nb = (n + kSortTile - 1) / kSortTile;
   uint32_t* hist = static_cast<uint32_t*>(ws);
@@ -290,6 +318,10 @@ inline hipError_t radix_sort_pairs_ws(uint64_t* k0, int32_t* v0, uint64_t* k1, i
     int32_t* tv = va; va = vb; vb = tv;
   }
   if (ka != k0) {
+    if (dn) {                           // an odd number of passes: copy the sorted items
+      rs_copy_k<<<grid_for(n, kSortBlock), kSortBlock, 0, s>>>(ka, va, k0, v0, n, dn);
+      return hipGetLastError();
+    }
     e = hipMemcpyAsync(k0, ka, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(v0, va, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s);
