@@ -201,7 +201,7 @@ __device__ void attract_tile(const SearchArgs& A, const AttractArgs& O, int tile
         x = sk;
         continue;
       }
-      const bool contains = li >= x && li < sk;
+      const bool contains = A.own && li >= x && li < sk;
       const double d2 = dist2(xi, yi, zi, cur.x, cur.y, cur.z);
       const bool acc_ok = bh_accept_u(A.L2, A.theta2, d2, meta);
       const bool open = active && (contains || !acc_ok);

@@ -28,6 +28,7 @@ struct SimDesc {
   const int32_t* nbeg;
   const int32_t* nend;
   const int32_t* leaf_of;
+  int32_t own;                  // per-thread walks test for the source's own cell
   int32_t* err;                 // the octree's sticky device flag
   const uint8_t* type;          // [n]
   const int32_t* vac_axon;      // [n]
@@ -83,6 +84,7 @@ __device__ __forceinline__ SearchArgs args_of(const SimDesc* sims, int s, const 
   A.nbeg = d->nbeg;
   A.nend = d->nend;
   A.leaf_of = d->leaf_of;
+  A.own = d->own != 0;
   A.type = d->type;
   A.vac_axon = d->vac_axon;
   A.elem_off = d->elem_off;

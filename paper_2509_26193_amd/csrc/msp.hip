@@ -70,6 +70,12 @@ __global__ void negative_k(const int32_t* __restrict__ a, int64_t n, int32_t* er
   if (k < n && a[k] < 0) atomicOr(err, 1);
 }
 
+// Whether the walks must test for the source's own cell: always, unless theta <= 1/2
+// and every position of the tree lies inside its cube (then that test never fires).
+bool own_cell_needed(const msp_octree_s* t, double theta) {
+  return !(t->inside && theta * theta <= 0.25);
+}
+
 // Fill the device descriptor of one simulation.
 SimDesc make_desc(const msp_octree_s* t, const uint8_t* neuron_type, const int32_t* vac_axon,
                   double sigma_um, double theta, uint64_t seed, uint64_t step, int32_t* target_out,
@@ -85,6 +91,7 @@ SimDesc make_desc(const msp_octree_s* t, const uint8_t* neuron_type, const int32
   d.nbeg = t->nbeg;
   d.nend = t->nend;
   d.leaf_of = t->leaf_of;
+  d.own = own_cell_needed(t, theta) ? 1 : 0;
   d.err = t->err;
   d.type = neuron_type;
   d.vac_axon = vac_axon;
@@ -103,12 +110,6 @@ SimDesc make_desc(const msp_octree_s* t, const uint8_t* neuron_type, const int32
 // Branch level of the two-phase search when the caller names none: restarts from
 // cells at this depth or deeper run in a second pass, in cell order.
 constexpr int kDefaultBranchLevel = kNoDefer;
-
-// Whether the sweep must test for the source's own cell: always, unless theta <= 1/2
-// and every position of the tree lies inside its cube (then that test never fires).
-bool own_cell_needed(const msp_octree_s* t, double theta) {
-  return !(t->inside && theta * theta <= 0.25);
-}
 
 // Persistent sweep blocks: occupancy x CUs (times `frac` in [0, 1]), at most one
 // wave per unit (a tile's part).

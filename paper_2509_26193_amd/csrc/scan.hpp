@@ -170,8 +170,15 @@ __device__ __forceinline__ int64_t sort_count(int64_t n, const int32_t* dn) {
   return c < 0 ? 0 : (c < n ? c : n);
 }
 
+// With a device count the histograms cover only the tiles that hold items: nbd (device)
+// is their number, and it replaces nb in the digit-major layout; blocks past it return.
 __global__ void __launch_bounds__(kSortBlock) rs_hist_k(const uint64_t* keys, int64_t n, int shift,
-                                                       uint32_t* hist, int nb, const int32_t* dn) {
+                                                       uint32_t* hist, int nb, const int32_t* dn,
+                                                       const int32_t* nbd) {
+  if (nbd) {
+    nb = *nbd;
+    if ((int)blockIdx.x >= nb) return;     // uniform over the block
+  }
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
@@ -192,7 +199,8 @@ __global__ void __launch_bounds__(kSortBlock) rs_hist_k(const uint64_t* keys, in
 __global__ void __launch_bounds__(kSortBlock) rs_scatter_k(const uint64_t* kin, const int32_t* vin,
                                                           uint64_t* kout, int32_t* vout, int64_t n,
                                                           int shift, const uint32_t* off, int nb,
-                                                          const int32_t* dn) {
+                                                          const int32_t* dn, const int32_t* nbd) {
+  if (nbd) nb = *nbd;
   __shared__ uint64_t lk[kSortTile];
   __shared__ int32_t lv[kSortTile];
   __shared__ uint32_t lstart[256];      // tile-local start of each digit's run
@@ -280,12 +288,22 @@ __global__ void __launch_bounds__(kSortBlock) rs_copy_k(const uint64_t* __restri
   vout[i] = vin[i];
 }
 
-// Scratch bytes of radix_sort_pairs_ws for n items: the digit histograms, then the
-// block sums of their scan.
+// The tiles that hold the first min(n, *dn) items (as int32 for the kernels) and their
+// histogram entries (as int64 for the scan).
+__global__ void rs_tiles_k(int64_t n, const int32_t* dn, int32_t* nbd, int64_t* hn) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int64_t c = sort_count(n, dn);
+  const int64_t t = (c + kSortTile - 1) / kSortTile;
+  *nbd = (int32_t)t;
+  *hn = 256 * t;
+}
+
+// Scratch bytes of radix_sort_pairs_ws for n items: the digit histograms, the block
+// sums of their scan, and the tile counts of a device-counted sort.
 inline size_t radix_sort_ws_bytes(int64_t n) {
   const int64_t nb = (n + kSortTile - 1) / kSortTile;
   const size_t hist = ((sizeof(uint32_t) * 256 * (size_t)(nb > 0 ? nb : 1)) + 255) & ~(size_t)255;
-  return hist + scan_tmp_bytes<uint32_t>(256 * (nb > 0 ? nb : 1));
+  return hist + scan_tmp_bytes<uint32_t>(256 * (nb > 0 ? nb : 1) + 1) + 256;
 }
 
 // Sort (keys, vals) of length n ascending by the low `bits` key bits (a multiple of 8).
@@ -299,19 +317,29 @@ inline hipError_t radix_sort_pairs_ws(uint64_t* k0, int32_t* v0, uint64_t* k1, i
   if (n <= 1) return hipSuccess;
   const int64_t nb = (n + kSortTile - 1) / kSortTile;
   uint32_t* hist = static_cast<uint32_t*>(ws);
-  void* scan_ws = static_cast<char*>(ws) + (((sizeof(uint32_t) * 256 * (size_t)nb) + 255) & ~(size_t)255);
+  const size_t hist_bytes = ((sizeof(uint32_t) * 256 * (size_t)nb) + 255) & ~(size_t)255;
+  void* scan_ws = static_cast<char*>(ws) + hist_bytes;
+  // a device-counted sort sizes its histograms by the tiles that hold items
+  int32_t* nbd = nullptr;
+  int64_t* hn = nullptr;
+  if (dn) {
+    char* tail = static_cast<char*>(scan_ws) + scan_tmp_bytes<uint32_t>(256 * nb + 1);
+    hn = reinterpret_cast<int64_t*>(tail);
+    nbd = reinterpret_cast<int32_t*>(tail + sizeof(int64_t));
+    rs_tiles_k<<<1, 64, 0, s>>>(n, dn, nbd, hn);
+  }
   uint64_t* ka = k0;
   int32_t* va = v0;
   uint64_t* kb = k1;
   int32_t* vb = v1;
   hipError_t e = hipSuccess;
   for (int shift = 0; shift < bits; shift += 8) {
-    rs_hist_k<<<(unsigned)nb, kSortBlock, 0, s>>>(ka, n, shift, hist, (int)nb, dn);
+    rs_hist_k<<<(unsigned)nb, kSortBlock, 0, s>>>(ka, n, shift, hist, (int)nb, dn, nbd);
     e = exclusive_scan<uint32_t, uint32_t, Ident<uint32_t>>(hist, hist, 256 * nb, Ident<uint32_t>(),
-                                                            false, s, scan_ws);
+                                                            false, s, scan_ws, hn);
     if (e != hipSuccess) return e;
     rs_scatter_k<<<(unsigned)nb, kSortBlock, 0, s>>>(ka, va, kb, vb, n, shift, hist, (int)nb,
-                                                     dn);
+                                                     dn, nbd);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     uint64_t* tk = ka; ka = kb; kb = tk;

@@ -31,6 +31,7 @@ struct SearchArgs {
   const int32_t* nbeg;
   const int32_t* nend;
   const int32_t* leaf_of;
+  bool own;                      // test for the source's own cell (see own_cell_needed)
   const uint8_t* type;
   const int32_t* vac_axon;
   const int64_t* elem_off;
@@ -188,7 +189,8 @@ __device__ void expand_range(const SearchArgs& A, const NodeRec* __restrict__ R,
       x = sk;
       continue;
     }
-    if (li >= x && li < sk) {        // the source's own cell is always opened
+    if (A.own && li >= x && li < sk) {   // the source's own cell is always opened,
+                                         // where the acceptance test could pass it
       if (COUNT) cnt.opens += 1;
       ++x;
       continue;
