@@ -254,7 +254,10 @@ msp_status msp_batch_create(const msp_sim* sims, int32_t n_sims, int32_t flags, 
  * nullable = reuse the previous run's) must name the plan's octrees in the same order.
  * Asynchronous: per-simulation errors (capacity exceeded, negative vac_axon, type > 1)
  * are reported by msp_batch_status; such a simulation's target_out is not written, its
- * elem_offset_out is. */
+ * elem_offset_out is. A run without `sims` writes the new theta and step on the device
+ * and never waits; a run with `sims` (and the first run) uploads the descriptors from
+ * a host staging buffer and first waits until the previous upload has been read.
+ * Runs of one plan must be ordered (one stream, or ordered by the caller). */
 msp_status msp_find_targets_batched(msp_batch b, const msp_sim* sims, double theta,
                                     uint64_t step, hipStream_t s);
 

@@ -29,6 +29,7 @@ struct SimDesc {
   const int32_t* nend;
   const int32_t* leaf_of;
   int32_t own;                  // per-thread walks test for the source's own cell
+  int32_t inside;               // the octree's positions lie inside its cube
   int32_t* err;                 // the octree's sticky device flag
   const uint8_t* type;          // [n]
   const int32_t* vac_axon;      // [n]

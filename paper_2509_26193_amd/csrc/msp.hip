@@ -92,6 +92,7 @@ SimDesc make_desc(const msp_octree_s* t, const uint8_t* neuron_type, const int32
   d.nend = t->nend;
   d.leaf_of = t->leaf_of;
   d.own = own_cell_needed(t, theta) ? 1 : 0;
+  d.inside = t->inside ? 1 : 0;
   d.err = t->err;
   d.type = neuron_type;
   d.vac_axon = vac_axon;
@@ -799,6 +800,7 @@ struct msp_batch_s {
   SearchScratch S;
   hipEvent_t staged;        // the descriptor upload of the last run has completed
   bool staged_pending;
+  bool uploaded;            // the device table holds descriptors of the plan's sims
   unsigned sweep_blocks;
   int draw_block;
   int ck_slots;             // checkpoint slots per region
@@ -823,6 +825,16 @@ void batch_release(msp_batch_s* b) {
   if (b->d_nbase) (void)hipFree(b->d_nbase);
   if (b->scratch) (void)hipFree(b->scratch);
   delete b;
+}
+
+// A new theta and step in every descriptor of a batch (the rest is unchanged); the
+// own-cell test as own_cell_needed decides it from the octree's `inside`.
+__global__ void desc_theta_step_k(SimDesc* d, int n, double theta2, uint64_t step) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  d[k].theta2 = theta2;
+  d[k].step = step;
+  d[k].own = (d[k].inside && theta2 <= 0.25) ? 0 : 1;
 }
 
 bool sim_ok(const msp_sim& m) {
@@ -932,6 +944,7 @@ msp_status msp_batch_create(const msp_sim* sims, int32_t n_sims, int32_t flags, 
   b->scratch = nullptr;
   b->staged = nullptr;
   b->staged_pending = false;
+  b->uploaded = false;
   b->tuned = false;
   b->captured = false;
   b->captured_own = true;
@@ -973,25 +986,34 @@ msp_status msp_find_targets_batched(msp_batch b, const msp_sim* sims, double the
       if (!sim_ok(sims[k]) || sims[k].tree != b->sims[k].tree) return MSP_ERR_INVALID;
     b->sims.assign(sims, sims + b->nsims);
   }
-  // the staging buffer is reused: wait until the previous upload has been read
-  if (b->staged_pending) MSP_HIP_TRY(hipEventSynchronize(b->staged));
   bool own = false;
-  for (int k = 0; k < b->nsims; ++k) {
-    const msp_sim& m = b->sims[k];
-    b->h_sims[k] = make_desc(m.tree, m.neuron_type, m.vac_axon, m.sigma_um, theta, m.seed, step,
-                             m.target_out, m.elem_offset_out, m.capacity_S);
-    own = own || own_cell_needed(m.tree, theta);
-  }
+  for (int k = 0; k < b->nsims; ++k) own = own || own_cell_needed(b->sims[k].tree, theta);
   b->S.own_cell = own;
   if (b->captured && b->captured_own != own) {     // the captured sweep is the other variant
     MSP_HIP_TRY(hipStreamSynchronize(s));
     (void)hipGraphExecDestroy(b->exec);
     b->captured = false;
   }
-  MSP_HIP_TRY(hipMemcpyAsync(b->d_sims, b->h_sims, sizeof(SimDesc) * b->nsims,
-                             hipMemcpyHostToDevice, s));
-  MSP_HIP_TRY(hipEventRecord(b->staged, s));
-  b->staged_pending = true;
+  if (sims || !b->uploaded) {
+    // new descriptors from the host; the staging buffer is reused: wait until the
+    // previous upload has been read
+    if (b->staged_pending) MSP_HIP_TRY(hipEventSynchronize(b->staged));
+    for (int k = 0; k < b->nsims; ++k) {
+      const msp_sim& m = b->sims[k];
+      b->h_sims[k] = make_desc(m.tree, m.neuron_type, m.vac_axon, m.sigma_um, theta, m.seed,
+                               step, m.target_out, m.elem_offset_out, m.capacity_S);
+    }
+    MSP_HIP_TRY(hipMemcpyAsync(b->d_sims, b->h_sims, sizeof(SimDesc) * b->nsims,
+                               hipMemcpyHostToDevice, s));
+    MSP_HIP_TRY(hipEventRecord(b->staged, s));
+    b->staged_pending = true;
+    b->uploaded = true;
+  } else {
+    // the same simulations: only theta and the step change, written on the device
+    desc_theta_step_k<<<grid_for(b->nsims, 64), 64, 0, s>>>(b->d_sims, b->nsims, theta * theta,
+                                                            step);
+    MSP_HIP_TRY(hipGetLastError());
+  }
   if ((b->flags & MSP_BATCH_AUTOTUNE) && !b->tuned) {
     MSP_HIP_TRY(batch_autotune(b, s));
     b->tuned = true;
