@@ -736,12 +736,13 @@ def main():
         ev[4].record()
         tree.free()
         if record:
-            torch.cuda.synchronize()
-            for k, (a, b) in zip(("build", "refresh", "search", "commit"), zip(ev[:-1], ev[1:])):
-                times[k].append(a.elapsed_time(b))
+            # the phase events are read after the timed loop: no wait inside it
+            pending.append(ev)
             times["sweep"].append(tm["sweep_ms"])
             times["draw"].append(tm["draw_ms"])
         return res["n_formed"]
+
+    pending = []
 
     for k in range(args.warmup):
         step(False)
@@ -757,6 +758,9 @@ def main():
     t1 = time.perf_counter()
     sec = (t1 - t0) / args.steps
     value = S / sec
+    for ev in pending:
+        for k, (a, b) in zip(("build", "refresh", "search", "commit"), zip(ev[:-1], ev[1:])):
+            times[k].append(a.elapsed_time(b))
 
     # the last timed step's targets (the commit does not touch them): the cpu_baseline
     # leg compares them with the oracle
