@@ -191,6 +191,17 @@ struct RetractFlag {            // live synapse of a neuron with an excess of ki
   }
 };
 
+// The candidate flags of one kind, once (the scan and the key pass read the bytes).
+__global__ void __launch_bounds__(kPlastBlock) retract_flag_k(RetractFlag F, DevCount m,
+                                                             uint8_t* __restrict__ flag) {
+  const int64_t m_ = m.get();
+  for (int64_t s = gtid(); s < m_; s += gstride()) flag[s] = (uint8_t)F(0, s);
+}
+
+struct ByteCount {
+  __device__ int32_t operator()(uint8_t a, int64_t) const { return (int32_t)a; }
+};
+
 __global__ void __launch_bounds__(kPlastBlock) cand_write_k(RetractFlag F, const int32_t* __restrict__ pos,
                                                            DevCount m, uint64_t seed, DevStep step,
                                                            uint64_t* __restrict__ key,
@@ -198,7 +209,7 @@ __global__ void __launch_bounds__(kPlastBlock) cand_write_k(RetractFlag F, const
   const int64_t m_ = m.get();
   const uint64_t st = step.get();
   for (int64_t s = gtid(); s < m_; s += gstride()) {
-    if (!F(0, s)) continue;
+    if (pos[s + 1] == pos[s]) continue;       // not a candidate (pos: the flags' scan)
     const int32_t o = owner_of(F.L, s, F.k);
     const uint64_t q = philox_word0(seed, 4, (uint64_t)s, st, (uint64_t)F.k, 0) >> 32;
     key[pos[s]] = ((uint64_t)(uint32_t)o << 32) | q;

@@ -1,6 +1,8 @@
 // Device-wide exclusive prefix sums and an LSD radix sort of (64-bit key, int32 value).
 #pragma once
 
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace msp {
@@ -49,6 +51,10 @@ __global__ void __launch_bounds__(kScanBlock) scan_reduce_k(const Tin* in, int64
   __shared__ T lds4[kScanBlock / kWave];
   n = scan_count(n, dn);
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  if (base >= n) {                      // past a device count: an empty block
+    if (threadIdx.x == 0) sums[blockIdx.x] = 0;
+    return;
+  }
   T s = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
@@ -67,6 +73,7 @@ __global__ void __launch_bounds__(kScanBlock) scan_apply_k(const Tin* in, int64_
                                                           const int64_t* dn) {
   __shared__ T lds4[kScanBlock / kWave];
   n = scan_count(n, dn);
+  if ((int64_t)blockIdx.x * kScanTile > n) return;   // nothing to write (uniform)
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   T v[kScanItems];
   T s = 0;
@@ -161,6 +168,7 @@ hipError_t exclusive_scan(const Tin* in, T* out, int64_t n, F f, bool write_tota
 constexpr int kSortBlock = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortBlock * kSortItems;
+constexpr int64_t kSortGridDn = 1024;   // blocks of a device-counted sort's passes
 
 // dn (nullable): a device count that lowers n (items past it are left alone; the
 // tiles beyond it contribute empty histograms and write nothing).
@@ -171,25 +179,26 @@ __device__ __forceinline__ int64_t sort_count(int64_t n, const int32_t* dn) {
 }
 
 // With a device count the histograms cover only the tiles that hold items: nbd (device)
-// is their number, and it replaces nb in the digit-major layout; blocks past it return.
+// is their number, and it replaces nb in the digit-major layout. A block takes tiles
+// blockIdx.x, + gridDim.x, ... (a device-counted sort launches fewer blocks than tiles).
 __global__ void __launch_bounds__(kSortBlock) rs_hist_k(const uint64_t* keys, int64_t n, int shift,
                                                        uint32_t* hist, int nb, const int32_t* dn,
                                                        const int32_t* nbd) {
-  if (nbd) {
-    nb = *nbd;
-    if ((int)blockIdx.x >= nb) return;     // uniform over the block
-  }
+  if (nbd) nb = *nbd;
   __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
-  __syncthreads();
   n = sort_count(n, dn);
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
-  for (int k = 0; k < kSortItems && base < n; ++k) {
-    int64_t idx = base + (int64_t)k * kSortBlock + threadIdx.x;
-    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+  for (int tile = blockIdx.x; tile < nb; tile += gridDim.x) {   // uniform over the block
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)tile * kSortTile;
+    for (int k = 0; k < kSortItems && base < n; ++k) {
+      int64_t idx = base + (int64_t)k * kSortBlock + threadIdx.x;
+      if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nb + tile] = h[threadIdx.x];
+    __syncthreads();                    // h is cleared for the next tile
   }
-  __syncthreads();
-  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
 // One tile of kSortTile items: ranked by digit (stable) into LDS first, then written
@@ -212,68 +221,71 @@ __global__ void __launch_bounds__(kSortBlock) rs_scatter_k(const uint64_t* kin, 
   const int lane = t & (kWave - 1);
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (kWave - lane));
   n = sort_count(n, dn);
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
-  if (base >= n) return;                // uniform over the block
-  const int64_t rem = n - base;
-  const int tile_n = rem < kSortTile ? (int)rem : kSortTile;
-  const int64_t h = (int64_t)t * nb + blockIdx.x;
-  const uint32_t g0 = off[h];
-  const uint32_t g1 = h + 1 < 256 * (int64_t)nb ? off[h + 1] : (uint32_t)n;
-  const uint32_t count = g1 - g0;       // this tile's items of digit t
-  gstart[t] = g0;
-  lstart[t] = count;
-  run[t] = 0;
-  __syncthreads();
-  // inclusive scan of the 256 counts (Hillis-Steele), then exclusive = inclusive - own
-  for (int d = 1; d < 256; d <<= 1) {
-    const uint32_t v = t >= d ? lstart[t - d] : 0u;
+  for (int tile = blockIdx.x; tile < nb; tile += gridDim.x) {   // uniform over the block
+    const int64_t base = (int64_t)tile * kSortTile;
+    if (base >= n) break;
+    const int64_t rem = n - base;
+    const int tile_n = rem < kSortTile ? (int)rem : kSortTile;
+    const int64_t h = (int64_t)t * nb + tile;
+    const uint32_t g0 = off[h];
+    const uint32_t g1 = h + 1 < 256 * (int64_t)nb ? off[h + 1] : (uint32_t)n;
+    const uint32_t count = g1 - g0;     // this tile's items of digit t
+    gstart[t] = g0;
+    lstart[t] = count;
+    run[t] = 0;
     __syncthreads();
-    lstart[t] += v;
-    __syncthreads();
-  }
-  lstart[t] -= count;
-  __syncthreads();
-  for (int c = 0; c < kSortItems; ++c) {
-#pragma unroll
-    for (int k = 0; k < kSortBlock / kWave; ++k) wcnt[k][t] = 0;
-    __syncthreads();
-    const int li = c * kSortBlock + t;
-    const bool valid = li < tile_n;
-    const uint64_t key = valid ? kin[base + li] : 0ull;
-    const uint32_t d = (uint32_t)(key >> shift) & 255u;
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bb = __ballot(bit);
-      peers &= bit ? bb : ~bb;
+    // inclusive scan of the 256 counts (Hillis-Steele), then exclusive = inclusive - own
+    for (int d = 1; d < 256; d <<= 1) {
+      const uint32_t v = t >= d ? lstart[t - d] : 0u;
+      __syncthreads();
+      lstart[t] += v;
+      __syncthreads();
     }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+    lstart[t] -= count;
     __syncthreads();
-    if (valid) {
-      uint32_t p = lstart[d] + run[d] + rank;
-      for (int k = 0; k < w; ++k) p += wcnt[k][d];
-      if (p < (uint32_t)kSortTile) {
-        lk[p] = key;
-        lv[p] = vin[base + li];
+    for (int c = 0; c < kSortItems; ++c) {
+#pragma unroll
+      for (int k = 0; k < kSortBlock / kWave; ++k) wcnt[k][t] = 0;
+      __syncthreads();
+      const int li = c * kSortBlock + t;
+      const bool valid = li < tile_n;
+      const uint64_t key = valid ? kin[base + li] : 0ull;
+      const uint32_t d = (uint32_t)(key >> shift) & 255u;
+      uint64_t peers = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        peers &= bit ? bb : ~bb;
+      }
+      const uint32_t rank = (uint32_t)__popcll(peers & lt);
+      if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+      __syncthreads();
+      if (valid) {
+        uint32_t p = lstart[d] + run[d] + rank;
+        for (int k = 0; k < w; ++k) p += wcnt[k][d];
+        if (p < (uint32_t)kSortTile) {
+          lk[p] = key;
+          lv[p] = vin[base + li];
+        }
+      }
+      __syncthreads();
+      uint32_t add = 0;
+#pragma unroll
+      for (int k = 0; k < kSortBlock / kWave; ++k) add += wcnt[k][t];
+      run[t] += add;
+    }
+    __syncthreads();
+    for (int i = t; i < tile_n; i += kSortBlock) {
+      const uint64_t key = lk[i];
+      const uint32_t d = (uint32_t)(key >> shift) & 255u;
+      const uint32_t g = gstart[d] + ((uint32_t)i - lstart[d]);
+      if ((int64_t)g < n) {
+        kout[g] = key;
+        vout[g] = lv[i];
       }
     }
-    __syncthreads();
-    uint32_t add = 0;
-#pragma unroll
-    for (int k = 0; k < kSortBlock / kWave; ++k) add += wcnt[k][t];
-    run[t] += add;
-  }
-  __syncthreads();
-  for (int i = t; i < tile_n; i += kSortBlock) {
-    const uint64_t key = lk[i];
-    const uint32_t d = (uint32_t)(key >> shift) & 255u;
-    const uint32_t g = gstart[d] + ((uint32_t)i - lstart[d]);
-    if ((int64_t)g < n) {
-      kout[g] = key;
-      vout[g] = lv[i];
-    }
+    __syncthreads();                    // the shared arrays are reused by the next tile
   }
 }
 
@@ -282,10 +294,11 @@ __global__ void __launch_bounds__(kSortBlock) rs_copy_k(const uint64_t* __restri
                                                        uint64_t* __restrict__ kout,
                                                        int32_t* __restrict__ vout, int64_t n,
                                                        const int32_t* dn) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= sort_count(n, dn)) return;
-  kout[i] = kin[i];
-  vout[i] = vin[i];
+  const int64_t c = sort_count(n, dn);
+  for (int64_t i = gtid(); i < c; i += gstride()) {
+    kout[i] = kin[i];
+    vout[i] = vin[i];
+  }
 }
 
 // The tiles that hold the first min(n, *dn) items (as int32 for the kernels) and their
@@ -333,13 +346,14 @@ inline hipError_t radix_sort_pairs_ws(uint64_t* k0, int32_t* v0, uint64_t* k1, i
   uint64_t* kb = k1;
   int32_t* vb = v1;
   hipError_t e = hipSuccess;
+  // a device-counted sort holds few tiles with items, mostly: a bounded grid loops
+  const unsigned grid = dn ? (unsigned)std::min<int64_t>(nb, kSortGridDn) : (unsigned)nb;
   for (int shift = 0; shift < bits; shift += 8) {
-    rs_hist_k<<<(unsigned)nb, kSortBlock, 0, s>>>(ka, n, shift, hist, (int)nb, dn, nbd);
+    rs_hist_k<<<grid, kSortBlock, 0, s>>>(ka, n, shift, hist, (int)nb, dn, nbd);
     e = exclusive_scan<uint32_t, uint32_t, Ident<uint32_t>>(hist, hist, 256 * nb, Ident<uint32_t>(),
                                                             false, s, scan_ws, hn);
     if (e != hipSuccess) return e;
-    rs_scatter_k<<<(unsigned)nb, kSortBlock, 0, s>>>(ka, va, kb, vb, n, shift, hist, (int)nb,
-                                                     dn, nbd);
+    rs_scatter_k<<<grid, kSortBlock, 0, s>>>(ka, va, kb, vb, n, shift, hist, (int)nb, dn, nbd);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     uint64_t* tk = ka; ka = kb; kb = tk;
@@ -347,7 +361,7 @@ inline hipError_t radix_sort_pairs_ws(uint64_t* k0, int32_t* v0, uint64_t* k1, i
   }
   if (ka != k0) {
     if (dn) {                           // an odd number of passes: copy the sorted items
-      rs_copy_k<<<grid_for(n, kSortBlock), kSortBlock, 0, s>>>(ka, va, k0, v0, n, dn);
+      rs_copy_k<<<grid_cap(n, kSortBlock), kSortBlock, 0, s>>>(ka, va, k0, v0, n, dn);
       return hipGetLastError();
     }
     e = hipMemcpyAsync(k0, ka, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s);

@@ -94,6 +94,7 @@ struct PlastConst {
 // Working memory of a plasticity step over a list of up to cap_m synapses.
 struct PlastWs {
   uint8_t* dead;
+  uint8_t* cflag;               // retraction candidates of one kind
   uint64_t* k0;
   uint64_t* k1;
   int32_t* v0;
@@ -113,6 +114,7 @@ inline PlastWs plast_ws(void* base, int64_t n, int64_t cap_m, size_t* bytes) {
   Carver c{static_cast<char*>(base)};
   PlastWs w;
   w.dead = c.take<uint8_t>(cap_m);
+  w.cflag = c.take<uint8_t>(cap_m);
   w.k0 = c.take<uint64_t>(cap_m);
   w.k1 = c.take<uint64_t>(cap_m);
   w.v0 = c.take<int32_t>(cap_m);
@@ -169,8 +171,9 @@ inline hipError_t enqueue_plasticity(const PlastWs& w, int64_t n, const PlastCon
       excess_k<<<grid_for(n, kPlastBlock), kPlastBlock, 0, s>>>(bound + k * n, z + k * n, n,
                                                                w.exc);
       const RetractFlag F{L, w.dead, w.exc, k};
-      e = exclusive_scan<int32_t, int32_t, RetractFlag>(nullptr, w.pos, m.v, F, true, s,
-                                                        w.scan_ws, m.p);
+      retract_flag_k<<<gm, kPlastBlock, 0, s>>>(F, m, w.cflag);
+      e = exclusive_scan<int32_t, uint8_t, ByteCount>(w.cflag, w.pos, m.v, ByteCount(), true, s,
+                                                      w.scan_ws, m.p);
       if (e != hipSuccess) return e;
       take_count_k<<<1, 64, 0, s>>>(w.pos, m, w.cnt, w.cnt32);
       cand_write_k<<<gm, kPlastBlock, 0, s>>>(F, w.pos, m, seed, step, w.k0, w.v0);
