@@ -148,7 +148,7 @@ search_sweep_k(BatchDev B, SweepOut W) {
 // One thread per worklist slot (source): its elements' draws and restarts. The 64
 // slots of a wavefront form one tile, so the simulation is uniform across the wave.
 template <bool DIAG, int SLOTS, bool DEFER>
-__global__ void __launch_bounds__(256) search_draw_k(BatchDev B, SweepOut W) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) search_draw_k(BatchDev B, SweepOut W) {
   const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t tile = slot / kWave;
   if (tile >= *W.tile_count) return;
@@ -168,7 +168,14 @@ __global__ void __launch_bounds__(256) search_draw_k(BatchDev B, SweepOut W) {
     D.opens0 = d->diag.opens0;
     D.entries0 = d->diag.entries0;
   }
-  draw_slot<DIAG, SLOTS, DEFER>(A, D, W, slot, u0, plog, *W.unit_count <= W.ck_units);
+  // the restart levels' entries: kRestartKeep weights, then as many ids, per thread,
+  // in LDS sized by the launch (kRestartLds bytes per thread)
+  extern __shared__ double keep_lds[];
+  const KeptEntries keep{keep_lds + threadIdx.x,
+                         reinterpret_cast<uint32_t*>(keep_lds + kRestartKeep * blockDim.x) +
+                             threadIdx.x,
+                         (int)blockDim.x};
+  draw_slot<DIAG, SLOTS, DEFER>(A, D, W, slot, u0, plog, *W.unit_count <= W.ck_units, &keep);
 }
 
 // Second phase of a two-phase search (one simulation): one thread per request in
@@ -572,6 +579,9 @@ inline hipError_t enqueue_prep(SearchScratch& S, int64_t total_n, hipStream_t s,
   return hipGetLastError();
 }
 
+// LDS bytes per draw thread: a restart level's kept weights and ids.
+constexpr size_t kRestartLds = kRestartKeep * (sizeof(double) + sizeof(uint32_t));
+
 // The sweep and draw launches. `sweep_blocks` persistent blocks; the draw covers
 // every possible slot (threads past the tile count return at once).
 template <bool DIAG, int SLOTS>
@@ -585,9 +595,9 @@ inline void launch_sweep(const SearchScratch& S, unsigned blocks, hipStream_t s)
 template <bool DIAG, int SLOTS>
 inline void launch_draw(const SearchScratch& S, unsigned grid, int block, hipStream_t s) {
   if (S.W.defer.depth < kNoDefer)
-    search_draw_k<DIAG, SLOTS, true><<<grid, block, 0, s>>>(S.B, S.W);
+    search_draw_k<DIAG, SLOTS, true><<<grid, block, kRestartLds * block, s>>>(S.B, S.W);
   else
-    search_draw_k<DIAG, SLOTS, false><<<grid, block, 0, s>>>(S.B, S.W);
+    search_draw_k<DIAG, SLOTS, false><<<grid, block, kRestartLds * block, s>>>(S.B, S.W);
 }
 
 inline hipError_t enqueue_search(SearchScratch& S, bool diag, unsigned sweep_blocks,

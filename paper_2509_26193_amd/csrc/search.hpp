@@ -235,30 +235,100 @@ __device__ __forceinline__ int cell_depth(uint32_t meta) {
   return (int)((meta >> kSkipBits) & 31u);
 }
 
+// A restart level's list is short (the children of a far cell, mostly): the sum walk
+// keeps up to kRestartKeep entries (weight; id with bit 31 set for a neuron) in
+// per-thread memory `stride` elements apart, and the choice is then made from them in
+// the same order with the same additions, without a second walk.
+constexpr int kRestartKeep = 8;
+constexpr uint32_t kKeptNeuron = 0x80000000u;
+
+struct KeptEntries {
+  double* w;
+  uint32_t* id;
+  int stride;
+};
+
+struct SumKeepPass {
+  double k2;
+  KeptEntries K;
+  double Z = 0.0;
+  int n = 0;
+  __device__ __forceinline__ bool operator()(int32_t id, bool neuron, int32_t v, double d2) {
+    const double w = kernel_weight(v, d2, k2);
+    Z = Z + w;
+    if (n < kRestartKeep) {
+      K.w[n * K.stride] = w;
+      K.id[n * K.stride] = (uint32_t)id | (neuron ? kKeptNeuron : 0u);
+    }
+    ++n;
+    return false;
+  }
+};
+
 // Levels >= level0 of a search (level0 >= 1): restart at the chosen cell S until a
 // neuron is drawn. A cell at depth >= defer_depth is not expanded here: the call
 // returns kDeferred with *S_out = that cell and *levels_out = the levels drawn so far
 // (its expansion is level *levels_out), for the second phase to continue from.
+// keep (nullable): memory for the entries of a level (see SumKeepPass).
 template <bool COUNT, bool DEFER>
 __device__ int32_t restart_search(const SearchArgs& A, const NodeRec* R, const int32_t* vs,
                                   int32_t S, int level0, int defer_depth, int32_t i, int32_t j,
                                   int32_t li, double xi, double yi, double zi, int* levels_out,
-                                  Count& cnt, int32_t* S_out) {
+                                  Count& cnt, int32_t* S_out, const KeptEntries* keep = nullptr) {
   Count none;
   for (int level = level0; level < kMaxLevels; ++level) {
     if (DEFER && cell_depth(R[S].meta) >= defer_depth) {
       *S_out = S;
       return kDeferred;
     }
-    SumPass s{A.k2};
-    expand<COUNT>(A, R, vs, S, i, li, xi, yi, zi, s, cnt);
-    *levels_out = level + 1;
-    if (!(s.Z > 0.0)) return -1;
-    const double T = draw_u(A.seed, i, j, A.step, level) * s.Z;
-    SelectPass p{A.k2, T};
-    expand<false>(A, R, vs, S, i, li, xi, yi, zi, p, none);
-    const int32_t id = p.chosen >= 0 ? p.chosen : p.last;
-    const bool neuron = p.chosen >= 0 ? p.chosen_neuron : p.last_neuron;
+    int32_t id;
+    bool neuron;
+    if (keep) {
+      SumKeepPass s{A.k2, *keep};
+      expand<COUNT>(A, R, vs, S, i, li, xi, yi, zi, s, cnt);
+      *levels_out = level + 1;
+      if (!(s.Z > 0.0)) return -1;
+      const double T = draw_u(A.seed, i, j, A.step, level) * s.Z;
+      if (s.n <= kRestartKeep) {
+        // SelectPass over the kept entries
+        double P = 0.0;
+        int32_t chosen = -1, last = -1;
+        bool chosen_neuron = false, last_neuron = false;
+        for (int e = 0; e < s.n; ++e) {
+          const double w = keep->w[e * keep->stride];
+          const uint32_t r = keep->id[e * keep->stride];
+          const int32_t eid = (int32_t)(r & ~kKeptNeuron);
+          const bool en = (r & kKeptNeuron) != 0;
+          if (w > 0.0) {
+            last = eid;
+            last_neuron = en;
+          }
+          P = P + w;
+          if (P > T) {
+            chosen = eid;
+            chosen_neuron = en;
+            break;
+          }
+        }
+        id = chosen >= 0 ? chosen : last;
+        neuron = chosen >= 0 ? chosen_neuron : last_neuron;
+      } else {
+        SelectPass p{A.k2, T};
+        expand<false>(A, R, vs, S, i, li, xi, yi, zi, p, none);
+        id = p.chosen >= 0 ? p.chosen : p.last;
+        neuron = p.chosen >= 0 ? p.chosen_neuron : p.last_neuron;
+      }
+    } else {
+      SumPass s{A.k2};
+      expand<COUNT>(A, R, vs, S, i, li, xi, yi, zi, s, cnt);
+      *levels_out = level + 1;
+      if (!(s.Z > 0.0)) return -1;
+      const double T = draw_u(A.seed, i, j, A.step, level) * s.Z;
+      SelectPass p{A.k2, T};
+      expand<false>(A, R, vs, S, i, li, xi, yi, zi, p, none);
+      id = p.chosen >= 0 ? p.chosen : p.last;
+      neuron = p.chosen >= 0 ? p.chosen_neuron : p.last_neuron;
+    }
     if (id < 0) return -1;
     if (neuron) return id;
     S = id;

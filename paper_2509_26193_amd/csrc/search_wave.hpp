@@ -376,10 +376,12 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
 
 // The draws and restarts of the source in worklist slot `slot` (DEFER: restarts from
 // cells at depth >= W.defer.depth become second-phase requests). The slot's tile has
-// 2^plog parts, units u0, u0 + 1, ...
+// 2^plog parts, units u0, u0 + 1, ... keep: the thread's memory for a restart level's
+// entries (see restart_search).
 template <bool DIAG, int SLOTS, bool DEFER>
 __device__ __forceinline__ void draw_slot(const SearchArgs& A, const DiagOut& D, const SweepOut& W,
-                                          int64_t slot, int64_t u0, int plog, bool own) {
+                                          int64_t slot, int64_t u0, int plog, bool own,
+                                          const KeptEntries* keep) {
   const int32_t i = A.work[slot];
   if (i < 0) return;
   const int64_t tile = slot / kWave;
@@ -456,7 +458,7 @@ __device__ __forceinline__ void draw_slot(const SearchArgs& A, const DiagOut& D,
       if (id >= 0)
         tgt = neuron ? id
                      : restart_search<DIAG, DEFER>(A, R, vs, id, 1, W.defer.depth, i, j, li,
-                                                   xi, yi, zi, &lev, c, &deferred);
+                                                   xi, yi, zi, &lev, c, &deferred, keep);
     }
     if (DEFER) {
       const int64_t e = off + j;
