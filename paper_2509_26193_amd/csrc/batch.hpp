@@ -19,6 +19,10 @@
 
 namespace msp {
 
+// LDS bytes per thread of the kernels that run restart levels: a level's kept weights
+// and ids (see restart_search).
+constexpr size_t kRestartLds = kRestartKeep * (sizeof(double) + sizeof(uint32_t));
+
 struct SimDesc {
   const NodeRec* rec[2];
   const int32_t* vs[2];
@@ -208,8 +212,13 @@ __global__ void __launch_bounds__(256) search_phase2_k(BatchDev B, SweepOut W, i
     if (D.opens) c.opens = D.opens[e];
   }
   int32_t none = -1;
+  extern __shared__ double keep_lds[];      // kRestartLds bytes per thread (see search_draw_k)
+  const KeptEntries keep{keep_lds + threadIdx.x,
+                         reinterpret_cast<uint32_t*>(keep_lds + kRestartKeep * blockDim.x) +
+                             threadIdx.x,
+                         (int)blockDim.x};
   const int32_t tgt = restart_search<DIAG, false>(A, R, A.vs[t], W.defer.cell[e], lev, kNoDefer,
-                                                  i, j, li, xi, yi, zi, &lev, c, &none);
+                                                  i, j, li, xi, yi, zi, &lev, c, &none, &keep);
   A.target[e] = tgt;
   if (DIAG) {
     if (D.levels) D.levels[e] = lev;
@@ -578,9 +587,6 @@ inline hipError_t enqueue_prep(SearchScratch& S, int64_t total_n, hipStream_t s,
   b_work_sorted_k<<<g, 256, 0, s>>>(B, total_n, S.hval[0]);
   return hipGetLastError();
 }
-
-// LDS bytes per draw thread: a restart level's kept weights and ids.
-constexpr size_t kRestartLds = kRestartKeep * (sizeof(double) + sizeof(uint32_t));
 
 // The sweep and draw launches. `sweep_blocks` persistent blocks; the draw covers
 // every possible slot (threads past the tile count return at once).

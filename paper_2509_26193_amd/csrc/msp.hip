@@ -586,9 +586,11 @@ msp_status msp_find_targets_diag(msp_octree t, const uint8_t* neuron_type,
                              p + 2 * ks + 5 * vs + align_up(sizeof(uint8_t) * total_S));
     if (le == hipSuccess) {
       if (any)
-        search_phase2_k<true><<<grid_for(total_S, 256), 256, 0, s>>>(S.B, S.W, total_S);
+        search_phase2_k<true><<<grid_for(total_S, 256), 256, kRestartLds * 256, s>>>(S.B, S.W,
+                                                                                   total_S);
       else
-        search_phase2_k<false><<<grid_for(total_S, 256), 256, 0, s>>>(S.B, S.W, total_S);
+        search_phase2_k<false><<<grid_for(total_S, 256), 256, kRestartLds * 256, s>>>(S.B, S.W,
+                                                                                    total_S);
       if (diag && diag->phase2_requests)
         phase2_count_k<<<1, 1, 0, s>>>(S.W, total_S, diag->phase2_requests);
       le = hipGetLastError();
