@@ -47,6 +47,11 @@ for name, res, args in [
                                                vp, vp, vp, ctypes.c_int64, ctypes.c_int64,
                                                vp, vp]),
     ("msp_activity_init", ctypes.c_int32, [ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+    ("msp_cycle_create", ctypes.c_int32, [vp, vp, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_uint64, vp, ctypes.c_int64, ctypes.c_int64,
+                                          vp, ctypes.c_int32, vp]),
+    ("msp_cycle_run", ctypes.c_int32, [vp, ctypes.c_int32, vp]),
+    ("msp_cycle_free", None, [vp]),
 ]:
     f = getattr(L, name)
     f.restype = res
@@ -76,6 +81,9 @@ for h in handles:
     assert L.msp_batch_status(h, None, None) == INVALID
     L.msp_batch_free(h)
     L.msp_batch_free(h)
+    assert L.msp_cycle_run(h, 1, None) == INVALID
+    L.msp_cycle_free(h)
+    L.msp_cycle_free(h)
 
 # argument checks before any device call
 bm = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
@@ -107,4 +115,17 @@ assert L.msp_plasticity_record(0, p8, p8, p8, 1, p8, p8, p8, 0, 10, p8, None) ==
 assert L.msp_plasticity_record(10, p8, p8, p8, 20, p8, p8, p8, 0, 10, p8, None) == -4
 assert L.msp_activity_init(0, p8, p8, p8, p8, p8, p8, p8, p8, None) == INVALID
 assert L.msp_activity_init(10, p8, None, p8, p8, p8, p8, p8, p8, None) == INVALID
+# the update cycle: a state with every pointer set, then each check in turn
+state = (ctypes.c_void_p * 13)(*([8] * 13))
+params = (ctypes.c_double * 6)(0.001, 0.7, 0.4, 0.7, 0.1, 0.1)
+P = ctypes.create_string_buffer(bytes(params) + (100).to_bytes(4, "little") + bytes(4))
+tree = ctypes.addressof(foreign)
+assert L.msp_cycle_create(tree, p8, 750.0, 0.3, 1, P, 100, 100, state, 0,
+                          ctypes.byref(out)) == INVALID          # not a live octree
+assert L.msp_cycle_create(None, p8, 750.0, 0.3, 1, P, 100, 100, state, 0,
+                          ctypes.byref(out)) == INVALID
+assert L.msp_cycle_create(tree, p8, 750.0, 0.3, 1, P, 100, 100, None, 0,
+                          ctypes.byref(out)) == INVALID
+assert L.msp_cycle_create(tree, p8, 750.0, 0.3, 1, P, 100, 100, state, 0, None) == INVALID
+assert out.value is None
 print("abi checks under sanitizers: ok", flush=True)
