@@ -689,8 +689,9 @@ def main():
         import paper_2509_26193_amd as msp
         if args.only == "clusters":
             from synth_inputs import config_clusters
-            r = bench_plain_update(msp, torch, config_clusters(theta=0.3), steps=args.steps,
-                                   warmup=args.warmup)
+            r = {f"theta{th}": bench_plain_update(msp, torch, config_clusters(theta=th),
+                                                  steps=args.steps, warmup=args.warmup)
+                 for th in (0.2, 0.3, 0.5)}
         elif args.only == "batched":
             r = bench_batched(msp, torch)
         elif args.only == "attraction":
@@ -865,6 +866,12 @@ def main():
         log(f"also: {wc.name}")
         also["plain_1M_clusters"] = bench_plain_update(msp, torch, wc, steps=5, warmup=1)
         del wc
+        for th in (0.2, 0.5):             # the other thetas of the clustered workload
+            wc = config_clusters(theta=th)
+            log(f"also: {wc.name}")
+            also[f"plain_1M_clusters_theta{th}"] = bench_plain_update(msp, torch, wc, steps=3,
+                                                                      warmup=1)
+            del wc
         log("also: two-phase search")
         also["two_phase_8M"] = bench_two_phase(msp, torch, w, B, ops)
         log("also: electrical activity")
