@@ -31,8 +31,8 @@ REC_BYTES = 16             # one per-type node record {x, y, z, count} at 4 byte
 OPEN_BYTES = 8             # child link + mask + depth of an opened node
 SRC_BYTES = 16             # source record
 OUT_BYTES = 4              # one int32 target
-# vector operations the method needs per source and level-0 record (the survey's
-# per-visit figure): a record with vacancy 8 (3 differences and 3 multiply-adds for
+# vector operations the method needs per source and level-0 record (the per-visit
+# operation model): a record with vacancy 8 (3 differences and 3 multiply-adds for
 # d^2, the theta^2 d^2 product and its compare), an accepted entry 3 more (exp2, the
 # product with v, the running sum), a record without vacancy 1 (the zero test)
 OPS_VISIT, OPS_ENTRY, OPS_EMPTY = 8, 3, 1
@@ -148,7 +148,7 @@ def hbm_roofline(bytes_, seconds, what):
 
 def alu_roofline(ops, logical_bytes, seconds, what):
     """The search rows' bound: vector operations the method needs over the kernels'
-    time against the vector-op peak; the survey's logical traversal bytes beside it
+    time against the vector-op peak; the logical traversal bytes beside it
     (every lane charged separately, so above 1 where lanes share record loads)."""
     return dict(bound="alu", unit="Tops/s", achieved=ops / seconds / 1e12,
                 peak=VALU_OPS_PEAK / 1e12, frac=ops / seconds / VALU_OPS_PEAK, ops=int(ops),
@@ -814,7 +814,7 @@ def main():
                     valu_per_wave_step=issue["SQ_INSTS_VALU"] / wave_steps,
                     salu_per_wave_step=issue["SQ_INSTS_SALU"] / wave_steps),
                 # HBM views: the bytes the shared walk needs (one 32-byte record per wave
-                # step, the sources' data and outputs), and the survey's logical bytes
+                # step, the sources' data and outputs), and the logical per-visit bytes
                 # (16 B per lane visit, 8 B per open, 16 B per source: every lane charged
                 # separately, so it exceeds 1 when the 64 lanes share a record load)
                 hbm_shared_walk=dict(bytes=walk_bytes, achieved=walk_bytes / sweep_s / 1e9,
