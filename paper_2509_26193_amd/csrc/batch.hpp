@@ -41,7 +41,7 @@ struct SimDesc {
   int32_t* target;              // [capacity] output
   int64_t capacity;
   int64_t n;
-  double L2, theta2, k2;
+  double L2, theta2, acc_d2, k2;  // acc_d2: accept_bound(L2, theta2)
   uint64_t seed, step;
   DiagOut diag;                 // nullable outputs of counting launches
 };
@@ -98,6 +98,7 @@ __device__ __forceinline__ SearchArgs args_of(const SimDesc* sims, int s, const 
   A.err = d->err;
   A.L2 = d->L2;
   A.theta2 = d->theta2;
+  A.acc_d2 = d->acc_d2;
   A.k2 = d->k2;
   A.seed = d->seed;
   A.step = d->step;

@@ -72,8 +72,10 @@ __global__ void negative_k(const int32_t* __restrict__ a, int64_t n, int32_t* er
 
 // Whether the walks must test for the source's own cell: always, unless theta <= 1/2
 // and every position of the tree lies inside its cube (then that test never fires).
+// The walks without the test also decide acceptance by a bound on d2 (accept_bound),
+// which asks for L^2 < kAcceptL2Max as well.
 bool own_cell_needed(const msp_octree_s* t, double theta) {
-  return !(t->inside && theta * theta <= 0.25);
+  return !(t->inside && theta * theta <= 0.25 && t->box_edge * t->box_edge < kAcceptL2Max);
 }
 
 // Fill the device descriptor of one simulation.
@@ -102,6 +104,7 @@ SimDesc make_desc(const msp_octree_s* t, const uint8_t* neuron_type, const int32
   d.n = t->n;
   d.L2 = t->box_edge * t->box_edge;
   d.theta2 = theta * theta;
+  d.acc_d2 = accept_bound(d.L2, d.theta2);
   d.k2 = kLog2e / (sigma_um * sigma_um);
   d.seed = seed;
   d.step = step;
@@ -835,8 +838,9 @@ __global__ void desc_theta_step_k(SimDesc* d, int n, double theta2, uint64_t ste
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   d[k].theta2 = theta2;
+  d[k].acc_d2 = accept_bound(d[k].L2, theta2);
   d[k].step = step;
-  d[k].own = (d[k].inside && theta2 <= 0.25) ? 0 : 1;
+  d[k].own = (d[k].inside && theta2 <= 0.25 && d[k].L2 < kAcceptL2Max) ? 0 : 1;
 }
 
 bool sim_ok(const msp_sim& m) {

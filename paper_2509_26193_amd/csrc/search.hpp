@@ -12,6 +12,7 @@
 // weight mantissas in float32, weights and running sums in float64.
 #pragma once
 
+#include <float.h>
 #include <math.h>
 
 #include "common.hpp"
@@ -40,6 +41,7 @@ struct SearchArgs {
   int32_t* err;
   double L2;                     // box_edge * box_edge
   double theta2;                 // theta * theta
+  double acc_d2;                 // accept_bound(L2, theta2) (walks without the own-cell test)
   double k2;                     // log2(e) / (sigma * sigma)
   uint64_t seed, step;
 };
@@ -75,6 +77,34 @@ __device__ __forceinline__ double edge2_at(double L2, uint32_t meta) {
 
 __device__ __forceinline__ bool bh_accept_u(double L2, double theta2, double d2, uint32_t meta) {
   return edge2_at(L2, meta) < theta2 * d2;
+}
+
+// The same test as a bound on d2 alone, where theta <= 1/2, every position lies in the
+// cube and L^2 < kAcceptL2Max. D = accept_bound(L^2, theta^2) is the largest double with
+// fl(theta^2 D) <= L^2; the rounded product is non-decreasing in d2, so the root test
+// passes iff d2 > D. At depth dep it passes iff d2 > D 4^-dep: around the bound the
+// product is a normal double (at least L^2 4^-21), where scaling by 4^-dep commutes with
+// its rounding, and D 4^-21 is normal (D >= 4 L^2). With theta = 0, D = DBL_MAX, and
+// DBL_MAX 4^-21 lies far above any d2 between points of a cube with L^2 < 2^900, so
+// nothing is accepted, as theta^2 d2 = 0 says. The bound takes the product's place in
+// the per-node step, with the same decisions.
+constexpr double kAcceptL2Max = 0x1p900;
+
+__host__ __device__ inline double accept_bound(double L2, double theta2) {
+  if (!(theta2 > 0.0)) return DBL_MAX;
+  double d = L2 / theta2;                // within an ulp or two of the bound
+  if (d > DBL_MAX) d = DBL_MAX;
+  while (d > 0.0 && theta2 * d > L2) d = nextafter(d, 0.0);
+  for (;;) {
+    const double up = nextafter(d, DBL_MAX);
+    if (up == d || !(theta2 * up <= L2)) break;
+    d = up;
+  }
+  return d;
+}
+
+__device__ __forceinline__ bool bh_accept_d(double acc_d2, double d2, uint32_t meta) {
+  return edge2_at(acc_d2, meta) < d2;
 }
 
 // v * 2^-y with y = d2 * k2 (= v exp(-d2 / sigma^2)), or exactly 0 where `keep` is

@@ -186,7 +186,8 @@ __device__ __forceinline__ int32_t mask_at(const SearchArgs& A, cptr<NodeRec> R,
       if (r.v != 0) {
         const double d2 = dist2(xi, yi, zi, r.x, r.y, r.z);
         const bool contains = OWN && (uint32_t)(li - y) < (uint32_t)(sk - y);
-        out = !contains && bh_accept_u(A.L2, A.theta2, d2, r.meta);
+        out = !contains && (OWN ? bh_accept_u(A.L2, A.theta2, d2, r.meta)
+                                : bh_accept_d(A.acc_d2, d2, r.meta));
       }
       if (me <= y && out) me = sk;
       y = y + 1;
@@ -335,7 +336,8 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
         } else {                                               // inner node
           const int32_t sk = (int32_t)(meta & kSkipMask);     // > x
           const double d2 = dist2(xi, yi, zi, cur.x, cur.y, cur.z);
-          uint64_t m_far = __builtin_amdgcn_ballot_w64(bh_accept_u(A.L2, A.theta2, d2, meta));
+          uint64_t m_far = __builtin_amdgcn_ballot_w64(
+              OWN ? bh_accept_u(A.L2, A.theta2, d2, meta) : bh_accept_d(A.acc_d2, d2, meta));
           // li in [x, sk) (padding lanes have li = -1, far above sk - x unsigned)
           if (OWN) m_far &= ~__builtin_amdgcn_ballot_w64((uint32_t)(li - x) < (uint32_t)(sk - x));
           const uint64_t m_take = m_act & m_far;
