@@ -29,7 +29,7 @@ __global__ void __launch_bounds__(kCommitBlock) req_key_k(
     const int32_t* __restrict__ target, const int64_t* __restrict__ off,
     const int32_t* __restrict__ src_of, const uint8_t* __restrict__ type, DevCount S, int64_t n,
     uint64_t seed, DevStep step, int64_t* __restrict__ key, uint64_t* __restrict__ prio,
-    int32_t* __restrict__ cnt, int32_t* err) {
+    int32_t* __restrict__ cnt, int32_t* __restrict__ within, int32_t* err) {
   const int64_t S_ = S.get();
   const uint64_t st = step.get();
   for (int64_t s = gtid(); s < S_; s += gstride()) {
@@ -43,19 +43,22 @@ __global__ void __launch_bounds__(kCommitBlock) req_key_k(
     const int64_t k = 2 * (int64_t)g + (type[i] ? 1 : 0);
     key[s] = k;
     prio[s] = philox_word0(seed, 1, (uint64_t)i, (uint64_t)(s - off[i]), st, 0);
-    atomicAdd(&cnt[k], 1);
+    within[s] = atomicAdd(&cnt[k], 1);      // the request's place in its group
   }
 }
 
+// Each request at its group's offset plus its place in the group (the order within a
+// group is the counting atomics' order; the ranks below do not depend on it).
 __global__ void __launch_bounds__(kCommitBlock) req_scatter_k(const int64_t* __restrict__ key,
-                                                             DevCount S, int32_t* __restrict__ cursor,
+                                                             DevCount S,
+                                                             const int32_t* __restrict__ seg_off,
+                                                             const int32_t* __restrict__ within,
                                                              int32_t* __restrict__ seg) {
   const int64_t S_ = S.get();
   for (int64_t s = gtid(); s < S_; s += gstride()) {
     const int64_t k = key[s];
     if (k < 0) continue;
-    const int32_t p = atomicAdd(&cursor[k], 1);
-    seg[p] = (int32_t)s;
+    seg[seg_off[k] + within[s]] = (int32_t)s;
   }
 }
 

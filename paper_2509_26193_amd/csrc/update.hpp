@@ -20,7 +20,8 @@ struct CommitWs {
   int32_t* src_of;
   int64_t* key;
   uint64_t* prio;
-  int32_t* cnt;                 // [2n] requests per group, then the scatter cursors
+  int32_t* cnt;                 // [2n] requests per group
+  int32_t* within;              // [cap_S] each request's place in its group
   int32_t* seg_off;             // [2n + 1]
   int32_t* seg;
   uint8_t* acc;
@@ -36,6 +37,7 @@ inline CommitWs commit_ws(void* base, int64_t n, int64_t cap_S, size_t* bytes) {
   w.key = c.take<int64_t>(cap_S);
   w.prio = c.take<uint64_t>(cap_S);
   w.cnt = c.take<int32_t>(2 * n);
+  w.within = c.take<int32_t>(cap_S);
   w.seg_off = c.take<int32_t>(2 * n + 1);
   w.seg = c.take<int32_t>(cap_S);
   w.acc = c.take<uint8_t>(cap_S);
@@ -63,15 +65,13 @@ inline hipError_t enqueue_commit(const CommitWs& w, const int32_t* target,
   fill_i32_k<<<1, 64, 0, s>>>(w.flags, 1, 0);
   src_of_k<<<grid_for(n, kCommitBlock), kCommitBlock, 0, s>>>(elem_offset, n, S, w.src_of);
   req_key_k<<<gs, kCommitBlock, 0, s>>>(target, elem_offset, w.src_of, neuron_type, S, n, seed,
-                                        step, w.key, w.prio, w.cnt, w.flags);
+                                        step, w.key, w.prio, w.cnt, w.within, w.flags);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = exclusive_scan<int32_t, int32_t, Ident<int32_t>>(w.cnt, w.seg_off, 2 * n, Ident<int32_t>(),
                                                        true, s, w.scan_ws);
   if (e != hipSuccess) return e;
-  // scatter cursors: a copy of the group offsets
-  copy_i32_k<<<grid_for(2 * n, 256), 256, 0, s>>>(w.seg_off, w.cnt, 2 * n);
-  req_scatter_k<<<gs, kCommitBlock, 0, s>>>(w.key, S, w.cnt, w.seg);
+  req_scatter_k<<<gs, kCommitBlock, 0, s>>>(w.key, S, w.seg_off, w.within, w.seg);
   req_rank_k<<<gs, kCommitBlock, 0, s>>>(w.key, w.prio, w.seg_off, w.seg, S, vac_exc, vac_inh,
                                          w.acc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
