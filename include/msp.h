@@ -309,8 +309,10 @@ msp_status msp_attraction_bwd(msp_octree t, const uint8_t* neuron_type, const in
  * MSP_ERR_INVALID if a target is >= n (then no vacancy count is modified, no synapse is
  * written and *n_formed = 0); MSP_ERR_INVALID if S = elem_offset[n] is negative or
  * not below 2^31 - 1 (requests are indexed with int32). Waits on `s` (to size its
- * working memory by S and to report the status). After a commit the octree is stale
- * until the next msp_update_vacant_counts.
+ * working memory by S and to report the status). The working memory (about 40 B per
+ * request and 24 B per neuron) is the one the library keeps per device for searches
+ * (see msp_find_targets): commits and searches on one device take turns with it.
+ * After a commit the octree is stale until the next msp_update_vacant_counts.
  */
 msp_status msp_commit_synapses(const int32_t* target, const int64_t* elem_offset,
                                const uint8_t* neuron_type, int64_t n, int32_t* vac_axon,
@@ -337,9 +339,9 @@ void msp_free_octree(msp_octree t);
  * a handle that is not live. */
 msp_status msp_free_octree_async(msp_octree t, hipStream_t s);
 
-/* Free the search working memory the library keeps on `device` (see msp_find_targets),
- * after the last search that used it has finished (waits for it). The next search
- * on that device allocates it again. MSP_ERR_INVALID for a device that does not
+/* Free the working memory the library keeps on `device` for searches, commits and
+ * plasticity steps (see msp_find_targets), after the last call that used it has
+ * finished (waits for it). The next such call on that device allocates it again. MSP_ERR_INVALID for a device that does not
  * exist. */
 msp_status msp_release_workspace(int32_t device);
 
@@ -428,7 +430,9 @@ msp_status msp_plasticity_record(int64_t n, const int32_t* new_src, const int32_
  *   4. the list is compacted in order; *m_out (host) = its new length;
  *   5. vac_axon, vac_exc, vac_inh [n] int32 = floor(z) - bound of each kind.
  * Errors: MSP_ERR_INVALID for n < 1, m < 0 or m >= 2^31, a null pointer or parameters
- * that are not finite (or growth_onset >= target_calcium). Waits on `s`.
+ * that are not finite (or growth_onset >= target_calcium). Waits on `s`. Its working
+ * memory (about 60 B per synapse) is the one the library keeps per device for
+ * searches (see msp_find_targets).
  */
 msp_status msp_plasticity_step(int64_t n, const msp_plasticity_params* params, uint64_t seed,
                                uint64_t step, double* z, int32_t* bound, int32_t* syn_src,

@@ -162,11 +162,13 @@ hipError_t ck_slots_for(int device, int64_t total_n, int nsims, int force, int* 
   return hipSuccess;
 }
 
-// The search's working memory (worklist and checkpoints: gigabytes for millions of
-// neurons) is kept per device between calls and grown when a larger search needs more:
-// mapping it anew on every call would cost more than the search. Calls on one device
-// take turns (a mutex held for the whole call); a call's stream waits for the kernels
-// of the previous user before they are overwritten.
+// The working memory of the search (worklist and checkpoints: gigabytes for millions
+// of neurons), the commit and the plasticity step is kept per device between calls and
+// grown when a larger call needs more: mapping it anew on every call would cost more
+// than the search, and returning hundreds of megabytes to the stream-ordered pool after
+// every commit made the next pool free on the host take about a millisecond. Calls on
+// one device take turns (a mutex held for the whole call); a call's stream waits for
+// the kernels of the previous user before they are overwritten.
 struct Workspace {
   std::mutex m;
   void* p = nullptr;
@@ -710,12 +712,15 @@ msp_status msp_commit_synapses_ex(const int32_t* target, const int64_t* elem_off
   }
   if (!target) return MSP_ERR_INVALID;
   if (syn_capacity > 0 && (!syn_src || !syn_tgt || !syn_type)) return MSP_ERR_INVALID;
-  // every temporary of the commit in one pool block (one allocation, one free)
+  // every temporary of the commit in the device's kept working memory
   size_t bytes = 0;
   (void)commit_ws(nullptr, n, S, &bytes);
-  Temp tmp(s);
-  MSP_HIP_TRY(tmp.alloc(bytes));
-  const CommitWs w = commit_ws(tmp.p, n, S, &bytes);
+  int dev = -1;
+  MSP_HIP_TRY(hipGetDevice(&dev));
+  WorkspaceLease lease(dev);
+  void* wsp = nullptr;
+  MSP_HIP_TRY(lease.acquire(bytes, s, &wsp));
+  const CommitWs w = commit_ws(wsp, n, S, &bytes);
   MSP_HIP_TRY(enqueue_commit(w, target, elem_offset, neuron_type, n, host_count(S), vac_axon,
                              vac_exc, vac_inh, seed, host_step(step), syn_src, syn_tgt, syn_type,
                              syn_capacity, n_formed, accepted_out, s));
@@ -1247,12 +1252,15 @@ msp_status msp_plasticity_step(int64_t n, const msp_plasticity_params* params, u
   if (!plast_params_ok(p)) return MSP_ERR_INVALID;
   const PlastConst c = plast_const(p);
   int64_t* m_dev = nullptr;
-  Temp tmp(s);
   size_t bytes = 0;
   (void)plast_ws(nullptr, n, m, &bytes);
-  MSP_HIP_TRY(tmp.alloc(bytes + align_up(sizeof(int64_t))));
-  const PlastWs w = plast_ws(tmp.p, n, m, &bytes);
-  m_dev = reinterpret_cast<int64_t*>(static_cast<char*>(tmp.p) + bytes);
+  int dev = -1;
+  MSP_HIP_TRY(hipGetDevice(&dev));
+  WorkspaceLease lease(dev);                  // the device's kept working memory
+  void* wsp = nullptr;
+  MSP_HIP_TRY(lease.acquire(bytes + align_up(sizeof(int64_t)), s, &wsp));
+  const PlastWs w = plast_ws(wsp, n, m, &bytes);
+  m_dev = reinterpret_cast<int64_t*>(static_cast<char*>(wsp) + bytes);
   MSP_HIP_TRY(enqueue_plasticity(w, n, c, seed, host_step(step), z, bound,
                                  SynList{syn_src, syn_tgt, syn_type}, host_count(m), m_dev,
                                  vac_axon, vac_exc, vac_inh, s));
