@@ -242,14 +242,24 @@ __global__ void __launch_bounds__(kSortBlock) rs_scatter_k(const uint64_t* kin, 
       __syncthreads();
     }
     lstart[t] -= count;
+    // the tile's items in registers first: one memory round trip per tile, not per round
+    uint64_t keys[kSortItems];
+    int32_t vals[kSortItems];
+#pragma unroll
+    for (int c = 0; c < kSortItems; ++c) {
+      const int li = c * kSortBlock + t;
+      keys[c] = li < tile_n ? kin[base + li] : 0ull;
+      vals[c] = li < tile_n ? vin[base + li] : 0;
+    }
     __syncthreads();
+#pragma unroll
     for (int c = 0; c < kSortItems; ++c) {
 #pragma unroll
       for (int k = 0; k < kSortBlock / kWave; ++k) wcnt[k][t] = 0;
       __syncthreads();
       const int li = c * kSortBlock + t;
       const bool valid = li < tile_n;
-      const uint64_t key = valid ? kin[base + li] : 0ull;
+      const uint64_t key = keys[c];
       const uint32_t d = (uint32_t)(key >> shift) & 255u;
       uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -266,7 +276,7 @@ __global__ void __launch_bounds__(kSortBlock) rs_scatter_k(const uint64_t* kin, 
         for (int k = 0; k < w; ++k) p += wcnt[k][d];
         if (p < (uint32_t)kSortTile) {
           lk[p] = key;
-          lv[p] = vin[base + li];
+          lv[p] = vals[c];
         }
       }
       __syncthreads();
