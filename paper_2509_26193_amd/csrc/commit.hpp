@@ -11,6 +11,8 @@ namespace msp {
 
 constexpr int kCommitBlock = 256;
 constexpr int32_t kCommitCapacity = 1;      // more accepted requests than list capacity
+constexpr int32_t kSmallGroup = 64;         // groups up to this size are ranked by one thread
+constexpr uint8_t kAccPending = 2;          // a member of a larger group, ranked per request
 
 // Source of every request slot below S.
 __global__ void __launch_bounds__(kCommitBlock) src_of_k(const int64_t* __restrict__ off, int64_t n,
@@ -48,17 +50,62 @@ __global__ void __launch_bounds__(kCommitBlock) req_key_k(
 }
 
 // Each request at its group's offset plus its place in the group (the order within a
-// group is the counting atomics' order; the ranks below do not depend on it).
+// group is the counting atomics' order; the ranks below do not depend on it). A request
+// without a group (target out of range) is declined here.
 __global__ void __launch_bounds__(kCommitBlock) req_scatter_k(const int64_t* __restrict__ key,
                                                              DevCount S,
                                                              const int32_t* __restrict__ seg_off,
                                                              const int32_t* __restrict__ within,
-                                                             int32_t* __restrict__ seg) {
+                                                             int32_t* __restrict__ seg,
+                                                             uint8_t* __restrict__ acc) {
   const int64_t S_ = S.get();
   for (int64_t s = gtid(); s < S_; s += gstride()) {
     const int64_t k = key[s];
-    if (k < 0) continue;
+    if (k < 0) {
+      acc[s] = 0;
+      continue;
+    }
     seg[seg_off[k] + within[s]] = (int32_t)s;
+  }
+}
+
+// One thread per group k (target k / 2, type k % 2; its requests seg[lo, hi)): the
+// group's accepted count min(requests, vacancies) into acc_cnt[k], and each member's
+// decision: all accepted where the vacancies suffice, none where there are none, else
+// ranked by (priority, slot) against the other members (groups of up to kSmallGroup
+// requests; the members of larger ones are marked kAccPending for req_rank_k). The
+// group arrays are read in order here, not gathered per request.
+__global__ void __launch_bounds__(kCommitBlock) group_rank_k(
+    const uint64_t* __restrict__ prio, const int32_t* __restrict__ seg_off,
+    const int32_t* __restrict__ seg, int64_t n2, const int32_t* __restrict__ vexc,
+    const int32_t* __restrict__ vinh, uint8_t* __restrict__ acc, int32_t* __restrict__ acc_cnt) {
+  for (int64_t k = gtid(); k < n2; k += gstride()) {
+    const int32_t lo = seg_off[k], hi = seg_off[k + 1];
+    const int32_t c = hi - lo;
+    if (c == 0) {
+      acc_cnt[k] = 0;
+      continue;
+    }
+    const int32_t g = (int32_t)(k >> 1);
+    int32_t v = (k & 1) ? vinh[g] : vexc[g];
+    v = v < 0 ? 0 : v;
+    acc_cnt[k] = c < v ? c : v;
+    if (c <= v || v == 0 || c > kSmallGroup) {
+      const uint8_t a = c <= v ? 1 : v == 0 ? 0 : kAccPending;
+      for (int32_t q = lo; q < hi; ++q) acc[seg[q]] = a;
+      continue;
+    }
+    for (int32_t q = lo; q < hi; ++q) {
+      const int32_t s = seg[q];
+      const uint64_t ps = prio[s];
+      int32_t rank = 0;
+      for (int32_t r = lo; r < hi && rank < v; ++r) {
+        const int32_t o = seg[r];
+        const uint64_t po = prio[o];
+        rank += (po < ps || (po == ps && o < s)) ? 1 : 0;
+      }
+      acc[s] = rank < v ? 1 : 0;
+    }
   }
 }
 
@@ -87,24 +134,30 @@ __device__ __forceinline__ uint8_t rank_accept(const int64_t* __restrict__ key,
   return rank < v ? 1 : 0;
 }
 
+// The members of groups larger than kSmallGroup, one thread per request.
 __global__ void __launch_bounds__(kCommitBlock) req_rank_k(
     const int64_t* __restrict__ key, const uint64_t* __restrict__ prio,
     const int32_t* __restrict__ seg_off, const int32_t* __restrict__ seg, DevCount S,
     const int32_t* __restrict__ vexc, const int32_t* __restrict__ vinh, uint8_t* __restrict__ acc) {
   const int64_t S_ = S.get();
   for (int64_t s = gtid(); s < S_; s += gstride())
-    acc[s] = rank_accept(key, prio, seg_off, seg, vexc, vinh, s);
+    if (acc[s] == kAccPending) acc[s] = rank_accept(key, prio, seg_off, seg, vexc, vinh, s);
 }
 
 // Writes the accepted requests' synapses at their places in the output list, unless
 // the list (capacity `cap`) cannot hold them all or a target was out of range
 // (kErrArgs in *flags): then it writes nothing (and sets kCommitCapacity for the
-// former).
+// former). The vacancies are taken by dec_groups_k and dec_sources_k under the same
+// condition.
+__device__ __forceinline__ bool commit_ok(const int64_t* __restrict__ dst, int64_t S_, int64_t cap,
+                                          const int32_t* flags) {
+  return S_ > 0 && !(*flags & kErrArgs) && dst[S_] <= cap;
+}
+
 __global__ void __launch_bounds__(kCommitBlock) commit_write_k(
     const uint8_t* __restrict__ acc, const int64_t* __restrict__ dst, const int64_t* __restrict__ key,
-    const int32_t* __restrict__ src_of, DevCount S, int64_t cap, int32_t* vac_axon, int32_t* vexc,
-    int32_t* vinh, int32_t* syn_src, int32_t* syn_tgt, uint8_t* syn_type, uint8_t* acc_out,
-    int32_t* flags) {
+    const int32_t* __restrict__ src_of, DevCount S, int64_t cap, int32_t* syn_src, int32_t* syn_tgt,
+    uint8_t* syn_type, uint8_t* acc_out, int32_t* flags) {
   const int64_t S_ = S.get();
   if (S_ == 0 || (*flags & kErrArgs)) return;
   if (dst[S_] > cap) {
@@ -118,13 +171,37 @@ __global__ void __launch_bounds__(kCommitBlock) commit_write_k(
     const int64_t k = key[s];
     const int32_t g = (int32_t)(k >> 1);
     const int ty = (int)(k & 1);
-    const int32_t i = src_of[s];
     const int64_t p = dst[s];
-    syn_src[p] = i;
+    syn_src[p] = src_of[s];
     syn_tgt[p] = g;
     syn_type[p] = (uint8_t)ty;
-    atomicSub(&vac_axon[i], 1);
-    atomicSub(ty ? &vinh[g] : &vexc[g], 1);
+  }
+}
+
+// Each group's accepted count off its target's vacancies of that type (the two types
+// of a target are different arrays, so no two threads write one count).
+__global__ void __launch_bounds__(kCommitBlock) dec_groups_k(
+    const int32_t* __restrict__ acc_cnt, int64_t n2, const int64_t* __restrict__ dst, DevCount S,
+    int64_t cap, const int32_t* flags, int32_t* __restrict__ vexc, int32_t* __restrict__ vinh) {
+  if (!commit_ok(dst, S.get(), cap, flags)) return;
+  for (int64_t k = gtid(); k < n2; k += gstride()) {
+    const int32_t a = acc_cnt[k];
+    if (a) ((k & 1) ? vinh : vexc)[k >> 1] -= a;
+  }
+}
+
+// Each source's accepted requests off its vacant axonal elements.
+__global__ void __launch_bounds__(kCommitBlock) dec_sources_k(
+    const int64_t* __restrict__ off, int64_t n, const uint8_t* __restrict__ acc,
+    const int64_t* __restrict__ dst, DevCount S, int64_t cap, const int32_t* flags,
+    int32_t* __restrict__ vac_axon) {
+  const int64_t S_ = S.get();
+  if (!commit_ok(dst, S_, cap, flags)) return;
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    const int64_t e = off[i + 1] < S_ ? off[i + 1] : S_;
+    int32_t a = 0;
+    for (int64_t s = off[i]; s < e; ++s) a += acc[s];
+    if (a) vac_axon[i] -= a;
   }
 }
 

@@ -20,7 +20,7 @@ struct CommitWs {
   int32_t* src_of;
   int64_t* key;
   uint64_t* prio;
-  int32_t* cnt;                 // [2n] requests per group
+  int32_t* cnt;                 // [2n] requests per group, then the accepted ones
   int32_t* within;              // [cap_S] each request's place in its group
   int32_t* seg_off;             // [2n + 1]
   int32_t* seg;
@@ -71,7 +71,12 @@ inline hipError_t enqueue_commit(const CommitWs& w, const int32_t* target,
   e = exclusive_scan<int32_t, int32_t, Ident<int32_t>>(w.cnt, w.seg_off, 2 * n, Ident<int32_t>(),
                                                        true, s, w.scan_ws);
   if (e != hipSuccess) return e;
-  req_scatter_k<<<gs, kCommitBlock, 0, s>>>(w.key, S, w.seg_off, w.within, w.seg);
+  req_scatter_k<<<gs, kCommitBlock, 0, s>>>(w.key, S, w.seg_off, w.within, w.seg, w.acc);
+  // decisions per group (w.cnt now takes each group's accepted count), then the members
+  // of large groups per request
+  const unsigned gg = grid_cap(2 * n, kCommitBlock);
+  group_rank_k<<<gg, kCommitBlock, 0, s>>>(w.prio, w.seg_off, w.seg, 2 * n, vac_exc, vac_inh,
+                                           w.acc, w.cnt);
   req_rank_k<<<gs, kCommitBlock, 0, s>>>(w.key, w.prio, w.seg_off, w.seg, S, vac_exc, vac_inh,
                                          w.acc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -79,8 +84,11 @@ inline hipError_t enqueue_commit(const CommitWs& w, const int32_t* target,
                                                 S.p);
   if (e != hipSuccess) return e;
   commit_write_k<<<gs, kCommitBlock, 0, s>>>(w.acc, w.dst, w.key, w.src_of, S, syn_capacity,
-                                             vac_axon, vac_exc, vac_inh, syn_src, syn_tgt,
-                                             syn_type, accepted_out, w.flags);
+                                             syn_src, syn_tgt, syn_type, accepted_out, w.flags);
+  dec_groups_k<<<gg, kCommitBlock, 0, s>>>(w.cnt, 2 * n, w.dst, S, syn_capacity, w.flags,
+                                           vac_exc, vac_inh);
+  dec_sources_k<<<grid_cap(n, kCommitBlock), kCommitBlock, 0, s>>>(
+      elem_offset, n, w.acc, w.dst, S, syn_capacity, w.flags, vac_axon);
   formed_k<<<1, 64, 0, s>>>(w.dst, S, syn_capacity, w.flags, n_formed);
   return hipGetLastError();
 }
