@@ -11,8 +11,17 @@ namespace msp {
 
 constexpr int kCommitBlock = 256;
 constexpr int32_t kCommitCapacity = 1;      // more accepted requests than list capacity
-constexpr int32_t kSmallGroup = 64;         // groups up to this size are ranked by one thread
-constexpr uint8_t kAccPending = 2;          // a member of a larger group, ranked per request
+constexpr int32_t kSmallGroup = 8;          // groups up to this size are ranked by one thread
+
+// A group's decision for its members: all accepted, none, those up to a (priority,
+// slot) threshold (the v-th smallest), or, for groups above kSmallGroup requests,
+// ranked per request.
+enum : int32_t { kGroupAll = 0, kGroupNone = 1, kGroupThr = 2, kGroupRank = 3 };
+struct GroupThr {
+  uint64_t prio;
+  int32_t slot;
+  int32_t mode;
+};
 
 // Source of every request slot below S.
 __global__ void __launch_bounds__(kCommitBlock) src_of_k(const int64_t* __restrict__ off, int64_t n,
@@ -50,35 +59,29 @@ __global__ void __launch_bounds__(kCommitBlock) req_key_k(
 }
 
 // Each request at its group's offset plus its place in the group (the order within a
-// group is the counting atomics' order; the ranks below do not depend on it). A request
-// without a group (target out of range) is declined here.
+// group is the counting atomics' order; the decisions below do not depend on it).
 __global__ void __launch_bounds__(kCommitBlock) req_scatter_k(const int64_t* __restrict__ key,
                                                              DevCount S,
                                                              const int32_t* __restrict__ seg_off,
                                                              const int32_t* __restrict__ within,
-                                                             int32_t* __restrict__ seg,
-                                                             uint8_t* __restrict__ acc) {
+                                                             int32_t* __restrict__ seg) {
   const int64_t S_ = S.get();
   for (int64_t s = gtid(); s < S_; s += gstride()) {
     const int64_t k = key[s];
-    if (k < 0) {
-      acc[s] = 0;
-      continue;
-    }
+    if (k < 0) continue;
     seg[seg_off[k] + within[s]] = (int32_t)s;
   }
 }
 
-// One thread per group k (target k / 2, type k % 2; its requests seg[lo, hi)): the
-// group's accepted count min(requests, vacancies) into acc_cnt[k], and each member's
-// decision: all accepted where the vacancies suffice, none where there are none, else
-// ranked by (priority, slot) against the other members (groups of up to kSmallGroup
-// requests; the members of larger ones are marked kAccPending for req_rank_k). The
-// group arrays are read in order here, not gathered per request.
-__global__ void __launch_bounds__(kCommitBlock) group_rank_k(
+// One thread per group k (target k / 2, type k % 2; its requests seg[lo, hi)), the
+// group's offsets and vacancies read in order: its accepted count min(requests,
+// vacancies) into acc_cnt[k] and its decision into thr[k]. Where some but not all are
+// accepted (and the group has at most kSmallGroup requests), the threshold is the
+// (priority, slot) of the member that exactly v - 1 others precede.
+__global__ void __launch_bounds__(kCommitBlock) group_thr_k(
     const uint64_t* __restrict__ prio, const int32_t* __restrict__ seg_off,
     const int32_t* __restrict__ seg, int64_t n2, const int32_t* __restrict__ vexc,
-    const int32_t* __restrict__ vinh, uint8_t* __restrict__ acc, int32_t* __restrict__ acc_cnt) {
+    const int32_t* __restrict__ vinh, GroupThr* __restrict__ thr, int32_t* __restrict__ acc_cnt) {
   for (int64_t k = gtid(); k < n2; k += gstride()) {
     const int32_t lo = seg_off[k], hi = seg_off[k + 1];
     const int32_t c = hi - lo;
@@ -90,22 +93,26 @@ __global__ void __launch_bounds__(kCommitBlock) group_rank_k(
     int32_t v = (k & 1) ? vinh[g] : vexc[g];
     v = v < 0 ? 0 : v;
     acc_cnt[k] = c < v ? c : v;
-    if (c <= v || v == 0 || c > kSmallGroup) {
-      const uint8_t a = c <= v ? 1 : v == 0 ? 0 : kAccPending;
-      for (int32_t q = lo; q < hi; ++q) acc[seg[q]] = a;
-      continue;
-    }
-    for (int32_t q = lo; q < hi; ++q) {
-      const int32_t s = seg[q];
-      const uint64_t ps = prio[s];
-      int32_t rank = 0;
-      for (int32_t r = lo; r < hi && rank < v; ++r) {
-        const int32_t o = seg[r];
-        const uint64_t po = prio[o];
-        rank += (po < ps || (po == ps && o < s)) ? 1 : 0;
+    GroupThr t{0, 0, c <= v ? kGroupAll : v == 0 ? kGroupNone : kGroupRank};
+    if (t.mode == kGroupRank && c <= kSmallGroup) {
+      // the members' slots and priorities in registers first (independent loads), then
+      // every member ranked against the others
+      int32_t ms[kSmallGroup];
+      uint64_t mp[kSmallGroup];
+#pragma unroll
+      for (int r = 0; r < kSmallGroup; ++r) ms[r] = r < c ? seg[lo + r] : 0;
+#pragma unroll
+      for (int r = 0; r < kSmallGroup; ++r) mp[r] = r < c ? prio[ms[r]] : 0;
+#pragma unroll
+      for (int q = 0; q < kSmallGroup; ++q) {
+        int32_t rank = 0;
+#pragma unroll
+        for (int r = 0; r < kSmallGroup; ++r)
+          rank += (r < c && (mp[r] < mp[q] || (mp[r] == mp[q] && ms[r] < ms[q]))) ? 1 : 0;
+        if (q < c && rank == v - 1) t = GroupThr{mp[q], ms[q], kGroupThr};
       }
-      acc[s] = rank < v ? 1 : 0;
     }
+    thr[k] = t;
   }
 }
 
@@ -134,14 +141,30 @@ __device__ __forceinline__ uint8_t rank_accept(const int64_t* __restrict__ key,
   return rank < v ? 1 : 0;
 }
 
-// The members of groups larger than kSmallGroup, one thread per request.
-__global__ void __launch_bounds__(kCommitBlock) req_rank_k(
+// Each request's decision from its group's (one gather per request; the members of
+// groups above kSmallGroup requests are ranked here, one thread per request).
+__global__ void __launch_bounds__(kCommitBlock) req_decide_k(
     const int64_t* __restrict__ key, const uint64_t* __restrict__ prio,
-    const int32_t* __restrict__ seg_off, const int32_t* __restrict__ seg, DevCount S,
-    const int32_t* __restrict__ vexc, const int32_t* __restrict__ vinh, uint8_t* __restrict__ acc) {
+    const GroupThr* __restrict__ thr, const int32_t* __restrict__ seg_off,
+    const int32_t* __restrict__ seg, DevCount S, const int32_t* __restrict__ vexc,
+    const int32_t* __restrict__ vinh, uint8_t* __restrict__ acc) {
   const int64_t S_ = S.get();
-  for (int64_t s = gtid(); s < S_; s += gstride())
-    if (acc[s] == kAccPending) acc[s] = rank_accept(key, prio, seg_off, seg, vexc, vinh, s);
+  for (int64_t s = gtid(); s < S_; s += gstride()) {
+    const int64_t k = key[s];
+    uint8_t a = 0;
+    if (k >= 0) {
+      const GroupThr t = thr[k];
+      if (t.mode == kGroupAll) {
+        a = 1;
+      } else if (t.mode == kGroupThr) {
+        const uint64_t ps = prio[s];
+        a = (ps < t.prio || (ps == t.prio && s <= t.slot)) ? 1 : 0;
+      } else if (t.mode == kGroupRank) {
+        a = rank_accept(key, prio, seg_off, seg, vexc, vinh, s);
+      }
+    }
+    acc[s] = a;
+  }
 }
 
 // Writes the accepted requests' synapses at their places in the output list, unless

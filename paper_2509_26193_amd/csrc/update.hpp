@@ -22,6 +22,7 @@ struct CommitWs {
   uint64_t* prio;
   int32_t* cnt;                 // [2n] requests per group, then the accepted ones
   int32_t* within;              // [cap_S] each request's place in its group
+  GroupThr* thr;                // [2n] each group's decision
   int32_t* seg_off;             // [2n + 1]
   int32_t* seg;
   uint8_t* acc;
@@ -38,6 +39,7 @@ inline CommitWs commit_ws(void* base, int64_t n, int64_t cap_S, size_t* bytes) {
   w.prio = c.take<uint64_t>(cap_S);
   w.cnt = c.take<int32_t>(2 * n);
   w.within = c.take<int32_t>(cap_S);
+  w.thr = c.take<GroupThr>(2 * n);
   w.seg_off = c.take<int32_t>(2 * n + 1);
   w.seg = c.take<int32_t>(cap_S);
   w.acc = c.take<uint8_t>(cap_S);
@@ -71,14 +73,13 @@ inline hipError_t enqueue_commit(const CommitWs& w, const int32_t* target,
   e = exclusive_scan<int32_t, int32_t, Ident<int32_t>>(w.cnt, w.seg_off, 2 * n, Ident<int32_t>(),
                                                        true, s, w.scan_ws);
   if (e != hipSuccess) return e;
-  req_scatter_k<<<gs, kCommitBlock, 0, s>>>(w.key, S, w.seg_off, w.within, w.seg, w.acc);
-  // decisions per group (w.cnt now takes each group's accepted count), then the members
-  // of large groups per request
+  req_scatter_k<<<gs, kCommitBlock, 0, s>>>(w.key, S, w.seg_off, w.within, w.seg);
+  // decisions per group (w.cnt now takes each group's accepted count), then per request
   const unsigned gg = grid_cap(2 * n, kCommitBlock);
-  group_rank_k<<<gg, kCommitBlock, 0, s>>>(w.prio, w.seg_off, w.seg, 2 * n, vac_exc, vac_inh,
-                                           w.acc, w.cnt);
-  req_rank_k<<<gs, kCommitBlock, 0, s>>>(w.key, w.prio, w.seg_off, w.seg, S, vac_exc, vac_inh,
-                                         w.acc);
+  group_thr_k<<<gg, kCommitBlock, 0, s>>>(w.prio, w.seg_off, w.seg, 2 * n, vac_exc, vac_inh,
+                                          w.thr, w.cnt);
+  req_decide_k<<<gs, kCommitBlock, 0, s>>>(w.key, w.prio, w.thr, w.seg_off, w.seg, S, vac_exc,
+                                           vac_inh, w.acc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   e = exclusive_scan<int64_t, uint8_t, AccFlag>(w.acc, w.dst, S.v, AccFlag(), true, s, w.scan_ws,
                                                 S.p);
