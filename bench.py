@@ -231,6 +231,7 @@ def cpu_baseline(w, gpu_target, sample, threads):
                 one_thread=dict(value=q1.size / t1, unit="searches/s",
                                 sample=f"the first {q1.size} of those searches, 1 thread"),
                 parity=dict(targets="the last timed step's", sampled=m, differing=differ,
+                            differing_share=differ / max(m, 1), share_bound=1e-4,
                             outside_window=outside, oracle_window_hits=window_hits))
 
 
