@@ -258,110 +258,107 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
     int imask = __builtin_amdgcn_readfirstlane(step0 - 1);   // interval - 1 (power of 2)
     NodeRec cur = load_rec_u(R, (uint32_t)x);
     while (x < end) {
-      int chunk = 0x7FFFFFFF;                 // without checkpoints: one chunk to the end
       if constexpr (SLOTS > 0) {
         // checkpoints at multiples of the interval; a full buffer keeps every other
         // one and doubles the interval
-        if (nck == ns) {
-#pragma unroll 1
-          for (int k = 1; k < ns / 2; ++k) {
-            ckP[k * kWave] = ckP[2 * k * kWave];
-            ckme[k * kWave] = ckme[2 * k * kWave];
-            if (lane == 0) ckx[k] = ckx[2 * k];
-          }
-          nck = ns / 2;
-          imask = __builtin_amdgcn_readfirstlane(2 * imask + 1);
-        }
         if ((steps & imask) == 0) {
-          ckP[nck * kWave] = sum.Z;
-          ckme[nck * kWave] = me;
-          if (lane == 0) ckx[nck] = x;
-          nck = __builtin_amdgcn_readfirstlane(nck + 1);
-        }
-        chunk = (imask + 1) - (steps & imask);   // steps to the next multiple
-      }
-      int left = chunk;
-      do {
-        // one node: uniform branches on its kind, per-lane decisions as lane masks, the
-        // weight evaluated on every lane and added where the lane takes the entry. The
-        // next record's load is issued as soon as the next node is known (a leaf's at
-        // once, an inner node's after the ballot), so it is in flight while this node's
-        // weights are computed.
-        // Lane decisions are lane masks: a ballot of each compare (its mask itself),
-        // combined on the scalar unit, and turned back into a lane condition where a
-        // select needs one (inverse ballot: the same mask).
-        const uint32_t meta = cur.meta;
-        const uint64_t m_act = __builtin_amdgcn_ballot_w64(x >= me);
-        const bool active = __builtin_amdgcn_inverse_ballot_w64(m_act);
-        if (DIAG && active) c0.visits += 1;
-        int32_t next;
-        NodeRec nxt;
-        if ((int32_t)meta < 0) {                               // leaf
-          next = x + 1;                                        // index N: the sentinel
-          if (cur.v == 0) {
-            nxt = load_rec_u(R, (uint32_t)next);
-          } else if (!(meta & kBucketBit)) {
-            const int32_t id = (int32_t)(meta & kIdMask);
-            const bool keep = active && id != i;
-            if (DIAG && keep) c0.entries += 1;
-            const double d2 = dist2(xi, yi, zi, cur.x, cur.y, cur.z);
-            const double vd = (double)cur.v;
-            // the record is no longer needed: its registers take the next one; the
-            // weight is computed while the load is in flight (no instruction of it may
-            // be scheduled above the load)
-            nxt = load_rec_u(R, (uint32_t)next);
-            __builtin_amdgcn_sched_barrier(0);
-            sum.Z = sum.Z + kernel_weight_vd(keep, vd, d2, A.k2);
-          } else {                              // several neurons at one finest cell
-            nxt = load_rec_u(R, (uint32_t)next);
-            const cptr<int32_t> vs = as_const(A.vs[t]);
-            const cptr<int32_t> order = as_const(A.order);
-            const cptr<double> pos = as_const(A.pos);
-            const int32_t pe = as_const(A.nend)[x];
-            for (int32_t p = as_const(A.nbeg)[x]; p < pe; ++p) {
-              const int32_t id = order[p];
-              const int32_t v = vs[p];
-              if (v == 0) continue;
-              if (DIAG && active && id != i) c0.entries += 1;
-              sum.Z = sum.Z + kernel_weight_if(
-                  active && id != i, v,
-                  dist2(xi, yi, zi, pos[3 * (int64_t)id], pos[3 * (int64_t)id + 1],
-                        pos[3 * (int64_t)id + 2]),
-                  A.k2);
+          if (nck == ns) {
+#pragma unroll 1
+            for (int k = 1; k < ns / 2; ++k) {
+              ckP[k * kWave] = ckP[2 * k * kWave];
+              ckme[k * kWave] = ckme[2 * k * kWave];
+              if (lane == 0) ckx[k] = ckx[2 * k];
             }
+            nck = ns / 2;
+            imask = __builtin_amdgcn_readfirstlane(2 * imask + 1);
           }
-        } else if (cur.v == 0) {                // no vacancy below: over the subtree
-          next = (int32_t)(meta & kSkipMask);
+          if ((steps & imask) == 0) {
+            ckP[nck * kWave] = sum.Z;
+            ckme[nck * kWave] = me;
+            if (lane == 0) ckx[nck] = x;
+            nck = __builtin_amdgcn_readfirstlane(nck + 1);
+          }
+        }
+      }
+      // one node: uniform branches on its kind, per-lane decisions as lane masks, the
+      // weight evaluated on every lane and added where the lane takes the entry. The
+      // next record's load is issued as soon as the next node is known (a leaf's at
+      // once, an inner node's after the ballot), so it is in flight while this node's
+      // weights are computed.
+      // Lane decisions are lane masks: a ballot of each compare (its mask itself),
+      // combined on the scalar unit, and turned back into a lane condition where a
+      // select needs one (inverse ballot: the same mask).
+      const uint32_t meta = cur.meta;
+      const uint64_t m_act = __builtin_amdgcn_ballot_w64(x >= me);
+      const bool active = __builtin_amdgcn_inverse_ballot_w64(m_act);
+      if (DIAG && active) c0.visits += 1;
+      int32_t next;
+      NodeRec nxt;
+      if ((int32_t)meta < 0) {                               // leaf
+        next = x + 1;                                        // index N: the sentinel
+        if (cur.v == 0) {
           nxt = load_rec_u(R, (uint32_t)next);
-        } else {                                               // inner node
-          const int32_t sk = (int32_t)(meta & kSkipMask);     // > x
+        } else if (!(meta & kBucketBit)) {
+          const int32_t id = (int32_t)(meta & kIdMask);
+          const bool keep = active && id != i;
+          if (DIAG && keep) c0.entries += 1;
           const double d2 = dist2(xi, yi, zi, cur.x, cur.y, cur.z);
-          uint64_t m_far = __builtin_amdgcn_ballot_w64(
-              OWN ? bh_accept_u(A.L2, A.theta2, d2, meta) : bh_accept_d(A.acc_d2, d2, meta));
-          // li in [x, sk) (padding lanes have li = -1, far above sk - x unsigned)
-          if (OWN) m_far &= ~__builtin_amdgcn_ballot_w64((uint32_t)(li - x) < (uint32_t)(sk - x));
-          const uint64_t m_take = m_act & m_far;
-          const uint64_t m_open = m_act & ~m_far;
           const double vd = (double)cur.v;
-          // the wave descends iff a lane opens x; the record is no longer needed: its
-          // registers take the next one
-          next = m_open ? x + 1 : sk;
+          // the record is no longer needed: its registers take the next one; the
+          // weight is computed while the load is in flight (no instruction of it may
+          // be scheduled above the load)
           nxt = load_rec_u(R, (uint32_t)next);
           __builtin_amdgcn_sched_barrier(0);
-          const bool take = __builtin_amdgcn_inverse_ballot_w64(m_take);
-          sum.Z = sum.Z + kernel_weight_vd(take, vd, d2, A.k2);
-          me = take ? sk : me;
-          if (DIAG && __builtin_amdgcn_inverse_ballot_w64(m_open)) c0.opens += 1;
-          if (DIAG && take) c0.entries += 1;
+          sum.Z = sum.Z + kernel_weight_vd(keep, vd, d2, A.k2);
+        } else {                              // several neurons at one finest cell
+          nxt = load_rec_u(R, (uint32_t)next);
+          const cptr<int32_t> vs = as_const(A.vs[t]);
+          const cptr<int32_t> order = as_const(A.order);
+          const cptr<double> pos = as_const(A.pos);
+          const int32_t pe = as_const(A.nend)[x];
+          for (int32_t p = as_const(A.nbeg)[x]; p < pe; ++p) {
+            const int32_t id = order[p];
+            const int32_t v = vs[p];
+            if (v == 0) continue;
+            if (DIAG && active && id != i) c0.entries += 1;
+            sum.Z = sum.Z + kernel_weight_if(
+                active && id != i, v,
+                dist2(xi, yi, zi, pos[3 * (int64_t)id], pos[3 * (int64_t)id + 1],
+                      pos[3 * (int64_t)id + 2]),
+                A.k2);
+          }
         }
-        x = next;
-        cur = nxt;
-        if (x >= end) {
-          --left;
-          break;
-        }
-      } while (--left > 0);
-      steps += chunk - left;
+      } else if (cur.v == 0) {                // no vacancy below: over the subtree
+        next = (int32_t)(meta & kSkipMask);
+        nxt = load_rec_u(R, (uint32_t)next);
+      } else {                                               // inner node
+        const int32_t sk = (int32_t)(meta & kSkipMask);     // > x
+        const double d2 = dist2(xi, yi, zi, cur.x, cur.y, cur.z);
+        uint64_t m_far = __builtin_amdgcn_ballot_w64(
+            OWN ? bh_accept_u(A.L2, A.theta2, d2, meta) : bh_accept_d(A.acc_d2, d2, meta));
+        // li in [x, sk) (padding lanes have li = -1, far above sk - x unsigned)
+        if (OWN) m_far &= ~__builtin_amdgcn_ballot_w64((uint32_t)(li - x) < (uint32_t)(sk - x));
+        const uint64_t m_take = m_act & m_far;
+        const double vd = (double)cur.v;
+        // the wave descends iff a lane opens x; the record is no longer needed: its
+        // registers take the next one. (The and-not sets the scalar condition code to
+        // "some lane opens", which the select uses directly.)
+        uint64_t m_open;
+        asm("s_andn2_b64 %0, %2, %3\n\ts_cselect_b32 %1, %4, %5"
+            : "=&s"(m_open), "=s"(next)
+            : "s"(m_act), "s"(m_far), "s"(x + 1), "s"(sk)
+            : "scc");
+        nxt = load_rec_u(R, (uint32_t)next);
+        __builtin_amdgcn_sched_barrier(0);
+        const bool take = __builtin_amdgcn_inverse_ballot_w64(m_take);
+        sum.Z = sum.Z + kernel_weight_vd(take, vd, d2, A.k2);
+        me = take ? sk : me;
+        if (DIAG && __builtin_amdgcn_inverse_ballot_w64(m_open)) c0.opens += 1;
+        if (DIAG && take) c0.entries += 1;
+      }
+      x = next;
+      cur = nxt;
+      ++steps;
     }
   }
   const int64_t us = unit * kWave + lane;
