@@ -20,11 +20,15 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # kind and count in the search walks) stay plain scalar branches instead of being
 # rewritten into structured flow with flag registers and copies of the loop-carried
 # vector values on every path; the walk loops issue about 15 % fewer instructions.
+# -enable-tail-merge=false: the search sweep's inner-node step (the common kind) ends
+# by falling into the loop's tail instead of branching to a block it shares with the
+# leaf step.
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-ffp-contract=off", "-fno-fast-math",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-mllvm", "-structurizecfg-skip-uniform-regions",
+    "-mllvm", "-enable-tail-merge=false",
     "-Wall", "-Wno-unused-function",
 ]
 

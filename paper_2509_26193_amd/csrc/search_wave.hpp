@@ -294,7 +294,7 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
       if (DIAG && active) c0.visits += 1;
       int32_t next;
       NodeRec nxt;
-      if ((int32_t)meta < 0) {                               // leaf
+      if (__builtin_expect((int32_t)meta < 0, 0)) {          // leaf
         next = x + 1;                                        // index N: the sentinel
         if (cur.v == 0) {
           nxt = load_rec_u(R, (uint32_t)next);
@@ -328,7 +328,7 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
                 A.k2);
           }
         }
-      } else if (cur.v == 0) {                // no vacancy below: over the subtree
+      } else if (__builtin_expect(cur.v == 0, 0)) {   // no vacancy below: over the subtree
         next = (int32_t)(meta & kSkipMask);
         nxt = load_rec_u(R, (uint32_t)next);
       } else {                                               // inner node
@@ -339,6 +339,8 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
         // li in [x, sk) (padding lanes have li = -1, far above sk - x unsigned)
         if (OWN) m_far &= ~__builtin_amdgcn_ballot_w64((uint32_t)(li - x) < (uint32_t)(sk - x));
         const uint64_t m_take = m_act & m_far;
+        const bool take = __builtin_amdgcn_inverse_ballot_w64(m_take);
+        const int32_t me_next = take ? sk : me;   // (sk is then free for the next node)
         const double vd = (double)cur.v;
         // the wave descends iff a lane opens x; the record is no longer needed: its
         // registers take the next one. (The and-not sets the scalar condition code to
@@ -350,9 +352,8 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
             : "scc");
         nxt = load_rec_u(R, (uint32_t)next);
         __builtin_amdgcn_sched_barrier(0);
-        const bool take = __builtin_amdgcn_inverse_ballot_w64(m_take);
         sum.Z = sum.Z + kernel_weight_vd(take, vd, d2, A.k2);
-        me = take ? sk : me;
+        me = me_next;
         if (DIAG && __builtin_amdgcn_inverse_ballot_w64(m_open)) c0.opens += 1;
         if (DIAG && take) c0.entries += 1;
       }
