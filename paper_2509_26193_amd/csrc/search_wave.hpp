@@ -100,6 +100,19 @@ __device__ __forceinline__ NodeRec load_rec_u(cptr<NodeRec> R, uint32_t x) {
   return r;
 }
 
+// Record at byte offset `off` (a multiple of the record size).
+__device__ __forceinline__ NodeRec load_rec_b(cptr<NodeRec> R, uint32_t off) {
+  const u32x8 w =
+      *(cptr<u32x8>)((const __attribute__((address_space(4))) char*)R + off);
+  NodeRec r;
+  r.x = __builtin_bit_cast(double, ((uint64_t)w[1] << 32) | w[0]);
+  r.y = __builtin_bit_cast(double, ((uint64_t)w[3] << 32) | w[2]);
+  r.z = __builtin_bit_cast(double, ((uint64_t)w[5] << 32) | w[4]);
+  r.v = (int32_t)w[6];
+  r.meta = w[7];
+  return r;
+}
+
 __device__ __forceinline__ NodeRec load_rec(cptr<NodeRec> R, int64_t x) {
   NodeRec r;
   r.x = R[x].x;
@@ -256,8 +269,17 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
       c0.opens = 1;
     }
     int imask = __builtin_amdgcn_readfirstlane(step0 - 1);   // interval - 1 (power of 2)
-    NodeRec cur = load_rec_u(R, (uint32_t)x);
-    while (x < end) {
+    // the walk counts positions in bytes of the record array (position x at 32 x):
+    // the next record's address is then the position itself
+    constexpr int kRecShift = 5;
+    static_assert(sizeof(NodeRec) == (1 << kRecShift), "32-byte records");
+    // (unsigned: up to kMaxNodes positions, the sentinel's offset is 2^31)
+    uint32_t xb = (uint32_t)x << kRecShift;
+    const uint32_t endb = (uint32_t)end << kRecShift;
+    uint32_t meb = valid ? (uint32_t)me << kRecShift : ~0u;  // padding lanes: never active
+    const uint32_t lib = (uint32_t)li << kRecShift;
+    NodeRec cur = load_rec_b(R, xb);
+    while (xb < endb) {
       if constexpr (SLOTS > 0) {
         // checkpoints at multiples of the interval; a full buffer keeps every other
         // one and doubles the interval
@@ -274,8 +296,8 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
           }
           if ((steps & imask) == 0) {
             ckP[nck * kWave] = sum.Z;
-            ckme[nck * kWave] = me;
-            if (lane == 0) ckx[nck] = x;
+            ckme[nck * kWave] = (int32_t)(meb >> kRecShift);
+            if (lane == 0) ckx[nck] = (int32_t)(xb >> kRecShift);
             nck = __builtin_amdgcn_readfirstlane(nck + 1);
           }
         }
@@ -289,15 +311,15 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
       // combined on the scalar unit, and turned back into a lane condition where a
       // select needs one (inverse ballot: the same mask).
       const uint32_t meta = cur.meta;
-      const uint64_t m_act = __builtin_amdgcn_ballot_w64(x >= me);
+      const uint64_t m_act = __builtin_amdgcn_ballot_w64(xb >= meb);
       const bool active = __builtin_amdgcn_inverse_ballot_w64(m_act);
       if (DIAG && active) c0.visits += 1;
-      int32_t next;
+      uint32_t next;                                         // bytes
       NodeRec nxt;
       if (__builtin_expect((int32_t)meta < 0, 0)) {          // leaf
-        next = x + 1;                                        // index N: the sentinel
+        next = xb + (1 << kRecShift);                        // index N: the sentinel
         if (cur.v == 0) {
-          nxt = load_rec_u(R, (uint32_t)next);
+          nxt = load_rec_b(R, next);
         } else if (!(meta & kBucketBit)) {
           const int32_t id = (int32_t)(meta & kIdMask);
           const bool keep = active && id != i;
@@ -307,11 +329,12 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
           // the record is no longer needed: its registers take the next one; the
           // weight is computed while the load is in flight (no instruction of it may
           // be scheduled above the load)
-          nxt = load_rec_u(R, (uint32_t)next);
+          nxt = load_rec_b(R, next);
           __builtin_amdgcn_sched_barrier(0);
           sum.Z = sum.Z + kernel_weight_vd(keep, vd, d2, A.k2);
         } else {                              // several neurons at one finest cell
-          nxt = load_rec_u(R, (uint32_t)next);
+          nxt = load_rec_b(R, next);
+          const int32_t x = (int32_t)(xb >> kRecShift);
           const cptr<int32_t> vs = as_const(A.vs[t]);
           const cptr<int32_t> order = as_const(A.order);
           const cptr<double> pos = as_const(A.pos);
@@ -329,18 +352,18 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
           }
         }
       } else if (__builtin_expect(cur.v == 0, 0)) {   // no vacancy below: over the subtree
-        next = (int32_t)(meta & kSkipMask);
-        nxt = load_rec_u(R, (uint32_t)next);
+        next = (meta & kSkipMask) << kRecShift;
+        nxt = load_rec_b(R, next);
       } else {                                               // inner node
-        const int32_t sk = (int32_t)(meta & kSkipMask);     // > x
+        const uint32_t sk = (meta & kSkipMask) << kRecShift;   // > xb
         const double d2 = dist2(xi, yi, zi, cur.x, cur.y, cur.z);
         uint64_t m_far = __builtin_amdgcn_ballot_w64(
             OWN ? bh_accept_u(A.L2, A.theta2, d2, meta) : bh_accept_d(A.acc_d2, d2, meta));
-        // li in [x, sk) (padding lanes have li = -1, far above sk - x unsigned)
-        if (OWN) m_far &= ~__builtin_amdgcn_ballot_w64((uint32_t)(li - x) < (uint32_t)(sk - x));
+        // li in [x, sk), as offsets (padding lanes have li = -1: far above, unsigned)
+        if (OWN) m_far &= ~__builtin_amdgcn_ballot_w64(lib - xb < sk - xb);
         const uint64_t m_take = m_act & m_far;
         const bool take = __builtin_amdgcn_inverse_ballot_w64(m_take);
-        const int32_t me_next = take ? sk : me;   // (sk is then free for the next node)
+        const uint32_t me_next = take ? sk : meb; // (sk is then free for the next node)
         const double vd = (double)cur.v;
         // the wave descends iff a lane opens x; the record is no longer needed: its
         // registers take the next one. (The and-not sets the scalar condition code to
@@ -348,16 +371,16 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
         uint64_t m_open;
         asm("s_andn2_b64 %0, %2, %3\n\ts_cselect_b32 %1, %4, %5"
             : "=&s"(m_open), "=s"(next)
-            : "s"(m_act), "s"(m_far), "s"(x + 1), "s"(sk)
+            : "s"(m_act), "s"(m_far), "s"(xb + (1 << kRecShift)), "s"(sk)
             : "scc");
-        nxt = load_rec_u(R, (uint32_t)next);
+        nxt = load_rec_b(R, next);
         __builtin_amdgcn_sched_barrier(0);
         sum.Z = sum.Z + kernel_weight_vd(take, vd, d2, A.k2);
-        me = me_next;
+        meb = me_next;
         if (DIAG && __builtin_amdgcn_inverse_ballot_w64(m_open)) c0.opens += 1;
         if (DIAG && take) c0.entries += 1;
       }
-      x = next;
+      xb = next;
       cur = nxt;
       ++steps;
     }
