@@ -268,7 +268,13 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
       c0.visits = 1;
       c0.opens = 1;
     }
-    int imask = __builtin_amdgcn_readfirstlane(step0 - 1);   // interval - 1 (power of 2)
+    // Steps are counted in `ph`: the step index modulo the checkpoint interval (a power
+    // of two, 2^32 / inc), kept in the top bits, so that it is 0 exactly at the
+    // multiples of the interval and the step needs no separate test; s1 is the next
+    // multiple to be reached (the current one while ph is 0).
+    uint32_t inc = 1u << (32 - __builtin_ctz((uint32_t)__builtin_amdgcn_readfirstlane(step0)));
+    uint32_t ph = 0;
+    int s1 = 0;
     // the walk counts positions in bytes of the record array (position x at 32 x):
     // the next record's address is then the position itself
     constexpr int kRecShift = 5;
@@ -283,7 +289,8 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
       if constexpr (SLOTS > 0) {
         // checkpoints at multiples of the interval; a full buffer keeps every other
         // one and doubles the interval
-        if ((steps & imask) == 0) {
+        if (ph == 0) {                    // step index s1
+          bool store = true;
           if (nck == ns) {
 #pragma unroll 1
             for (int k = 1; k < ns / 2; ++k) {
@@ -292,13 +299,20 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
               if (lane == 0) ckx[k] = ckx[2 * k];
             }
             nck = ns / 2;
-            imask = __builtin_amdgcn_readfirstlane(2 * imask + 1);
+            inc >>= 1;
+            const int half = (int)(1u << (31 - __builtin_ctz(inc)));   // the old interval
+            if (s1 & half) {                // half way between multiples of the new one
+              ph = 0x80000000u;
+              s1 += half;
+              store = false;
+            }
           }
-          if ((steps & imask) == 0) {
+          if (store) {
             ckP[nck * kWave] = sum.Z;
             ckme[nck * kWave] = (int32_t)(meb >> kRecShift);
             if (lane == 0) ckx[nck] = (int32_t)(xb >> kRecShift);
             nck = __builtin_amdgcn_readfirstlane(nck + 1);
+            s1 += (int)(1u << (32 - __builtin_ctz(inc)));   // the interval
           }
         }
       }
@@ -382,8 +396,13 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
       }
       xb = next;
       cur = nxt;
-      ++steps;
+      if (SLOTS > 0) {
+        ph += inc;
+      } else if (DIAG) {
+        ++steps;
+      }
     }
+    if (SLOTS > 0) steps = s1 - (int)((0u - ph) >> __builtin_ctz(inc));
   }
   const int64_t us = unit * kWave + lane;
   if (lane == 0) W.nck[unit] = nck;
