@@ -40,8 +40,10 @@ void carve_neurons(msp_octree_s* t, char* base, size_t* bytes) {
 void carve_nodes(msp_octree_s* t, char* base, size_t* bytes) {
   Carver c{base};
   const int64_t N = t->N;
-  t->rec[0] = c.take<NodeRec>(N + 1);        // + a sentinel record at index N
-  t->rec[1] = c.take<NodeRec>(N + 1);
+  // + a sentinel record at index N, then room for the search sweep's requests ahead of
+  // its position (never written, never read into registers)
+  t->rec[0] = c.take<NodeRec>(N + 1 + kAheadRecords);
+  t->rec[1] = c.take<NodeRec>(N + 1 + kAheadRecords);
   t->skip = c.take<int32_t>(N);
   t->nbeg = c.take<int32_t>(N);
   t->nend = c.take<int32_t>(N);

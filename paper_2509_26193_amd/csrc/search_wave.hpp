@@ -35,6 +35,11 @@ constexpr int kPartUnits = 131072; // parts are added while a simulation's units
                                    // within this (16 per wave of a full launch)
 constexpr int kWaveBlock = 256;    // 4 independent waves per block
 constexpr int kXcd = 8;            // accelerator dies; workgroup b runs on die b % 8
+constexpr uint32_t kAheadBytes = 256;   // the sweep requests the records this far ahead
+                                        // of its position into the L2
+constexpr int64_t kAheadRecords = kAheadBytes / sizeof(NodeRec);   // room kept after the
+                                        // sentinel record for those requests
+constexpr int kRawBufferWord3 = 0x00020000;   // buffer descriptor word 3: raw dwords
 
 // Requests of the second phase of a two-phase search (one simulation): one entry per
 // element e; key[e] is the deferred cell's pre-order index >> shift, or `none` if the
@@ -285,6 +290,19 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
     uint32_t meb = valid ? (uint32_t)me << kRecShift : ~0u;  // padding lanes: never active
     const uint32_t lib = (uint32_t)li << kRecShift;
     NodeRec cur = load_rec_b(R, xb);
+    // Most wave steps go to a record a little ahead of the current one (the next one,
+    // or the end of a small subtree), and a record that misses the L2 costs the step a
+    // trip to the Infinity Cache or HBM. Every step therefore also requests the line
+    // kAheadBytes past the new position into the L2: a buffer load whose data goes to
+    // local memory (one scratch word per lane, never read), so that it holds no register
+    // and nothing ever waits for it. The record array keeps kAheadRecords of room after
+    // the sentinel (the position is at most the sentinel's), and the buffer covers them.
+    __shared__ uint32_t ahead_sink[kWaveBlock];
+    const __amdgpu_buffer_rsrc_t ahead_buf = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)R, (short)0, (int)((uint32_t)(root_end + 1 + kAheadRecords) << kRecShift),
+        kRawBufferWord3);
+    auto* ahead_lds = (__attribute__((address_space(3))) void*)(
+        ahead_sink + __builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~(kWave - 1))));
     while (xb < endb) {
       if constexpr (SLOTS > 0) {
         // checkpoints at multiples of the interval; a full buffer keeps every other
@@ -396,6 +414,8 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
       }
       xb = next;
       cur = nxt;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ahead_buf, ahead_lds, 4, 0,
+                                               (int)(xb + kAheadBytes), 0, 0);
       if (SLOTS > 0) {
         ph += inc;
       } else if (DIAG) {
