@@ -414,8 +414,8 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
       }
       xb = next;
       cur = nxt;
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(ahead_buf, ahead_lds, 4, 0,
-                                               (int)(xb + kAheadBytes), 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ahead_buf, ahead_lds, 4, 0, (int)xb,
+                                               (int)kAheadBytes, 0);
       if (SLOTS > 0) {
         ph += inc;
       } else if (DIAG) {
