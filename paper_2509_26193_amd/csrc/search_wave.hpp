@@ -297,7 +297,10 @@ __device__ __forceinline__ int sweep_tile(const SearchArgs& A, const SweepOut& W
     // local memory (one scratch word per lane, never read), so that it holds no register
     // and nothing ever waits for it. The record array keeps kAheadRecords of room after
     // the sentinel (the position is at most the sentinel's), and the buffer covers them.
-    __shared__ uint32_t ahead_sink[kWaveBlock];
+    // The distance is the instruction's immediate offset, which the hardware may also add
+    // to the local-memory address: the sink keeps that much room after the last wave's
+    // words, so every write stays inside the block's own local memory either way.
+    __shared__ uint32_t ahead_sink[kWaveBlock + kAheadBytes / sizeof(uint32_t)];
     const __amdgpu_buffer_rsrc_t ahead_buf = __builtin_amdgcn_make_buffer_rsrc(
         (void*)R, (short)0, (int)((uint32_t)(root_end + 1 + kAheadRecords) << kRecShift),
         kRawBufferWord3);
