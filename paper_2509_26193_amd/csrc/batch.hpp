@@ -109,8 +109,13 @@ __device__ __forceinline__ SearchArgs args_of(const SimDesc* sims, int s, const 
 // the Morton range of their own die (neighbouring sources share upper-tree nodes in
 // that die's L2), then from the other dies' ranges. A unit's simulation is found from
 // the unit bases.
+// Scalar registers: on this chip a wave that needs more than 80 (the count the compiler
+// reports, with VCC) leaves room for only 7 waves per SIMD, although the compiler and the
+// occupancy query both count 8 (measured: 78 give 8 resident waves per SIMD, 82 give 7).
+// The sweep hides record latency with resident waves, so it is held to 80; what does not
+// fit is kept in vector-register lanes on the rare paths (bucket leaves, thinning).
 template <bool DIAG, int SLOTS, bool OWN>
-__global__ void __launch_bounds__(kWaveBlock) __attribute__((amdgpu_num_sgpr(94)))
+__global__ void __launch_bounds__(kWaveBlock) __attribute__((amdgpu_num_sgpr(80)))
 search_sweep_k(BatchDev B, SweepOut W) {
   const int lane = threadIdx.x & (kWave - 1);
   const int home = blockIdx.x % kXcd;
